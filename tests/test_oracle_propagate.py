@@ -1,0 +1,83 @@
+"""Pins of the oracle's time propagation.
+
+* One classical RK4 step of a time-independent affine ODE equals the degree-4
+  Taylor polynomial of the augmented generator (textbook property of RK4).
+* RK4 converges to the matrix exponential with order four.
+* RK4 on the density matrix (eq. 1) and on the Bloch vector (eq. 9) give the
+  same trajectory (the map rho <-> v of eq. 5 is affine and fixed).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import basis, lindblad as lb, propagate as pr
+from workloads import dimer, random_ops
+
+
+def _dimer_system(N):
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    F = basis.generators(N)
+    G0 = lb.q_hamiltonian(F, ops["H0"].to_dense()) + p.gamma_eff * lb.q_dissipator(F, ops["L"].to_dense())
+    G1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    K = p.gamma_eff * lb.k_dissipator(F, ops["L"].to_dense())
+    return p, ops, F, G0, G1, K
+
+
+def test_rk4_step_is_taylor_polynomial():
+    p, ops, F, G0, G1, K = _dimer_system(4)
+    G = G0 + 1.3 * G1
+    A = pr.augmented(G, K)
+    dt = 0.05
+    z = dt * A
+    P4 = np.eye(A.shape[0])
+    term = np.eye(A.shape[0])
+    for k in range(1, 5):
+        term = term @ z / k
+        P4 = P4 + term
+    v0 = np.random.default_rng(1).standard_normal(G.shape[0]) * 0.1
+    coef = np.full((3, 1), 1.3)
+    v1 = pr.rk4_bloch(G0, [G1], K, v0, coef, dt, 1)
+    np.testing.assert_allclose(v1, (P4 @ np.concatenate([v0, [1.0]]))[:-1], atol=1e-14)
+
+
+def test_rk4_fourth_order_convergence():
+    p, ops, F, G0, G1, K = _dimer_system(4)
+    G = G0 + 0.7 * G1
+    v0 = np.random.default_rng(2).standard_normal(G.shape[0]) * 0.1
+    t = 1.0
+    exact = pr.expm_affine(G, K, v0, t)
+    errs = []
+    for steps in (20, 40, 80):
+        coef = np.full((2 * steps + 1, 1), 0.7)
+        v = pr.rk4_bloch(G0, [G1], K, v0, coef, t / steps, steps)
+        errs.append(np.max(np.abs(v - exact)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 14.0 < r1 < 18.0 and 14.0 < r2 < 18.0, (errs, r1, r2)
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_rho_form_equals_bloch_form(N):
+    p, ops, F, G0, G1, K = _dimer_system(N)
+    steps = 60
+    coef = dimer.drive_table(p, steps=steps)[:, None]
+    rho0 = np.zeros((N, N), complex)
+    rho0[0, 0] = 1
+    v0 = lb.bloch_vector(F, rho0)
+    v = pr.rk4_bloch(G0, [G1], K, v0, coef, p.dt, steps)
+    rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho0, coef, p.dt, steps)
+    np.testing.assert_allclose(lb.bloch_vector(F, rho), v, atol=1e-13)
+    assert abs(np.trace(rho) - 1) < 1e-13
+
+
+def test_bloch_rk4_sparse_equals_dense():
+    import scipy.sparse as sp
+    p, ops, F, G0, G1, K = _dimer_system(4)
+    steps = 30
+    coef = dimer.drive_table(p, steps=steps)[:, None]
+    v0 = random_ops.random_vector(15, seed=4, scale=0.2)
+    a = pr.rk4_bloch(G0, [G1], K, v0, coef, p.dt, steps)
+    b = pr.rk4_bloch(sp.csr_matrix(G0), [sp.csr_matrix(G1)], K, v0, coef, p.dt, steps)
+    np.testing.assert_allclose(a, b, atol=1e-14)
