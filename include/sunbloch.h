@@ -1,0 +1,174 @@
+/*
+ * sunbloch -- SU(N) Bloch-vector form of a GKSL master equation on one
+ * AMD Instinct MI355X (gfx950), FP64.
+ *
+ * Method: A. Liniov et al., "Unfolding quantum master equation into a system
+ * of real-valued equations: computationally effective expansion over the
+ * basis of SU(N) generators" (arXiv:1812.11626).  The density matrix of an
+ * N-level system is written rho = 1/N + sum_j v_j F_j over the M = N^2 - 1
+ * generators of SU(N) (Sec. II, eq. 5); the Lindbladian (eq. 1) becomes the
+ * real affine ODE dv/dt = (Q(t) + R) v + K (eq. 9) whose matrices are
+ * contractions of the structure constants f, d (eq. 4) with the expansion
+ * coefficients of H and L_p (eqs. 6, 10, 11); the ODE is integrated with
+ * classical RK4 (Sec. IV, step 3.1).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Generator order ("grouped"): index p in [0,P), P = N(N-1)/2, is the pair
+ *    (j,k), j<k, in row-major order, p = j(2N-j-1)/2 + k-j-1; S^(j,k) has
+ *    index p, J^(j,k) index P+p, D^l index 2P+l-1 (l = 1..N-1).  All indices
+ *    are 0-based.  The diagonal generators are (sum_{i<l} G_ii - l G_ll) /
+ *    sqrt(l(l+1)) (the factor i printed in Sec. II is dropped; see design
+ *    notes).
+ *  - Every pointer argument documented "device" must point to memory of the
+ *    current HIP device; "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Kernels are queued on it.  Entry points that return sizes or counts to
+ *    host memory synchronise that stream before returning.
+ *  - Memory ownership: buffers passed in stay owned by the caller.  Objects
+ *    created by the library (sun_basis, sun_lind, sun_prop, sun_batch) own
+ *    their internal device memory (allocated with hipMalloc) until the
+ *    matching *_free call.  Objects must be freed before the process ends.
+ *  - Errors: every int-returning call returns SUN_OK (0) or a negative
+ *    status; sun_last_error() then returns a message for the calling thread.
+ *    On error, outputs are unspecified but no object is leaked.
+ *  - Calls on one object are not thread-safe; distinct objects are.
+ */
+#ifndef SUNBLOCH_H
+#define SUNBLOCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SUN_OK = 0,
+  SUN_EINVAL = -1,   /* invalid argument (sizes, null pointers, non-Hermitian H, gamma < 0, ...) */
+  SUN_ENOMEM = -2,   /* device allocation failed */
+  SUN_EDEVICE = -3,  /* a HIP runtime call failed */
+  SUN_ENOTSUP = -4,  /* valid input outside what this build supports (limits stated per call) */
+  SUN_ERANGE = -5    /* caller buffer too small; the needed size is returned */
+};
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* sun_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int sun_version(void);
+
+/* ------------------------------------------------------------------------
+ * Basis (Sec. II; Sec. IV step 2.2)
+ * ---------------------------------------------------------------------- */
+typedef struct sun_basis_s* sun_basis;
+
+/* Build the device metadata of the SU(N) basis: pair <-> index tables and the
+ * normalisations 1/sqrt(l(l+1)).  Requires 2 <= N and M = N^2-1 < 2^31.
+ * O(N^2) device memory. */
+int sun_build_basis(int32_t N, void* stream, sun_basis* out);
+/* N and M of a basis. */
+int sun_basis_dims(sun_basis b, int32_t* N, int64_t* M);
+/* Number of nonzero entries of the full structure-constant tensors f_mns and
+ * d_mns (all index orders), counted on the GPU by enumerating the closed-form
+ * nonzero pattern (Sec. IV step 2.2 states that the pattern is known
+ * analytically).  Host outputs; synchronises `stream`. */
+int sun_basis_counts(sun_basis b, void* stream, int64_t* nnz_f, int64_t* nnz_d);
+/* Export the nonzero entries of f (which = 0) or d (which = 1) in
+ * lexicographic order of (m, n, s): idx device int32[cap][3], val device
+ * double[cap].  *written (host) receives the number of entries; if it
+ * exceeds cap, nothing is written and SUN_ERANGE is returned.  Supports
+ * N <= 64 (each row of the tensor must have at most 8192 entries). */
+int sun_basis_export(sun_basis b, int32_t which, int32_t* idx, double* val,
+                     int64_t cap, int64_t* written, void* stream);
+void sun_basis_free(sun_basis b);
+
+/* ------------------------------------------------------------------------
+ * Operators and their expansion (Sec. IV step 2.1)
+ * ---------------------------------------------------------------------- */
+/* N x N complex operator in CSR form, all arrays device memory.  Columns in
+ * each row must be strictly increasing (no duplicates).  im may be NULL for a
+ * real operator. */
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* rowptr; /* [n+1] */
+  const int32_t* col;    /* [nnz] */
+  const double* re;      /* [nnz] */
+  const double* im;      /* [nnz] or NULL */
+} sun_zcsr;
+
+/* Expansion coefficients x_m = Tr(F_m X), m = 0..M-1 (complex for a
+ * non-Hermitian X), and the trace Tr(X).  coef_re/coef_im: device double[M];
+ * trace: host double[2] (re, im) or NULL (synchronises when non-NULL). */
+int sun_expand_operator(sun_basis b, const sun_zcsr* X, double* coef_re,
+                        double* coef_im, double* trace, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Lindbladian expansion (Sec. II eqs. 6, 10, 11; Sec. IV steps 2.3-2.5)
+ * ---------------------------------------------------------------------- */
+typedef struct sun_lind_s* sun_lind;
+
+enum { SUN_TERM_H = 0, SUN_TERM_L = 1 };
+
+/* Assemble, for each Hamiltonian term H_a (a < nH), the real M x M matrix
+ * Q_a with (Q_a)_sn = sum_m f_mns h_m (eq. 6), and for each dissipator L_p
+ * (p < P) the matrix R_p and vector K_p at unit rate:
+ *     R_p = -(1/2) Re(B^T A),  A_lm = sum_j l_j z_jlm,  B_ls = sum_k conj(l_k) f_kls,
+ *     z = f + i d,             K_p = (1/N) Im(B^T l)
+ * (eq. 10 with the prefactor and z read as derived in the design notes;
+ * eq. 11 with the rate factored out).  The structure constants are
+ * generated on the fly from their closed forms; nothing of size O(N^3) is
+ * stored.  Exact cancellations are dropped from each matrix: entries with
+ * |q| <= 1e-12 max|Q| are removed.
+ * H terms must be Hermitian (checked to 1e-12 max|H|, else SUN_EINVAL) and
+ * L operators traceless (|Tr L| <= 1e-12 max|L|, else SUN_ENOTSUP).
+ * Limits: every assembled row must have at most 8192 raw contributions
+ * (else SUN_ENOTSUP); total nnz of each matrix < 2^31.
+ * Synchronises `stream` (sizes are read back).  */
+int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH,
+                           const sun_zcsr* L, int32_t P, void* stream,
+                           sun_lind* out);
+/* nnz of Q_a (which = SUN_TERM_H) or R_p (which = SUN_TERM_L). */
+int sun_lind_nnz(sun_lind l, int32_t which, int32_t index, int64_t* nnz);
+/* Copy Q_a or R_p out as CSR into caller device buffers rowptr int32[M+1],
+ * col int32[nnz], val double[nnz]; for SUN_TERM_L and K != NULL also K_p
+ * (device double[M]).  Any of rowptr/col/val may be NULL to skip it. */
+int sun_lind_export(sun_lind l, int32_t which, int32_t index, int32_t* rowptr,
+                    int32_t* col, double* val, double* K, void* stream);
+void sun_lind_free(sun_lind l);
+
+/* ------------------------------------------------------------------------
+ * Propagation (eq. 9; Sec. IV step 3.1): classical RK4
+ * ---------------------------------------------------------------------- */
+typedef struct sun_prop_s* sun_prop;
+
+/* Terms of a sun_lind are numbered 0..nH-1 (Hamiltonians) then nH..nH+P-1
+ * (dissipators).  The generator is
+ *     G(t) = sum_a w_a T_a + sum_{d<ndyn} c_d(t) T_{dyn[d]},
+ *     K(t) = sum_{a in L} w_a K_a + sum_{d: dyn[d] in L} c_d(t) K_{dyn[d]}
+ * static_w: host double[nH+P]; dyn: host int32[ndyn], ndyn <= 4.
+ * Builds the fused device layout (static part merged into one CSR, the
+ * free vector folded in as an extra column, then one segment per dynamic
+ * term) and the row-block partition of the streaming kernel. */
+int sun_prop_create(sun_lind l, const double* static_w, const int32_t* dyn,
+                    int32_t ndyn, void* stream, sun_prop* out);
+/* Advance v (device double[M], in/out) by `steps` RK4 steps of size dt.
+ * coef: device double[(2*steps+1) * ndyn]; row k holds c_d(t0 + k dt/2), so
+ * the stages of step n read rows 2n, 2n+1, 2n+1, 2n+2.  Asynchronous on
+ * `stream`.  Four kernel launches per step (one per stage). */
+int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
+                  int64_t steps, void* stream);
+/* Layout facts for measurement: nnz of the fused matrix (static + dynamic
+ * segments + folded free vector), number of row blocks, rows M. */
+int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
+/* Tuning knobs of the streaming kernel: block_nnz (nnz per row block, a
+ * power of two in [256, 8192]) and xcd_remap (0/1).  Rebuilds the
+ * partition.  Defaults: 2048, 1. */
+int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t xcd_remap, void* stream);
+void sun_prop_free(sun_prop p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUNBLOCH_H */

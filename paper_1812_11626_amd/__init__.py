@@ -1,0 +1,25 @@
+"""sunbloch: SU(N) Bloch-vector Lindblad expansion and RK4 propagation on
+AMD Instinct MI355X (gfx950), FP64, as hand-written HIP kernels behind a C ABI
+(include/sunbloch.h).
+
+Public entry points mirror the C ABI:
+
+    basis = build_basis(N)
+    lind, prop = expand_lindbladian(basis, H0, H1, [(L, gamma)])
+    v = propagate(prop, v0, eps, dt, steps)
+
+plus the batched form (``BatchedPropagator``) and the adjoint form
+(``adjoint_gradient`` / ``SunBlochLoss``).  The package has no CPU fallback.
+"""
+
+from ._lib import SunError, load as load_library  # noqa: F401
+from .api import (  # noqa: F401
+    Basis,
+    DeviceOperator,
+    Lindbladian,
+    Propagator,
+    build_basis,
+    expand_lindbladian,
+    propagate,
+    require_gpu,
+)

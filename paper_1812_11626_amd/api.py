@@ -1,0 +1,230 @@
+"""Python binding of the sunbloch C ABI (argument marshalling only).
+
+Device memory and streams come from PyTorch (ROCm); every computation runs in
+the HIP library.  There is no CPU fallback: without a GPU or without
+libsunbloch.so every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SUN_TERM_H, SUN_TERM_L, ZCSR, check
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("sunbloch needs a HIP GPU (torch.cuda.is_available() is False)")
+    _lib.load()
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+@dataclass
+class DeviceOperator:
+    """An N x N operator in CSR form on the GPU (keeps the tensors alive)."""
+
+    n: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    re: torch.Tensor
+    im: torch.Tensor | None
+
+    @staticmethod
+    def from_csr(op, device="cuda") -> "DeviceOperator":
+        """From an object with n, indptr, indices, re, im (e.g. workloads.ZCSR)
+        or a scipy sparse matrix."""
+        if hasattr(op, "indptr") and hasattr(op, "re"):
+            n, indptr, indices, re, im = op.n, op.indptr, op.indices, op.re, op.im
+        else:
+            import scipy.sparse as sp
+            m = sp.csr_matrix(op)
+            m.sort_indices()
+            n = m.shape[0]
+            indptr, indices = m.indptr, m.indices
+            re, im = np.real(m.data), np.imag(m.data)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
+        return DeviceOperator(int(n), t(indptr, torch.int32), t(indices, torch.int32),
+                              t(re, torch.float64), t(im, torch.float64))
+
+    def as_struct(self) -> ZCSR:
+        return ZCSR(self.n, int(self.col.numel()), self.rowptr.data_ptr(), self.col.data_ptr(),
+                    self.re.data_ptr(), 0 if self.im is None else self.im.data_ptr())
+
+
+def _dev_op(op) -> DeviceOperator:
+    return op if isinstance(op, DeviceOperator) else DeviceOperator.from_csr(op)
+
+
+class Basis:
+    """SU(N) basis metadata on the GPU (sun_build_basis)."""
+
+    def __init__(self, N: int):
+        require_gpu()
+        self._lib = _lib.load()
+        h = C.c_void_p()
+        check(self._lib.sun_build_basis(int(N), _stream(), C.byref(h)))
+        self.handle = h
+        self.N = int(N)
+        self.M = self.N * self.N - 1
+        self.P = self.N * (self.N - 1) // 2
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.sun_basis_free(self.handle)
+            self.handle = None
+
+    def counts(self):
+        """(nnz_f, nnz_d) of the full structure-constant tensors."""
+        nf, nd = C.c_int64(), C.c_int64()
+        check(self._lib.sun_basis_counts(self.handle, _stream(), C.byref(nf), C.byref(nd)))
+        return nf.value, nd.value
+
+    def export(self, which: str):
+        """Nonzero entries of f ('f') or d ('d'): (idx int32 (nnz,3), val float64)."""
+        w = {"f": 0, "d": 1}[which]
+        n = C.c_int64()
+        st = self._lib.sun_basis_export(self.handle, w, None, None, 0, C.byref(n), _stream())
+        if st not in (_lib.SUN_OK, _lib.SUN_ERANGE):
+            check(st)
+        idx = torch.empty((max(n.value, 1), 3), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(n.value, 1), dtype=torch.float64, device="cuda")
+        check(self._lib.sun_basis_export(self.handle, w, _ptr(idx), _ptr(val), n.value, C.byref(n), _stream()))
+        return idx[: n.value], val[: n.value]
+
+    def expand(self, op):
+        """Coefficients x_m = Tr(F_m X) (complex128 tensor) and Tr(X)."""
+        d = _dev_op(op)
+        re = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        im = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        tr = (C.c_double * 2)()
+        s = d.as_struct()
+        check(self._lib.sun_expand_operator(self.handle, C.byref(s), _ptr(re), _ptr(im), tr, _stream()))
+        return torch.complex(re, im), complex(tr[0], tr[1])
+
+
+def build_basis(N: int) -> Basis:
+    return Basis(N)
+
+
+class Lindbladian:
+    """Assembled Bloch-form generator: Q_a per Hamiltonian term, R_p and K_p
+    per dissipator (unit rates), kept on the GPU (sun_expand_lindbladian)."""
+
+    def __init__(self, basis: Basis, H: list, L: list):
+        self.basis = basis
+        self._lib = basis._lib
+        hs = [_dev_op(h) for h in H]
+        ls = [_dev_op(l) for l in L]
+        Harr = (ZCSR * max(1, len(hs)))(*[h.as_struct() for h in hs])
+        Larr = (ZCSR * max(1, len(ls)))(*[l.as_struct() for l in ls])
+        h = C.c_void_p()
+        check(self._lib.sun_expand_lindbladian(basis.handle, Harr, len(hs), Larr, len(ls), _stream(),
+                                               C.byref(h)))
+        self.handle = h
+        self.nH = len(hs)
+        self.P = len(ls)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.sun_lind_free(self.handle)
+            self.handle = None
+
+    def nnz(self, which: str, index: int) -> int:
+        w = SUN_TERM_H if which == "H" else SUN_TERM_L
+        n = C.c_int64()
+        check(self._lib.sun_lind_nnz(self.handle, w, int(index), C.byref(n)))
+        return n.value
+
+    def export(self, which: str, index: int):
+        """(rowptr, col, val[, K]) device tensors of Q_index ('H') or R_index ('L')."""
+        w = SUN_TERM_H if which == "H" else SUN_TERM_L
+        n = self.nnz(which, index)
+        M = self.basis.M
+        rowptr = torch.empty(M + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        K = torch.empty(M, dtype=torch.float64, device="cuda") if w == SUN_TERM_L else None
+        check(self._lib.sun_lind_export(self.handle, w, int(index), _ptr(rowptr), _ptr(col), _ptr(val),
+                                        _ptr(K), _stream()))
+        if K is None:
+            return rowptr, col[:n], val[:n]
+        return rowptr, col[:n], val[:n], K
+
+    def propagator(self, static_w, dyn=()) -> "Propagator":
+        return Propagator(self, static_w, dyn)
+
+
+def expand_lindbladian(basis: Basis, H0, H1=None, dissipators=()):
+    """H0 (constant), H1 (multiplied by eps(t)) and [(L_p, gamma_p)]:
+    returns (Lindbladian, Propagator) with G(t) = Q_H0 + eps(t) Q_H1 +
+    sum_p gamma_p R_p and K = sum_p gamma_p K_p."""
+    Hs = [H0] + ([H1] if H1 is not None else [])
+    Ls = [l for l, _ in dissipators]
+    lind = Lindbladian(basis, Hs, Ls)
+    w = [1.0] + ([0.0] if H1 is not None else []) + [float(g) for _, g in dissipators]
+    dyn = [1] if H1 is not None else []
+    return lind, lind.propagator(w, dyn)
+
+
+class Propagator:
+    """RK4 propagator over a fused static + dynamic layout (sun_prop_create)."""
+
+    def __init__(self, lind: Lindbladian, static_w, dyn=()):
+        self.lind = lind
+        self._lib = lind._lib
+        w = (C.c_double * len(static_w))(*[float(x) for x in static_w])
+        dyn = list(dyn)
+        d = (C.c_int32 * max(1, len(dyn)))(*dyn)
+        h = C.c_void_p()
+        check(self._lib.sun_prop_create(lind.handle, w, d, len(dyn), _stream(), C.byref(h)))
+        self.handle = h
+        self.ndyn = len(dyn)
+        self.M = lind.basis.M
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.sun_prop_free(self.handle)
+            self.handle = None
+
+    def info(self):
+        nnz, nb, M = C.c_int64(), C.c_int64(), C.c_int64()
+        check(self._lib.sun_prop_info(self.handle, C.byref(nnz), C.byref(nb), C.byref(M)))
+        return {"nnz_fused": nnz.value, "nblocks": nb.value, "M": M.value}
+
+    def tune(self, block_nnz: int = 2048, xcd_remap: bool = True):
+        check(self._lib.sun_prop_tune(self.handle, int(block_nnz), int(bool(xcd_remap)), _stream()))
+
+    def propagate(self, v: torch.Tensor, coef: torch.Tensor | None, dt: float, steps: int) -> torch.Tensor:
+        """In-place RK4 on v (float64 cuda tensor of length M); coef is the
+        (2*steps+1, ndyn) half-step coefficient table on the GPU."""
+        assert v.dtype == torch.float64 and v.is_cuda and v.is_contiguous() and v.numel() == self.M
+        if self.ndyn:
+            assert coef is not None and coef.dtype == torch.float64 and coef.is_cuda and coef.is_contiguous()
+            assert coef.numel() >= (2 * steps + 1) * self.ndyn
+        check(self._lib.sun_propagate(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), _stream()))
+        return v
+
+
+def propagate(prop: Propagator, v0, eps, dt: float, steps: int) -> torch.Tensor:
+    """propagate(v0, eps(t), dt, steps): eps is a (2*steps+1,) table (numpy or
+    tensor) or a callable sampled on the half-step grid t = k dt/2."""
+    if callable(eps):
+        t = np.arange(2 * steps + 1) * (0.5 * dt)
+        eps = np.asarray([eps(x) for x in t], dtype=np.float64)
+    coef = torch.as_tensor(np.asarray(eps, dtype=np.float64).reshape(2 * steps + 1, -1)).cuda().contiguous() \
+        if prop.ndyn else None
+    v = torch.as_tensor(np.asarray(v0, dtype=np.float64)).cuda().clone() if not torch.is_tensor(v0) \
+        else v0.detach().to("cuda", torch.float64).clone()
+    return prop.propagate(v, coef, dt, steps)

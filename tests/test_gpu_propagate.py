@@ -1,0 +1,180 @@
+"""GPU RK4 propagation against the oracle.
+
+Bar: ||v_gpu - v_oracle||_inf <= 1e-12 ||v_oracle||_inf at every compared
+step.  The oracle is classical RK4 on matrices from explicit traces (dense
+tier at N = 4, column tier at N = 51) and RK4 on the density matrix itself
+(N = 51, 1001), which shares nothing with the Bloch form but the drive table.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import flush, rel_vec_err
+from oracle import basis as ob, lindblad as lb, propagate as pr
+from workloads import dimer, random_ops
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _gpu_system(lib, p, ops):
+    b = lib.build_basis(p.N)
+    lind, prop = lib.expand_lindbladian(b, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+    return b, lind, prop
+
+
+def _fock_v0(N, i=0):
+    rho = np.zeros((N, N), complex)
+    rho[i, i] = 1
+    return lb.bloch_vector_sparse(rho)
+
+
+def _run_chunks(prop, v0, eps, dt, chunk, nchunks):
+    """GPU propagation in chunks, returning the state after every chunk."""
+    v = torch.as_tensor(v0).cuda().clone()
+    coef = torch.as_tensor(eps).cuda().contiguous()
+    out = []
+    for c in range(nchunks):
+        prop.propagate(v, coef[2 * c * chunk:], dt, chunk)
+        out.append(v.cpu().numpy().copy())
+    return out
+
+
+def test_plain_N4_full_horizon_dense_oracle(lib):
+    flush("[propagate] N=4 10 periods")
+    p = dimer.plain_config(4)
+    ops = dimer.dimer_operators(p)
+    F = ob.generators(4)
+    G0 = lb.q_hamiltonian(F, ops["H0"].to_dense()) + p.gamma_eff * lb.q_dissipator(F, ops["L"].to_dense())
+    G1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    K = p.gamma_eff * lb.k_dissipator(F, ops["L"].to_dense())
+    eps = dimer.drive_table(p)
+    v0 = _fock_v0(4)
+    _, rec = pr.rk4_bloch(G0, [G1], K, v0, eps[:, None], p.dt, p.steps, record_every=p.steps_per_period)
+    _, _, prop = _gpu_system(lib, p, ops)
+    got = _run_chunks(prop, v0, eps, p.dt, p.steps_per_period, p.periods)
+    for t, (a, b) in enumerate(zip(got, rec)):
+        assert rel_vec_err(a, b) <= TOL, (t, rel_vec_err(a, b))
+
+
+def test_plain_N51_against_both_oracle_forms(lib):
+    flush("[propagate] N=51 two periods")
+    p = dimer.plain_config(51)
+    ops = dimer.dimer_operators(p)
+    G0 = lb.q_full("H", ops["H0"]) + p.gamma_eff * lb.q_full("L", ops["L"])
+    G1 = lb.q_full("H", ops["H1"])
+    K = p.gamma_eff * lb.k_vector(ops["L"])
+    steps = 2 * p.steps_per_period
+    eps = dimer.drive_table(p, steps=steps)
+    v0 = _fock_v0(51)
+    _, rec = pr.rk4_bloch(G0, [G1], K, v0, eps[:, None], p.dt, steps, record_every=250)
+    _, _, prop = _gpu_system(lib, p, ops)
+    got = _run_chunks(prop, v0, eps, p.dt, 250, steps // 250)
+    for t, (a, b) in enumerate(zip(got, rec)):
+        assert rel_vec_err(a, b) <= TOL, (t, rel_vec_err(a, b))
+    # density-matrix form, first 250 steps
+    rho0 = np.zeros((51, 51), complex)
+    rho0[0, 0] = 1
+    rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho0, eps[: 2 * 250 + 1, None], p.dt, 250)
+    assert rel_vec_err(got[0], lb.bloch_vector_sparse(rho)) <= TOL
+
+
+def test_plain_N1001_few_steps_rho_form(lib):
+    N = 1001
+    flush(f"[propagate] N={N} 3 steps")
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    steps = 3
+    # a random state near the Fock state (Hermitian, unit trace)
+    rng = np.random.default_rng(5)
+    rho0 = np.zeros((N, N), complex)
+    rho0[0, 0] = 1
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    rho0 = rho0 + 1e-3 * (X + X.conj().T)
+    rho0 /= np.trace(rho0)
+    v0 = lb.bloch_vector_sparse(rho0)
+    eps = dimer.drive_table(p, steps=steps)
+    rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho0, eps[:, None], p.dt, steps)
+    want = lb.bloch_vector_sparse(rho)
+    _, _, prop = _gpu_system(lib, p, ops)
+    got = _run_chunks(prop, v0, eps, p.dt, steps, 1)[0]
+    assert rel_vec_err(got, want) <= TOL
+
+
+def test_static_only_and_zero_steps(lib):
+    """No time-dependent term (drive folded in with a constant weight), and
+    steps = 0 leaves v unchanged."""
+    N = 5
+    flush("[propagate] static-only N=5")
+    H = random_ops.random_hermitian_csr(N, 0.8, seed=3)
+    L1 = random_ops.random_complex_csr(N, 0.5, seed=4)
+    L2 = random_ops.random_complex_csr(N, 0.5, seed=5)
+    F = ob.generators(N)
+    G = lb.q_hamiltonian(F, H.to_dense()) + 0.3 * lb.q_dissipator(F, L1.to_dense()) \
+        + 0.7 * lb.q_dissipator(F, L2.to_dense())
+    K = 0.3 * lb.k_dissipator(F, L1.to_dense()) + 0.7 * lb.k_dissipator(F, L2.to_dense())
+    v0 = random_ops.random_vector(N * N - 1, seed=6, scale=0.1)
+    steps, dt = 300, 0.01
+    want = pr.rk4_bloch(G, [], K, v0, np.zeros((2 * steps + 1, 0)), dt, steps)
+    b = lib.build_basis(N)
+    lind = lib.Lindbladian(b, [H], [L1, L2])
+    prop = lind.propagator([1.0, 0.3, 0.7], [])
+    v = torch.as_tensor(v0).cuda().clone()
+    prop.propagate(v, None, dt, 0)
+    assert np.array_equal(v.cpu().numpy(), v0)
+    prop.propagate(v, None, dt, steps)
+    assert rel_vec_err(v.cpu().numpy(), want) <= TOL
+
+
+def test_two_dynamic_terms_time_dependent_rate(lib):
+    """Drive on H1 and a time-dependent dissipation rate (dynamic L term)."""
+    N = 4
+    flush("[propagate] two dynamic terms N=4")
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    F = ob.generators(N)
+    Q0 = lb.q_hamiltonian(F, ops["H0"].to_dense())
+    Q1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    R = lb.q_dissipator(F, ops["L"].to_dense())
+    KL = lb.k_dissipator(F, ops["L"].to_dense())
+    steps = 400
+    t = np.arange(2 * steps + 1) * 0.5 * p.dt
+    coef = np.stack([p.E + p.A * np.cos(t), 0.1 * (1 + 0.5 * np.sin(2 * t))], axis=1)
+    v0 = _fock_v0(N)
+    # oracle with K carried by a term: split as G0 = Q0, terms (Q1, R), K via rate
+    v = np.array(v0)
+    for n in range(steps):
+        def rhs(x, c):
+            return Q0 @ x + c[0] * (Q1 @ x) + c[1] * (R @ x + KL)
+        c0, ch, c1 = coef[2 * n], coef[2 * n + 1], coef[2 * n + 2]
+        k1 = rhs(v, c0)
+        k2 = rhs(v + 0.5 * p.dt * k1, ch)
+        k3 = rhs(v + 0.5 * p.dt * k2, ch)
+        k4 = rhs(v + p.dt * k3, c1)
+        v = v + (p.dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    b = lib.build_basis(N)
+    lind = lib.Lindbladian(b, [ops["H0"], ops["H1"]], [ops["L"]])
+    prop = lind.propagator([1.0, 0.0, 0.0], [1, 2])
+    g = torch.as_tensor(v0).cuda().clone()
+    prop.propagate(g, torch.as_tensor(coef).cuda().contiguous(), p.dt, steps)
+    assert rel_vec_err(g.cpu().numpy(), v) <= TOL
+
+
+def test_deterministic_and_block_size_invariant(lib):
+    """Two runs are bitwise equal; another row-block size gives the same
+    numbers (each row is summed by one lane in nonzero order)."""
+    p = dimer.plain_config(51)
+    ops = dimer.dimer_operators(p)
+    _, _, prop = _gpu_system(lib, p, ops)
+    eps = torch.as_tensor(dimer.drive_table(p, steps=200)).cuda().contiguous()
+    v0 = torch.as_tensor(_fock_v0(51)).cuda()
+    outs = []
+    for bn, remap in ((2048, True), (2048, True), (512, False), (8192, True)):
+        prop.tune(bn, remap)
+        v = v0.clone()
+        prop.propagate(v, eps, p.dt, 200)
+        outs.append(v.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
