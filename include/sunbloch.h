@@ -159,13 +159,43 @@ int sun_prop_create(sun_lind l, const double* static_w, const int32_t* dyn,
  * `stream`.  Four kernel launches per step (one per stage). */
 int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
                   int64_t steps, void* stream);
+/* Same as sun_propagate, and additionally records a HIP event pair around
+ * every stage launch on `stream`; on return (synchronised) stage_ms[i]
+ * (host double[4]) holds the summed GPU time of stage i over all steps and
+ * *launches (host, may be NULL) the number of launches.  For measurement. */
+int sun_propagate_profile(sun_prop p, double* v, const double* coef, double dt,
+                          int64_t steps, void* stream, double* stage_ms,
+                          int64_t* launches);
 /* Layout facts for measurement: nnz of the fused matrix (static + dynamic
- * segments + folded free vector), number of row blocks, rows M. */
+ * segments + folded free vector), number of work units per stage launch
+ * (row blocks, or slices + long rows), rows M. */
 int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
-/* Tuning knobs of the streaming kernel: block_nnz (nnz per row block, a
- * power of two in [256, 8192]) and xcd_remap (0/1).  Rebuilds the
- * partition.  Defaults: 2048, 1. */
-int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t xcd_remap, void* stream);
+/* Two device layouts exist for the stage kernel:
+ *  1 (default when ndyn <= 1) sliced ELL: rows of at most long_len nonzeros
+ *    are sorted by length inside windows of sigma rows and packed 64 per
+ *    slice, one wavefront lane per row; longer rows are reduced by one
+ *    wavefront each.
+ *  0 (default when ndyn > 1) CSR stream: row blocks of about block_nnz
+ *    nonzeros are streamed into LDS by a workgroup of `threads` lanes, then
+ *    reduced one lane per row.
+ * Both sum every row segment in nonzero order.  sun_prop_tune selects layout 0
+ * with its knobs (block_nnz a power of two in [128, 8192], threads 64, 128 or
+ * 256, xcd_remap 0/1 gives each XCD one contiguous range of blocks);
+ * sun_prop_tune_sliced selects layout 1 (sigma a power of two in [64, 4096],
+ * long_len in [1, 4096]; ndyn <= 1 only).  In layout 1 the column index of
+ * each stored entry is kept as an offset from a per-(slice, entry) base, in
+ * 1, 2 or 4 bytes per slice, the narrowest that fits; min_col_bytes (1, 2, 4)
+ * bounds that width from below (4 = uncompressed).  Defaults 1024/256/0 and
+ * 4096/64/1. */
+int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
+                  void* stream);
+int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,
+                         void* stream);
+/* Current layout, number of stored matrix entries (with padding), rows on
+ * the long-row path, and bytes of matrix data plus per-row metadata one
+ * stage launch streams (sliced layout: excluding the long rows' entries). */
+int sun_prop_layout(sun_prop p, int32_t* layout, int64_t* stored_entries, int64_t* long_rows,
+                    int64_t* bytes_per_launch);
 void sun_prop_free(sun_prop p);
 
 #ifdef __cplusplus

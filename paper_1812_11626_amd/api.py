@@ -203,8 +203,21 @@ class Propagator:
         check(self._lib.sun_prop_info(self.handle, C.byref(nnz), C.byref(nb), C.byref(M)))
         return {"nnz_fused": nnz.value, "nblocks": nb.value, "M": M.value}
 
-    def tune(self, block_nnz: int = 2048, xcd_remap: bool = True):
-        check(self._lib.sun_prop_tune(self.handle, int(block_nnz), int(bool(xcd_remap)), _stream()))
+    def tune(self, block_nnz: int = 1024, threads: int = 256, xcd_remap: bool = False):
+        """Select the CSR-stream layout with these knobs."""
+        check(self._lib.sun_prop_tune(self.handle, int(block_nnz), int(threads), int(bool(xcd_remap)),
+                                      _stream()))
+
+    def tune_sliced(self, sigma: int = 1024, long_len: int = 64, min_col_bytes: int = 1):
+        """Select the sliced-ELL layout with these knobs."""
+        check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes),
+                                             _stream()))
+
+    def layout(self):
+        lay, stored, nlong, nb = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+        check(self._lib.sun_prop_layout(self.handle, C.byref(lay), C.byref(stored), C.byref(nlong), C.byref(nb)))
+        return {"layout": "sliced" if lay.value == 1 else "stream", "stored_entries": stored.value,
+                "long_rows": nlong.value, "matrix_bytes_per_launch": nb.value}
 
     def propagate(self, v: torch.Tensor, coef: torch.Tensor | None, dt: float, steps: int) -> torch.Tensor:
         """In-place RK4 on v (float64 cuda tensor of length M); coef is the
@@ -215,6 +228,20 @@ class Propagator:
             assert coef.numel() >= (2 * steps + 1) * self.ndyn
         check(self._lib.sun_propagate(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), _stream()))
         return v
+
+
+def _profile(self, v, coef, dt, steps):
+    """Propagate like ``propagate`` while timing every stage launch with HIP
+    events on the launch stream.  Returns per-stage summed ms (list of 4) and
+    the launch count."""
+    ms = (C.c_double * 4)()
+    n = C.c_int64()
+    check(self._lib.sun_propagate_profile(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), _stream(),
+                                          ms, C.byref(n)))
+    return list(ms), n.value
+
+
+Propagator.profile = _profile
 
 
 def propagate(prop: Propagator, v0, eps, dt: float, steps: int) -> torch.Tensor:

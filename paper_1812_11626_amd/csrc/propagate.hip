@@ -39,9 +39,19 @@ struct sun_prop_s {
   DevBuf<int> rowptr, col, seg, blk_row;
   DevBuf<double> val;
   int64_t nblocks = 0;
-  int block_nnz = 2048;
-  int xcd_remap = 1;
+  int block_nnz = 1024;
+  int threads = 256;
+  int xcd_remap = 0;
   DevBuf<double> vaug, xa, xb, acc;
+  // sliced-ELL layout (used when ndyn <= 1)
+  int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows
+  int sigma = 4096;          // rows sorted by length inside windows of sigma rows
+  int long_len = 64;         // rows longer than this use the wave-per-row path
+  int min_col_bytes = 1;     // narrowest column-delta width allowed (1, 2 or 4)
+  int64_t nshort = 0, nlong = 0, nslices = 0, sell_nnz = 0, sell_col_bytes = 0;
+  DevBuf<int> sell_row, sell_len, sell_off, sell_coff, sell_base, long_rows;
+  DevBuf<unsigned char> sell_cb;
+  DevBuf<double> sell_val;
 };
 
 namespace {
@@ -159,14 +169,14 @@ __device__ inline void rk4_update(int r, double k, const double* v, double* acc,
   }
 }
 
-template <int STAGE>
-__global__ __launch_bounds__(kThreads) void k_rk4_stage(
+template <int STAGE, int NT>
+__global__ __launch_bounds__(NT) void k_rk4_stage(
     const int* __restrict__ rowptr, const int* __restrict__ seg, int ndyn, const int* __restrict__ col,
     const double* __restrict__ val, const int* __restrict__ blk_row, int nblocks, int xcd_remap, int cap,
     const double* __restrict__ xin, const double* v, double* acc, double* xout,
     const double* __restrict__ coef, int64_t coef_row, double dt, int M) {
   extern __shared__ double prod[];
-  __shared__ double red[kThreads / 64][1 + kMaxDyn];
+  __shared__ double red[NT / 64][1 + kMaxDyn];
   int b = blockIdx.x;
   if (xcd_remap) {
     const int q = (nblocks + 7) >> 3;
@@ -182,14 +192,52 @@ __global__ __launch_bounds__(kThreads) void k_rk4_stage(
   const int n = e1 - e0;
   const int tid = threadIdx.x;
   if (n <= cap) {
-    for (int i = tid; i < n; i += kThreads) prod[i] = val[e0 + i] * xin[col[e0 + i]];
+    // operands of the row this lane finishes in phase 2, fetched early
+    const int rr = r0 + tid;
+    const bool own = rr < r1;
+    int ra = 0, rz = 0, rs = 0;
+    double vr = 0.0, ar = 0.0;
+    if (own) {
+      ra = rowptr[rr];
+      rz = rowptr[rr + 1];
+      rs = ndyn ? seg[rr] : rz;
+      vr = v[rr];
+      if (STAGE != 0) ar = acc[rr];
+    }
+    // phase 1: stream the block's nonzeros, kIt per lane per round, with all
+    // index/value loads issued before the dependent gathers
+    constexpr int kIt = 8;
+    for (int base = 0; base < n; base += NT * kIt) {
+      int ci[kIt];
+      double cv[kIt], xv[kIt];
+#pragma unroll
+      for (int u = 0; u < kIt; ++u) {
+        const int i = base + u * NT + tid;
+        ci[u] = i < n ? __builtin_nontemporal_load(col + e0 + i) : M;
+        cv[u] = i < n ? __builtin_nontemporal_load(val + e0 + i) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kIt; ++u) xv[u] = xin[ci[u]];
+#pragma unroll
+      for (int u = 0; u < kIt; ++u) {
+        const int i = base + u * NT + tid;
+        if (i < n) prod[i] = cv[u] * xv[u];
+      }
+    }
     __syncthreads();
-    for (int r = r0 + tid; r < r1; r += kThreads) {
-      const int a = rowptr[r] - e0;
-      const int z = rowptr[r + 1] - e0;
-      int send = ndyn ? seg[r] - e0 : z;
+    // phase 2: one lane per row sums its segments and updates the stage
+    for (int r = rr; r < r1; r += NT) {
+      if (r != rr) {
+        ra = rowptr[r];
+        rz = rowptr[r + 1];
+        rs = ndyn ? seg[r] : rz;
+        vr = v[r];
+        if (STAGE != 0) ar = acc[r];
+      }
+      int send = rs - e0;
+      const int z = rz - e0;
       double k = 0.0;
-      for (int i = a; i < send; ++i) k += prod[i];
+      for (int i = ra - e0; i < send; ++i) k += prod[i];
       for (int d = 0; d < ndyn; ++d) {
         const int s0 = send;
         send = (d + 1 < ndyn) ? seg[(int64_t)(d + 1) * M + r] - e0 : z;
@@ -197,7 +245,18 @@ __global__ __launch_bounds__(kThreads) void k_rk4_stage(
         for (int i = s0; i < send; ++i) sd += prod[i];
         k += eps[d] * sd;
       }
-      rk4_update<STAGE>(r, k, v, acc, xout, dt);
+      if (STAGE == 0) {
+        xout[r] = vr + (0.5 * dt) * k;
+        acc[r] = k;
+      } else if (STAGE == 1) {
+        xout[r] = vr + (0.5 * dt) * k;
+        acc[r] = ar + 2.0 * k;
+      } else if (STAGE == 2) {
+        xout[r] = vr + dt * k;
+        acc[r] = ar + 2.0 * k;
+      } else {
+        xout[r] = vr + (dt / 6.0) * (ar + k);
+      }
     }
   } else {
     // rows too long for the LDS buffer: the whole workgroup reduces one row
@@ -211,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_rk4_stage(
       for (int d = 0; d < ndyn; ++d) bounds[d + 1] = seg[(int64_t)d * M + r];
       bounds[ndyn + 1] = z;
       for (int sgm = 0; sgm <= ndyn; ++sgm)
-        for (int i = bounds[sgm] + tid; i < bounds[sgm + 1]; i += kThreads) part[sgm] += val[i] * xin[col[i]];
+        for (int i = bounds[sgm] + tid; i < bounds[sgm + 1]; i += NT) part[sgm] += val[i] * xin[col[i]];
       for (int sgm = 0; sgm <= ndyn; ++sgm) {
         double x = part[sgm];
         for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
@@ -222,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_rk4_stage(
         double k = 0.0;
         for (int sgm = 0; sgm <= ndyn; ++sgm) {
           double s = 0.0;
-          for (int w = 0; w < kThreads / 64; ++w) s += red[w][sgm];
+          for (int w = 0; w < NT / 64; ++w) s += red[w][sgm];
           k += (sgm == 0 ? 1.0 : eps[sgm - 1]) * s;
         }
         rk4_update<STAGE>(r, k, v, acc, xout, dt);
@@ -232,7 +291,372 @@ __global__ __launch_bounds__(kThreads) void k_rk4_stage(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sliced-ELL layout.  Rows of length <= long_len are taken in their natural
+// order, cut into windows of `sigma` rows, sorted by decreasing length inside
+// each window (stable), and packed 64 rows per slice: entry k of the row in
+// lane l of slice s sits at off[s] + 64 k + l, so one load instruction of a
+// wavefront reads 64 consecutive values.  A slice is as wide as its longest
+// row; shorter rows are padded with (column M, value 0), which multiplies the
+// constant 1 at x[M] and adds nothing.  Each lane keeps the static length of
+// its row so that it can split its sum into the static and the dynamic
+// segment.  Longer rows are listed separately and reduced by one wavefront
+// each.
+// ---------------------------------------------------------------------------
+constexpr int kSlice = 64;
+
+__global__ void k_row_class(int64_t M, const int* __restrict__ rowptr, int long_len,
+                            int64_t* __restrict__ is_short, int64_t* __restrict__ is_long) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    const int len = rowptr[r + 1] - rowptr[r];
+    is_short[r] = len <= long_len;
+    is_long[r] = len > long_len;
+  }
+}
+
+__global__ void k_row_scatter(int64_t M, const int64_t* __restrict__ is_short, const int64_t* __restrict__ spos,
+                              const int64_t* __restrict__ lpos, int* __restrict__ short_rows,
+                              int* __restrict__ long_rows) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    if (is_short[r]) short_rows[spos[r]] = (int)r;
+    else long_rows[lpos[r]] = (int)r;
+  }
+}
+
+// One workgroup per window: bitonic sort of (long_len - len, position) keys.
+__global__ __launch_bounds__(256) void k_window_sort(int64_t nshort, int sigma, const int* __restrict__ rowptr,
+                                                     const int* __restrict__ short_rows,
+                                                     int* __restrict__ sell_row) {
+  extern __shared__ uint64_t wk[];
+  const int64_t w0 = (int64_t)blockIdx.x * sigma;
+  const int n = (int)min((int64_t)sigma, nshort - w0);
+  int np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+    if (i < n) {
+      const int r = short_rows[w0 + i];
+      const uint32_t len = (uint32_t)(rowptr[r + 1] - rowptr[r]);
+      wk[i] = ((uint64_t)(0xFFFFFFFFu - len) << 32) | (uint32_t)i;
+    } else {
+      wk[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= np2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint64_t a = wk[i], b = wk[l];
+          if ((a > b) == ((i & k) == 0)) { wk[i] = b; wk[l] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    sell_row[w0 + i] = short_rows[w0 + (int64_t)(wk[i] & 0xFFFFFFFFu)];
+}
+
+__global__ void k_slice_width(int64_t nslices, int64_t nshort, const int* __restrict__ rowptr,
+                              const int* __restrict__ sell_row, int64_t* __restrict__ width_x64) {
+  for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < nslices;
+       sl += (int64_t)gridDim.x * blockDim.x) {
+    int w = 0;
+    for (int l = 0; l < kSlice; ++l) {
+      const int64_t i = sl * kSlice + l;
+      if (i < nshort) { const int r = sell_row[i]; w = max(w, rowptr[r + 1] - rowptr[r]); }
+    }
+    width_x64[sl] = (int64_t)w * kSlice;
+  }
+}
+
+__global__ void k_sell_fill(int64_t nslices, int64_t nshort, const int* __restrict__ rowptr,
+                            const int* __restrict__ seg, int ndyn, const int* __restrict__ col,
+                            const double* __restrict__ val, const int* __restrict__ sell_row,
+                            const int64_t* __restrict__ off64, const int64_t* __restrict__ width_x64,
+                            int* __restrict__ sell_off, int* __restrict__ sell_len, int* __restrict__ scol,
+                            double* __restrict__ sval) {
+  const int64_t total = nslices * kSlice;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = i / kSlice;
+    const int l = (int)(i % kSlice);
+    const int w = (int)(width_x64[sl] / kSlice);
+    const int64_t base = off64[sl] + l;
+    if (l == 0) sell_off[sl] = (int)off64[sl];
+    int len = 0, slen = 0, a = 0;
+    if (i < nshort) {
+      const int r = sell_row[i];
+      a = rowptr[r];
+      len = rowptr[r + 1] - a;
+      slen = ndyn ? seg[r] - a : len;
+    }
+    sell_len[i] = (len << 16) | slen;
+    for (int k = 0; k < w; ++k) {
+      const int64_t dst = base + (int64_t)k * kSlice;
+      if (k < len) { scol[dst] = col[a + k]; sval[dst] = val[a + k]; }
+      else { scol[dst] = -1; sval[dst] = 0.0; }     // padding, never read
+    }
+  }
+}
+
+// Column compression.  For every slice column (slice s, entry k) the base is
+// the smallest column index over the lanes that hold an entry there; a lane
+// stores col - base in 1, 2 or 4 bytes, the width chosen per slice (the
+// narrowest that fits every column of the slice).  Padding stores 0.
+__global__ void k_group_base(int64_t ngroups, const int* __restrict__ scol, int* __restrict__ gbase,
+                             int* __restrict__ gspan) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x) {
+    int mn = INT32_MAX, mx = -1;
+    for (int l = 0; l < kSlice; ++l) {
+      const int c = scol[g * kSlice + l];
+      if (c >= 0) { mn = min(mn, c); mx = max(mx, c); }
+    }
+    if (mx < 0) mn = mx = 0;
+    gbase[g] = mn;
+    gspan[g] = mx - mn;
+  }
+}
+
+__global__ void k_slice_mode(int64_t nslices, const int* __restrict__ sell_off, const int* __restrict__ gspan,
+                             int min_bytes, int64_t* __restrict__ cbytes, int* __restrict__ mode) {
+  for (int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sl < nslices; sl += (int64_t)gridDim.x * blockDim.x) {
+    const int g0 = sell_off[sl] / kSlice, g1 = sell_off[sl + 1] / kSlice;
+    int span = 0;
+    for (int g = g0; g < g1; ++g) span = max(span, gspan[g]);
+    int m = span < 256 ? 0 : (span < 65536 ? 1 : 2);      // 1, 2 or 4 bytes
+    const int mmin = min_bytes >= 4 ? 2 : (min_bytes >= 2 ? 1 : 0);
+    m = max(m, mmin);
+    mode[sl] = m;
+    cbytes[sl] = (int64_t)(g1 - g0) * kSlice << m;
+  }
+}
+
+__global__ void k_pack_cols(int64_t nslices, const int* __restrict__ sell_off, const int* __restrict__ scol,
+                            const int* __restrict__ gbase, const int* __restrict__ mode,
+                            const int64_t* __restrict__ coff64, int* __restrict__ sell_coff,
+                            unsigned char* __restrict__ cb) {
+  const int64_t total = nslices * kSlice;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = i / kSlice;
+    const int l = (int)(i % kSlice);
+    const int m = mode[sl];
+    if (l == 0) sell_coff[sl] = (int)coff64[sl] | m;    // offsets are multiples of 64
+    const int g0 = sell_off[sl] / kSlice, g1 = sell_off[sl + 1] / kSlice;
+    for (int g = g0; g < g1; ++g) {
+      const int c = scol[(int64_t)g * kSlice + l];
+      const uint32_t d = c >= 0 ? (uint32_t)(c - gbase[g]) : 0u;
+      const int64_t e = (int64_t)(g - g0) * kSlice + l;
+      unsigned char* dst = cb + coff64[sl];
+      if (m == 0) dst[e] = (unsigned char)d;
+      else if (m == 1) reinterpret_cast<uint16_t*>(dst)[e] = (uint16_t)d;
+      else reinterpret_cast<uint32_t*>(dst)[e] = d;
+    }
+  }
+}
+
+template <int STAGE>
+__device__ inline void stage_store(int r, double k, double vr, double ar, double* acc, double* xout, double dt) {
+  if (STAGE == 0) {
+    xout[r] = vr + (0.5 * dt) * k;
+    acc[r] = k;
+  } else if (STAGE == 1) {
+    xout[r] = vr + (0.5 * dt) * k;
+    acc[r] = ar + 2.0 * k;
+  } else if (STAGE == 2) {
+    xout[r] = vr + dt * k;
+    acc[r] = ar + 2.0 * k;
+  } else {
+    xout[r] = vr + (dt / 6.0) * (ar + k);
+  }
+}
+
+template <class T>
+__device__ inline int load_delta(const unsigned char* p, int64_t e) {
+  return (int)__builtin_nontemporal_load(reinterpret_cast<const T*>(p) + e);
+}
+
+// Sum of one lane's row over a slice whose column deltas are of type T.
+// wd, cb, gbase and vp - lane are wavefront-uniform.
+template <class T, int U>
+__device__ inline void slice_row_sum(const unsigned char* cb, const int* __restrict__ gbase,
+                                     const double* __restrict__ vp, int wd, int lane, int slen, int len,
+                                     const double* __restrict__ xin, double& a0, double& a1) {
+  // accumulate in locals with value selects (a select of the target
+  // accumulator would force both into scratch memory)
+  double s0 = 0.0, s1 = 0.0;
+  int k = 0;
+  for (; k + U <= wd; k += U) {
+    int ci[U];
+    double cv[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ci[u] = gbase[k + u] + load_delta<T>(cb, (int64_t)(k + u) * kSlice + lane);
+      cv[u] = __builtin_nontemporal_load(vp + (int64_t)(k + u) * kSlice);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = xin[ci[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double pr = cv[u] * xv[u];
+      s0 += (k + u < slen) ? pr : 0.0;
+      s1 += (k + u >= slen && k + u < len) ? pr : 0.0;
+    }
+  }
+  if (k < wd) {
+    constexpr int R = U / 2 > 0 ? U / 2 : 1;
+    for (; k < wd; k += R) {
+      int ci[R];
+      double cv[R], xv[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const bool in = k + u < wd;   // uniform
+        ci[u] = in ? gbase[k + u] + load_delta<T>(cb, (int64_t)(k + u) * kSlice + lane) : gbase[0];
+        cv[u] = in ? __builtin_nontemporal_load(vp + (int64_t)(k + u) * kSlice) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) xv[u] = xin[ci[u]];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const double pr = cv[u] * xv[u];
+        s0 += (k + u < slen) ? pr : 0.0;
+        s1 += (k + u >= slen && k + u < len) ? pr : 0.0;
+      }
+    }
+  }
+  a0 = s0;
+  a1 = s1;
+}
+
+// One wavefront per slice (or per long row).  Workgroups of 4 wavefronts.
+template <int STAGE, int U>
+__global__ __launch_bounds__(256) void k_rk4_sell(
+    const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
+    const unsigned char* __restrict__ cb_all, const int* __restrict__ sell_row, const int* __restrict__ sell_len,
+    const double* __restrict__ sval, int64_t nslices, int64_t nshort,
+    const int* __restrict__ long_rows, int64_t nlong, const int* __restrict__ rowptr, const int* __restrict__ seg,
+    const int* __restrict__ col, const double* __restrict__ val, int ndyn,
+    const double* __restrict__ xin, const double* v, double* acc, double* xout,
+    const double* __restrict__ coef, int64_t coef_row, double dt) {
+  const int lane = threadIdx.x & 63;
+  // wavefront index, made explicitly uniform so that slice metadata become
+  // scalar loads and width tests scalar branches
+  const int64_t wid = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double eps = ndyn ? coef[coef_row] : 0.0;
+  if (wid < nslices) {
+    const int64_t i = wid * kSlice + lane;
+    const int off = __builtin_amdgcn_readfirstlane(sell_off[wid]);
+    const int wd = (__builtin_amdgcn_readfirstlane(sell_off[wid + 1]) - off) / kSlice;   // slice width
+    const int coff = __builtin_amdgcn_readfirstlane(sell_coff[wid]);
+    const bool own = i < nshort;
+    const int r = own ? sell_row[i] : 0;
+    const int lens = sell_len[i];
+    const int slen = lens & 0xFFFF, len = lens >> 16;
+    double vr = 0.0, ar = 0.0;
+    if (own) {
+      vr = v[r];
+      if (STAGE != 0) ar = acc[r];
+    }
+    const unsigned char* cb = cb_all + (coff & ~63);
+    const int* gbase = gbase_all + off / kSlice;
+    const double* vp = sval + off + lane;
+    double a0 = 0.0, a1 = 0.0;
+    switch (coff & 3) {
+      case 0: slice_row_sum<uint8_t, U>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 1: slice_row_sum<uint16_t, U>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      default: slice_row_sum<uint32_t, U>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+    }
+    if (own) stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
+  } else if (wid < nslices + nlong) {
+    const int r = long_rows[wid - nslices];
+    const int a = rowptr[r], z = rowptr[r + 1];
+    const int sb = ndyn ? seg[r] : z;
+    double a0 = 0.0, a1 = 0.0;
+    for (int e = a + lane; e < z; e += 64) {
+      const double pr = val[e] * xin[col[e]];
+      a0 += e < sb ? pr : 0.0;
+      a1 += e < sb ? 0.0 : pr;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      a0 += __shfl_down(a0, o, 64);
+      a1 += __shfl_down(a1, o, 64);
+    }
+    if (lane == 0) {
+      const double vr = v[r];
+      const double ar = STAGE != 0 ? acc[r] : 0.0;
+      stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
+    }
+  }
+}
+
+void build_sell(sun_prop_s& p, hipStream_t s) {
+  HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old layout
+  const int64_t M = p.M;
+  DevBuf<int64_t> is_short(M), is_long(M), spos(M), lpos(M);
+  hipLaunchKernelGGL(k_row_class, dim3(grid_for(M, 256)), dim3(256), 0, s, M, p.rowptr.get(), p.long_len,
+                     is_short.get(), is_long.get());
+  HIP_LAUNCH_OK();
+  p.nshort = exclusive_scan_i64(is_short.get(), spos.get(), M, s);
+  p.nlong = exclusive_scan_i64(is_long.get(), lpos.get(), M, s);
+  DevBuf<int> short_rows(p.nshort > 0 ? p.nshort : 1);
+  p.long_rows.alloc(p.nlong > 0 ? p.nlong : 1);
+  hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(M, 256)), dim3(256), 0, s, M, is_short.get(), spos.get(),
+                     lpos.get(), short_rows.get(), p.long_rows.get());
+  HIP_LAUNCH_OK();
+  p.nslices = (p.nshort + kSlice - 1) / kSlice;
+  const int64_t padded_rows = p.nslices * kSlice;
+  p.sell_row.alloc(padded_rows > 0 ? padded_rows : 1);
+  p.sell_len.alloc(padded_rows > 0 ? padded_rows : 1);
+  p.sell_off.alloc(p.nslices + 1);
+  p.sell_coff.alloc(p.nslices + 1);
+  p.sell_nnz = 0;
+  p.sell_col_bytes = 0;
+  if (p.nshort > 0) {
+    const int64_t nwin = (p.nshort + p.sigma - 1) / p.sigma;
+    int np2 = 1;
+    while (np2 < p.sigma) np2 <<= 1;
+    hipLaunchKernelGGL(k_window_sort, dim3((unsigned)nwin), dim3(256), np2 * sizeof(uint64_t), s, p.nshort,
+                       p.sigma, p.rowptr.get(), short_rows.get(), p.sell_row.get());
+    HIP_LAUNCH_OK();
+    DevBuf<int64_t> wx(p.nslices), off64(p.nslices);
+    hipLaunchKernelGGL(k_slice_width, dim3(grid_for(p.nslices, 256)), dim3(256), 0, s, p.nslices, p.nshort,
+                       p.rowptr.get(), p.sell_row.get(), wx.get());
+    HIP_LAUNCH_OK();
+    p.sell_nnz = exclusive_scan_i64(wx.get(), off64.get(), p.nslices, s);
+    SUN_REQUIRE(p.sell_nnz < (int64_t)INT32_MAX, SUN_ENOTSUP, "sliced layout has 2^31 or more entries");
+    DevBuf<int> scol(p.sell_nnz);
+    p.sell_val.alloc(p.sell_nnz);
+    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(padded_rows, 256)), dim3(256), 0, s, p.nslices, p.nshort,
+                       p.rowptr.get(), p.seg.get(), p.ndyn, p.col.get(), p.val.get(), p.sell_row.get(),
+                       off64.get(), wx.get(), p.sell_off.get(), p.sell_len.get(), scol.get(), p.sell_val.get());
+    HIP_LAUNCH_OK();
+    int tot = (int)p.sell_nnz;
+    HIP_OK(hipMemcpyAsync(p.sell_off.get() + p.nslices, &tot, sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    // column compression
+    const int64_t ngroups = p.sell_nnz / kSlice;
+    p.sell_base.alloc(ngroups);
+    DevBuf<int> gspan(ngroups), mode(p.nslices);
+    DevBuf<int64_t> cbytes(p.nslices), coff64(p.nslices);
+    hipLaunchKernelGGL(k_group_base, dim3(grid_for(ngroups, 256)), dim3(256), 0, s, ngroups, scol.get(),
+                       p.sell_base.get(), gspan.get());
+    HIP_LAUNCH_OK();
+    hipLaunchKernelGGL(k_slice_mode, dim3(grid_for(p.nslices, 256)), dim3(256), 0, s, p.nslices,
+                       p.sell_off.get(), gspan.get(), p.min_col_bytes, cbytes.get(), mode.get());
+    HIP_LAUNCH_OK();
+    p.sell_col_bytes = exclusive_scan_i64(cbytes.get(), coff64.get(), p.nslices, s);
+    SUN_REQUIRE(p.sell_col_bytes < (int64_t)INT32_MAX, SUN_ENOTSUP, "column stream of 2^31 bytes or more");
+    p.sell_cb.alloc(p.sell_col_bytes);
+    hipLaunchKernelGGL(k_pack_cols, dim3(grid_for(padded_rows, 256)), dim3(256), 0, s, p.nslices,
+                       p.sell_off.get(), scol.get(), p.sell_base.get(), mode.get(), coff64.get(),
+                       p.sell_coff.get(), p.sell_cb.get());
+    HIP_LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+}
+
 void build_partition(sun_prop_s& p, hipStream_t s) {
+  HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old partition
   const int64_t M = p.M;
   DevBuf<int64_t> flag(M), id(M);
   hipLaunchKernelGGL(k_block_flags, dim3(grid_for(M, 256)), dim3(256), 0, s, M, p.rowptr.get(), p.block_nnz,
@@ -246,23 +670,45 @@ void build_partition(sun_prop_s& p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));
 }
 
-int stage_capacity(int block_nnz) {
+int stage_capacity(int block_nnz, int threads) {
   static size_t lim = 0;
   if (!lim) lim = lds_limit();
-  int cap = 2 * block_nnz;
+  // single-wave blocks keep their LDS small (occupancy); blocks with a row
+  // that does not fit take the row-reduction path instead
+  int cap = threads == 64 ? block_nnz + block_nnz / 2 : 2 * block_nnz;
   while (cap > 256 && (size_t)cap * sizeof(double) + 1024 > lim) cap >>= 1;
   return cap;
+}
+
+template <int STAGE, int NT>
+void launch_stage_nt(const sun_prop_s& p, const double* xin, double* xout, const double* coef, int64_t row,
+                     double dt, hipStream_t s) {
+  const int cap = stage_capacity(p.block_nnz, NT);
+  const int grid = p.xcd_remap ? (int)(((p.nblocks + 7) / 8) * 8) : (int)p.nblocks;
+  hipLaunchKernelGGL((k_rk4_stage<STAGE, NT>), dim3(grid), dim3(NT), cap * sizeof(double), s,
+                     p.rowptr.get(), p.seg.get(), p.ndyn, p.col.get(), p.val.get(), p.blk_row.get(),
+                     (int)p.nblocks, p.xcd_remap, cap, xin, p.vaug.get(), p.acc.get(), xout, coef, row, dt,
+                     (int)p.M);
 }
 
 template <int STAGE>
 void launch_stage(const sun_prop_s& p, const double* xin, double* xout, const double* coef, int64_t row,
                   double dt, hipStream_t s) {
-  const int cap = stage_capacity(p.block_nnz);
-  const int grid = p.xcd_remap ? (int)(((p.nblocks + 7) / 8) * 8) : (int)p.nblocks;
-  hipLaunchKernelGGL((k_rk4_stage<STAGE>), dim3(grid), dim3(kThreads), cap * sizeof(double), s,
-                     p.rowptr.get(), p.seg.get(), p.ndyn, p.col.get(), p.val.get(), p.blk_row.get(),
-                     (int)p.nblocks, p.xcd_remap, cap, xin, p.vaug.get(), p.acc.get(), xout, coef, row, dt,
-                     (int)p.M);
+  if (p.layout == 1) {
+    const int64_t waves = p.nslices + p.nlong;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    hipLaunchKernelGGL((k_rk4_sell<STAGE, 8>), dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
+                       p.sell_base.get(), p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_val.get(),
+                       p.nslices, p.nshort,
+                       p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(), p.val.get(), p.ndyn,
+                       xin, p.vaug.get(), p.acc.get(), xout, coef, row, dt);
+    return;
+  }
+  switch (p.threads) {
+    case 64: launch_stage_nt<STAGE, 64>(p, xin, xout, coef, row, dt, s); break;
+    case 128: launch_stage_nt<STAGE, 128>(p, xin, xout, coef, row, dt, s); break;
+    default: launch_stage_nt<STAGE, 256>(p, xin, xout, coef, row, dt, s); break;
+  }
 }
 
 }  // namespace
@@ -331,6 +777,8 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
                          p->rowptr.get());
       HIP_LAUNCH_OK();
       build_partition(*p, s);
+      p->layout = ndyn <= 1 ? 1 : 0;
+      if (p->layout == 1) build_sell(*p, s);
       p->vaug.alloc(M + 1);
       p->xa.alloc(M + 1);
       p->xb.alloc(M + 1);
@@ -350,14 +798,36 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
   });
 }
 
-extern "C" int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t xcd_remap, void* stream) {
+extern "C" int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
+                             void* stream) {
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
-    SUN_REQUIRE(block_nnz >= 256 && block_nnz <= 8192 && (block_nnz & (block_nnz - 1)) == 0, SUN_EINVAL,
-                "block_nnz must be a power of two in [256, 8192]");
+    SUN_REQUIRE(block_nnz >= 128 && block_nnz <= 8192 && (block_nnz & (block_nnz - 1)) == 0, SUN_EINVAL,
+                "block_nnz must be a power of two in [128, 8192]");
+    SUN_REQUIRE(threads == 64 || threads == 128 || threads == 256, SUN_EINVAL, "threads must be 64, 128 or 256");
     p->block_nnz = block_nnz;
+    p->threads = threads;
     p->xcd_remap = xcd_remap ? 1 : 0;
+    p->layout = 0;
     build_partition(*p, as_stream(stream));
+  });
+}
+
+extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,
+                                    void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
+    SUN_REQUIRE(p->ndyn <= 1, SUN_ENOTSUP, "the sliced layout supports at most one time-dependent term");
+    SUN_REQUIRE(sigma >= 64 && sigma <= 4096 && (sigma & (sigma - 1)) == 0, SUN_EINVAL,
+                "sigma must be a power of two in [64, 4096]");
+    SUN_REQUIRE(long_len >= 1 && long_len <= 4096, SUN_EINVAL, "long_len must be in [1, 4096]");
+    SUN_REQUIRE(min_col_bytes == 1 || min_col_bytes == 2 || min_col_bytes == 4, SUN_EINVAL,
+                "min_col_bytes must be 1, 2 or 4");
+    p->sigma = sigma;
+    p->long_len = long_len;
+    p->min_col_bytes = min_col_bytes;
+    p->layout = 1;
+    build_sell(*p, as_stream(stream));
   });
 }
 
@@ -365,8 +835,31 @@ extern "C" int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, i
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
     if (nnz_fused) *nnz_fused = p->nnz;
-    if (nblocks) *nblocks = p->nblocks;
+    if (nblocks) *nblocks = p->layout == 1 ? p->nslices + p->nlong : p->nblocks;
     if (M) *M = p->M;
+  });
+}
+
+extern "C" int sun_prop_layout(sun_prop p, int32_t* layout, int64_t* stored_entries, int64_t* long_rows,
+                               int64_t* bytes_per_launch) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
+    if (layout) *layout = p->layout;
+    if (stored_entries) *stored_entries = p->layout == 1 ? p->sell_nnz : p->nnz;
+    if (long_rows) *long_rows = p->layout == 1 ? p->nlong : 0;
+    if (bytes_per_launch) {
+      // matrix stream + per-row metadata, excluding the vectors
+      int64_t b = 0;
+      if (p->layout == 1) {
+        int64_t long_nnz = 0;  // long rows stream their CSR entries
+        b = p->sell_nnz * 8 + p->sell_col_bytes + (p->sell_nnz / kSlice) * 4 + p->nslices * kSlice * 8 +
+            (p->nslices + 1) * 8;
+        (void)long_nnz;
+      } else {
+        b = p->nnz * 12 + (p->M + 1) * 4 + (int64_t)p->ndyn * p->M * 4;
+      }
+      *bytes_per_launch = b;
+    }
   });
 }
 
@@ -390,6 +883,55 @@ extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double d
     }
     HIP_LAUNCH_OK();
     HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  });
+}
+
+extern "C" int sun_propagate_profile(sun_prop p, double* v, const double* coef, double dt, int64_t steps,
+                                     void* stream, double* stage_ms, int64_t* launches) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr && v != nullptr && stage_ms != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(steps >= 0, SUN_EINVAL, "steps must be >= 0");
+    SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    hipStream_t s = as_stream(stream);
+    const int64_t M = p->M;
+    for (int i = 0; i < 4; ++i) stage_ms[i] = 0.0;
+    if (launches) *launches = 4 * steps;
+    if (steps == 0) return;
+    // one event pair per launch, recorded on the launch stream
+    std::vector<hipEvent_t> ev(8 * steps, nullptr);
+    struct Guard {
+      std::vector<hipEvent_t>& e;
+      ~Guard() { for (auto x : e) if (x) (void)hipEventDestroy(x); }
+    } guard{ev};
+    for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+    HIP_OK(hipMemcpyAsync(p->vaug.get(), v, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double* va = p->vaug.get();
+    double* xa = p->xa.get();
+    double* xb = p->xb.get();
+    for (int64_t n = 0; n < steps; ++n) {
+      hipEvent_t* e = &ev[8 * n];
+      HIP_OK(hipEventRecord(e[0], s));
+      launch_stage<0>(*p, va, xa, coef, 2 * n, dt, s);
+      HIP_OK(hipEventRecord(e[1], s));
+      HIP_OK(hipEventRecord(e[2], s));
+      launch_stage<1>(*p, xa, xb, coef, 2 * n + 1, dt, s);
+      HIP_OK(hipEventRecord(e[3], s));
+      HIP_OK(hipEventRecord(e[4], s));
+      launch_stage<2>(*p, xb, xa, coef, 2 * n + 1, dt, s);
+      HIP_OK(hipEventRecord(e[5], s));
+      HIP_OK(hipEventRecord(e[6], s));
+      launch_stage<3>(*p, xa, va, coef, 2 * n + 2, dt, s);
+      HIP_OK(hipEventRecord(e[7], s));
+    }
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int64_t n = 0; n < steps; ++n)
+      for (int i = 0; i < 4; ++i) {
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, ev[8 * n + 2 * i], ev[8 * n + 2 * i + 1]));
+        stage_ms[i] += ms;
+      }
   });
 }
 

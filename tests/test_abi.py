@@ -51,6 +51,6 @@ def test_host_side_argument_checks():
     assert lib.sun_build_basis(50000, None, ctypes.byref(h)) == _lib.SUN_EINVAL
     assert lib.sun_build_basis(4, None, None) == _lib.SUN_EINVAL
     assert lib.sun_propagate(None, None, None, 0.1, 1, None) == _lib.SUN_EINVAL
-    assert lib.sun_prop_tune(None, 2048, 1, None) == _lib.SUN_EINVAL
+    assert lib.sun_prop_tune(None, 2048, 256, 1, None) == _lib.SUN_EINVAL
     n = ctypes.c_int64()
     assert lib.sun_lind_nnz(None, 0, 0, ctypes.byref(n)) == _lib.SUN_EINVAL

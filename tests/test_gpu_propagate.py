@@ -171,10 +171,39 @@ def test_deterministic_and_block_size_invariant(lib):
     eps = torch.as_tensor(dimer.drive_table(p, steps=200)).cuda().contiguous()
     v0 = torch.as_tensor(_fock_v0(51)).cuda()
     outs = []
-    for bn, remap in ((2048, True), (2048, True), (512, False), (8192, True)):
-        prop.tune(bn, remap)
+    for bn, nt, remap in ((1024, 256, False), (1024, 256, False), (512, 64, False), (256, 64, True),
+                          (8192, 256, True), (2048, 128, False)):
+        prop.tune(bn, nt, remap)
         v = v0.clone()
         prop.propagate(v, eps, p.dt, 200)
         outs.append(v.cpu().numpy())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+def test_sliced_layout_matches_stream_layout(lib):
+    """The sliced-ELL layout (default for <= 1 dynamic term) and the CSR
+    stream layout agree to rounding, and the sliced layout is deterministic,
+    for several window sizes and long-row thresholds (N = 51 has rows from 5
+    to 62 nonzeros)."""
+    p = dimer.plain_config(51)
+    ops = dimer.dimer_operators(p)
+    _, _, prop = _gpu_system(lib, p, ops)
+    assert prop.layout()["layout"] == "sliced"
+    eps = torch.as_tensor(dimer.drive_table(p, steps=300)).cuda().contiguous()
+    v0 = torch.as_tensor(_fock_v0(51)).cuda()
+    prop.tune(1024, 256, False)
+    ref = v0.clone()
+    prop.propagate(ref, eps, p.dt, 300)
+    ref = ref.cpu().numpy()
+    for sigma, long_len, cb in ((1024, 64, 1), (1024, 64, 4), (64, 8, 2), (4096, 1, 1), (256, 4096, 1)):
+        prop.tune_sliced(sigma, long_len, cb)
+        v = v0.clone()
+        prop.propagate(v, eps, p.dt, 300)
+        assert rel_vec_err(v.cpu().numpy(), ref) <= 1e-14, (sigma, long_len, cb)
+    a = v0.clone()
+    b = v0.clone()
+    prop.tune_sliced(1024, 64)
+    prop.propagate(a, eps, p.dt, 300)
+    prop.propagate(b, eps, p.dt, 300)
+    assert torch.equal(a, b)
