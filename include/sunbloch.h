@@ -178,7 +178,8 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  *  0 (default when ndyn > 1) CSR stream: row blocks of about block_nnz
  *    nonzeros are streamed into LDS by a workgroup of `threads` lanes, then
  *    reduced one lane per row.
- * Both sum every row segment in nonzero order.  sun_prop_tune selects layout 0
+ * Rows summed by one lane (all of layout 0, the short rows of layout 1) add
+ * their entries in nonzero order; long rows use a wavefront tree reduction.  sun_prop_tune selects layout 0
  * with its knobs (block_nnz a power of two in [128, 8192], threads 64, 128 or
  * 256, xcd_remap 0/1 gives each XCD one contiguous range of blocks);
  * sun_prop_tune_sliced selects layout 1 (sigma a power of two in [64, 4096],
@@ -197,6 +198,77 @@ int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t mi
 int sun_prop_layout(sun_prop p, int32_t* layout, int64_t* stored_entries, int64_t* long_rows,
                     int64_t* bytes_per_launch);
 void sun_prop_free(sun_prop p);
+
+/* ------------------------------------------------------------------------
+ * Batched propagation: many parameter instances, one launch per RK4 stage
+ * ---------------------------------------------------------------------- */
+typedef struct sun_batch_s* sun_batch;
+
+/* Groups of instances that share an assembled system lind[g] (terms T_a,
+ * a < nt_g = nH + P of that system; nt_g <= 8).  Instance b of group g
+ * evolves under G_b(t) = sum_a c_{b,a}(t) T_a and K_b(t) = sum over the
+ * dissipator terms of c_{b,a}(t) K_a, with the coefficient on the half-step
+ * grid t_k = k dt_g / 2 given by c_{b,a}(t_k) = w_g[b*nt_g + a] +
+ * u_g[b*nt_g + a] * wave_g[k].  w[g], u[g]: device double[B[g]*nt_g];
+ * wave[g]: device double[2*steps[g]+1]; dt, steps: host arrays.  The library
+ * keeps pointers to w, u and wave (they must outlive the object).  Each group
+ * gets a fused row layout with one segment per term and a state of
+ * (M_g+1) x ld_g doubles per buffer (4 buffers, ld_g = B[g] rounded up to 64).
+ * States start at zero; set them with sun_batch_set_state.  Synchronises. */
+int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int32_t* B,
+                     const double* const* w, const double* const* u,
+                     const double* const* wave, const double* dt,
+                     const int64_t* steps, void* stream, sun_batch* out);
+/* Load the states of group g from V (device double[B[g]][M_g], one Bloch
+ * vector per instance) and reset the group's step counter to 0. */
+int sun_batch_set_state(sun_batch b, int32_t g, const double* V, void* stream);
+/* Copy the states of group g to V (device double[B[g]][M_g]). */
+int sun_batch_get_state(sun_batch b, int32_t g, double* V, void* stream);
+/* Advance every group (or only group `only_group` if >= 0) by up to nsteps
+ * RK4 steps, never past its own step count.  Each step is four launches
+ * (one per stage) that cover all active groups: work items (group, block of
+ * rows, tile of instances) are spread over a fixed grid of wavefronts.
+ * Synchronises at the end. */
+int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream);
+/* Per-group tiling: tile = instances per lane group (8, 16, 32 or 64; a
+ * wavefront treats 64/tile rows side by side), rows_per_item = rows per work
+ * item.  Defaults 64 and 64.  Results do not depend on the tiling. */
+int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, void* stream);
+int sun_batch_info(sun_batch b, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,
+                   int32_t* rows_per_item);
+void sun_batch_free(sun_batch b);
+
+/* ------------------------------------------------------------------------
+ * Adjoint: gradient of a time-averaged observable through the RK4 map
+ * ---------------------------------------------------------------------- */
+typedef struct sun_adj_s* sun_adj;
+
+/* Prepare the forward propagator of the generator described by (static_w,
+ * dyn, ndyn) exactly as sun_prop_create does (ndyn <= 1 here), and a second
+ * one over the transposed terms T_a^T (built on the GPU) for the reverse
+ * sweep.  The terms of `l` must stay alive while the object is used. */
+int sun_adjoint_create(sun_lind l, const double* static_w, const int32_t* dyn, int32_t ndyn,
+                       void* stream, sun_adj* out);
+/* J = (1/S_avg) sum_{n=steps-S_avg+1}^{steps} cobs . v_n for the RK4 states
+ * v_n from v0 (device double[M]) with the drive table coef (device
+ * double[(2*steps+1)*ndyn], as for sun_propagate), and dJ/dtheta for ntheta
+ * (<= 8) parameters, by the discrete adjoint of the RK4 map (the derivative
+ * of this J, not of the exact ODE solution).  The coefficient of term a is
+ * static_w[a] (+ c_d(t) if a = dyn[d]); its derivative is dstatic[a*ntheta +
+ * th] (host) plus, for the time-dependent term, dcoef[(k*ndyn + d)*ntheta +
+ * th] (device, may be NULL = 0).  cobs: device double[M].  States are
+ * checkpointed every ckpt_every steps and recomputed one interval at a time
+ * in the reverse sweep (memory: (steps/ckpt_every + ckpt_every + 10) vectors
+ * of M+1 doubles).  J_out: host double; grad_out: host double[ntheta] (may be
+ * NULL).  Synchronises. */
+int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, const double* dstatic,
+                    const double* dcoef, int32_t ntheta, const double* cobs, double dt,
+                    int64_t steps, int64_t S_avg, int64_t ckpt_every, double* J_out,
+                    double* grad_out, void* stream);
+/* The forward objective J alone (same definition), e.g. for finite differences. */
+int sun_adjoint_objective(sun_adj a, const double* v0, const double* coef, const double* cobs,
+                          double dt, int64_t steps, int64_t S_avg, double* J_out, void* stream);
+void sun_adjoint_free(sun_adj a);
 
 #ifdef __cplusplus
 }

@@ -8,12 +8,15 @@ Public entry points mirror the C ABI:
     lind, prop = expand_lindbladian(basis, H0, H1, [(L, gamma)])
     v = propagate(prop, v0, eps, dt, steps)
 
-plus the batched form (``BatchedPropagator``) and the adjoint form
-(``adjoint_gradient`` / ``SunBlochLoss``).  The package has no CPU fallback.
+plus the batched form (``BatchedPropagator``, ``autotune_batched``) and the
+adjoint form (``Adjoint``, ``AdjointProblem``, ``SunBlochLoss``).  The package has no CPU fallback.
 """
 
 from ._lib import SunError, load as load_library  # noqa: F401
 from .api import (  # noqa: F401
+    Adjoint,
+    AdjointProblem,
+    BatchedPropagator,
     Basis,
     DeviceOperator,
     Lindbladian,
@@ -22,4 +25,6 @@ from .api import (  # noqa: F401
     expand_lindbladian,
     propagate,
     require_gpu,
+    SunBlochLoss,
 )
+from .autotune import autotune_batched  # noqa: F401

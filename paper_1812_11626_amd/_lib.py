@@ -61,12 +61,16 @@ PROTOS = {
     "sun_prop_layout": (C.c_int, [vp, P(i32), P(i64), P(i64), P(i64)]),
     "sun_prop_free": (None, [vp]),
     "sun_batch_create": (C.c_int, [P(vp), i32, P(i32), P(vp), P(vp), P(vp), P(f64), P(i64), vp, P(vp)]),
-    "sun_batch_run": (C.c_int, [vp, P(vp), i64, vp]),
+    "sun_batch_set_state": (C.c_int, [vp, i32, vp, vp]),
+    "sun_batch_get_state": (C.c_int, [vp, i32, vp, vp]),
+    "sun_batch_run": (C.c_int, [vp, i64, i32, vp]),
     "sun_batch_info": (C.c_int, [vp, i32, P(i64), P(i64), P(i32), P(i32)]),
     "sun_batch_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_batch_free": (None, [vp]),
-    "sun_adjoint": (C.c_int, [vp, P(f64), P(i32), i32, vp, vp, P(f64), vp, i32, vp, f64, i64, i64, i64,
-                               P(f64), P(f64), vp]),
+    "sun_adjoint_create": (C.c_int, [vp, P(f64), P(i32), i32, vp, P(vp)]),
+    "sun_adjoint_run": (C.c_int, [vp, vp, vp, P(f64), vp, i32, vp, f64, i64, i64, i64, P(f64), P(f64), vp]),
+    "sun_adjoint_objective": (C.c_int, [vp, vp, vp, vp, f64, i64, i64, P(f64), vp]),
+    "sun_adjoint_free": (None, [vp]),
 }
 
 _lib = None

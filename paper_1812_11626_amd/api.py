@@ -255,3 +255,166 @@ def propagate(prop: Propagator, v0, eps, dt: float, steps: int) -> torch.Tensor:
     v = torch.as_tensor(np.asarray(v0, dtype=np.float64)).cuda().clone() if not torch.is_tensor(v0) \
         else v0.detach().to("cuda", torch.float64).clone()
     return prop.propagate(v, coef, dt, steps)
+
+
+class BatchedPropagator:
+    """Many parameter instances advanced together (sun_batch_*).
+
+    groups: list of dicts with keys
+      lind  -- Lindbladian shared by the group's instances
+      w, u  -- (B, nt) coefficient arrays: c_{b,a}(t_k) = w[b,a] + u[b,a] wave[k]
+      wave  -- (2*steps+1,) waveform on the half-step grid
+      dt, steps
+    """
+
+    def __init__(self, groups):
+        require_gpu()
+        self._lib = _lib.load()
+        self.groups = []
+        keep = []
+        for g in groups:
+            lind = g["lind"]
+            nt = lind.nH + lind.P
+            w = torch.as_tensor(np.asarray(g["w"], dtype=np.float64).reshape(-1, nt)).cuda().contiguous()
+            u = torch.as_tensor(np.asarray(g["u"], dtype=np.float64).reshape(-1, nt)).cuda().contiguous()
+            wave = torch.as_tensor(np.asarray(g["wave"], dtype=np.float64)).cuda().contiguous()
+            assert wave.numel() >= 2 * int(g["steps"]) + 1
+            self.groups.append(dict(lind=lind, w=w, u=u, wave=wave, dt=float(g["dt"]), steps=int(g["steps"]),
+                                    B=w.shape[0], M=lind.basis.M, N=lind.basis.N, nt=nt))
+            keep.append(lind)
+        n = len(self.groups)
+        linds = (C.c_void_p * n)(*[g["lind"].handle.value for g in self.groups])
+        B = (C.c_int32 * n)(*[g["B"] for g in self.groups])
+        wp = (C.c_void_p * n)(*[g["w"].data_ptr() for g in self.groups])
+        up = (C.c_void_p * n)(*[g["u"].data_ptr() for g in self.groups])
+        vp = (C.c_void_p * n)(*[g["wave"].data_ptr() for g in self.groups])
+        dt = (C.c_double * n)(*[g["dt"] for g in self.groups])
+        st = (C.c_int64 * n)(*[g["steps"] for g in self.groups])
+        h = C.c_void_p()
+        check(self._lib.sun_batch_create(linds, n, B, wp, up, vp, dt, st, _stream(), C.byref(h)))
+        self.handle = h
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.sun_batch_free(self.handle)
+            self.handle = None
+
+    def set_state(self, g: int, V: torch.Tensor):
+        G = self.groups[g]
+        V = V.to("cuda", torch.float64).contiguous()
+        assert V.shape == (G["B"], G["M"])
+        check(self._lib.sun_batch_set_state(self.handle, int(g), _ptr(V), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def get_state(self, g: int) -> torch.Tensor:
+        G = self.groups[g]
+        V = torch.empty((G["B"], G["M"]), dtype=torch.float64, device="cuda")
+        check(self._lib.sun_batch_get_state(self.handle, int(g), _ptr(V), _stream()))
+        return V
+
+    def run(self, nsteps: int, only_group: int = -1):
+        check(self._lib.sun_batch_run(self.handle, int(nsteps), int(only_group), _stream()))
+
+    def tune(self, g: int, tile: int, rows_per_item: int):
+        check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), _stream()))
+
+    def info(self, g: int):
+        M, nnz, tile, rows = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()
+        check(self._lib.sun_batch_info(self.handle, int(g), C.byref(M), C.byref(nnz), C.byref(tile),
+                                       C.byref(rows)))
+        return {"M": M.value, "nnz": nnz.value, "tile": tile.value, "rows_per_item": rows.value}
+
+
+class Adjoint:
+    """Forward + transposed propagators for the discrete adjoint (sun_adjoint_*)."""
+
+    def __init__(self, lind: Lindbladian, static_w, dyn=()):
+        self.lind = lind
+        self._lib = lind._lib
+        self.nt = lind.nH + lind.P
+        w = (C.c_double * self.nt)(*[float(x) for x in static_w])
+        dyn = list(dyn)
+        d = (C.c_int32 * max(1, len(dyn)))(*dyn)
+        h = C.c_void_p()
+        check(self._lib.sun_adjoint_create(lind.handle, w, d, len(dyn), _stream(), C.byref(h)))
+        self.handle = h
+        self.ndyn = len(dyn)
+        self.M = lind.basis.M
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.sun_adjoint_free(self.handle)
+            self.handle = None
+
+    def run(self, v0, coef, dstatic, dcoef, cobs, dt, steps, S_avg, ckpt_every):
+        """(J, dJ/dtheta).  dstatic: host (nt, ntheta); dcoef: device
+        (2*steps+1, ndyn, ntheta) tensor or None."""
+        dstatic = np.ascontiguousarray(np.asarray(dstatic, dtype=np.float64).reshape(self.nt, -1))
+        ntheta = dstatic.shape[1]
+        ds = dstatic.ctypes.data_as(C.POINTER(C.c_double))
+        J = C.c_double()
+        g = (C.c_double * max(1, ntheta))()
+        check(self._lib.sun_adjoint_run(self.handle, _ptr(v0), _ptr(coef), ds, _ptr(dcoef), ntheta, _ptr(cobs),
+                                        float(dt), int(steps), int(S_avg), int(ckpt_every), C.byref(J), g,
+                                        _stream()))
+        return J.value, np.array(g[:ntheta])
+
+    def objective(self, v0, coef, cobs, dt, steps, S_avg):
+        J = C.c_double()
+        check(self._lib.sun_adjoint_objective(self.handle, _ptr(v0), _ptr(coef), _ptr(cobs), float(dt), int(steps),
+                                              int(S_avg), C.byref(J), _stream()))
+        return J.value
+
+
+class AdjointProblem:
+    """A parametrised propagation problem for the adjoint form.
+
+    lind       -- assembled terms T_a (fixed)
+    param_map  -- callable theta -> dict(static_w (nt,), dyn (list), coef
+                  (2*steps+1, ndyn) array, dstatic (nt, ntheta), dcoef
+                  (2*steps+1, ndyn, ntheta) array)
+    v0, cobs   -- device tensors (length M): initial Bloch vector and the
+                  observable's coefficients
+    """
+
+    def __init__(self, lind, param_map, v0, cobs, dt, steps, S_avg, ckpt_every):
+        self.lind = lind
+        self.param_map = param_map
+        self.v0 = v0.to("cuda", torch.float64).contiguous()
+        self.cobs = cobs.to("cuda", torch.float64).contiguous()
+        self.dt, self.steps, self.S_avg, self.ckpt_every = float(dt), int(steps), int(S_avg), int(ckpt_every)
+
+    def _setup(self, theta):
+        p = self.param_map(np.asarray(theta, dtype=np.float64))
+        adj = Adjoint(self.lind, p["static_w"], p["dyn"])
+        coef = torch.as_tensor(np.ascontiguousarray(p["coef"], dtype=np.float64)).cuda() if len(p["dyn"]) else None
+        dcoef = torch.as_tensor(np.ascontiguousarray(p["dcoef"], dtype=np.float64)).cuda() \
+            if len(p["dyn"]) and p.get("dcoef") is not None else None
+        return adj, coef, p["dstatic"], dcoef
+
+    def value_and_grad(self, theta):
+        adj, coef, dstatic, dcoef = self._setup(theta)
+        return adj.run(self.v0, coef, dstatic, dcoef, self.cobs, self.dt, self.steps, self.S_avg, self.ckpt_every)
+
+    def value(self, theta):
+        adj, coef, _, _ = self._setup(theta)
+        return adj.objective(self.v0, coef, self.cobs, self.dt, self.steps, self.S_avg)
+
+
+class SunBlochLoss(torch.autograd.Function):
+    """J(theta) of an AdjointProblem with the adjoint gradient as backward.
+
+        J = SunBlochLoss.apply(theta, problem);  J.backward()
+    """
+
+    @staticmethod
+    def forward(ctx, theta, problem):
+        J, g = problem.value_and_grad(theta.detach().cpu().numpy())
+        ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
+        return torch.tensor(J, dtype=theta.dtype, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return gout * g, None

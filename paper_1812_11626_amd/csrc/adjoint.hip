@@ -1,0 +1,433 @@
+// Discrete adjoint of the RK4 propagation (eq. 9; Sec. IV step 3.1) for the
+// gradient of a time-averaged observable
+//     J = (1/S) sum_{n = steps-S+1}^{steps} c . v_n
+// with respect to parameters theta on which the term coefficients depend:
+//     G(t) = sum_a c_a(t) T_a,  K(t) = sum_{a dissipator} c_a(t) K_a,
+//     c_a = w_a (static) or the table value c_d(t_k) (time-dependent term d),
+//     d c_a / d theta = dstatic[a][theta] or dcoef[k][d][theta].
+//
+// Reverse sweep of one step n (v' = v + dt/6 (k1 + 2k2 + 2k3 + k4)), with
+// lambda = dJ/dv_{n+1}:
+//     kb4 = dt/6 lambda,              xb4 = G(t_{n+1})^T kb4
+//     kb3 = dt/3 lambda + dt xb4,     xb3 = G(t_{n+1/2})^T kb3
+//     kb2 = dt/3 lambda + dt/2 xb3,   xb2 = G(t_{n+1/2})^T kb2
+//     kb1 = dt/6 lambda + dt/2 xb2,   xb1 = G(t_n)^T kb1
+//     lambda <- lambda + xb4 + xb3 + xb2 + xb1  (+ c/S where v_n enters J)
+//     grad   += sum_i sum_a dc_a/dtheta(t_i) kb_i . (T_a x_i + K_a)
+// where x_i are the forward stage inputs of step n.  The transposed
+// generator runs on the same fused stage kernels (a second propagator built
+// from the transposed terms, with the reverse-mode vector updates fused in).
+// States are checkpointed every `ckpt_every` steps in the forward sweep; the
+// backward sweep recomputes one checkpoint interval at a time.
+#include <algorithm>
+#include <vector>
+
+#include "prop_internal.hpp"
+
+using namespace sun;
+
+struct sun_adj_s {
+  const sun_lind_s* lind = nullptr;
+  sun_lind_s lindT;             // transposed terms, K = 0
+  sun_prop fwd = nullptr, bwd = nullptr;
+  std::vector<double> static_w;
+  std::vector<int> dyn;
+  int nt = 0, ndyn = 0;
+  int64_t M = 0;
+  ~sun_adj_s() {
+    if (fwd) sun_prop_free(fwd);
+    if (bwd) sun_prop_free(bwd);
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// CSR transpose (count, scan, scatter, per-row sort for a deterministic order)
+// ---------------------------------------------------------------------------
+__global__ void k_tr_count(int64_t M, const int* __restrict__ rowptr, const int* __restrict__ col,
+                           int64_t* __restrict__ cnt) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x)
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[col[e]]), 1ull);
+}
+
+__global__ void k_tr_fill(int64_t M, const int* __restrict__ rowptr, const int* __restrict__ col,
+                          const double* __restrict__ val, const int64_t* __restrict__ off, int* __restrict__ slot,
+                          int* __restrict__ tcol, double* __restrict__ tval) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x)
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      const int c = col[e];
+      const int k = atomicAdd(&slot[c], 1);
+      tcol[off[c] + k] = (int)r;
+      tval[off[c] + k] = val[e];
+    }
+}
+
+__global__ void k_tr_sort(int64_t M, const int64_t* __restrict__ off, const int64_t* __restrict__ cnt,
+                          int* __restrict__ tcol, double* __restrict__ tval, int* __restrict__ rowptr) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    int* c = tcol + off[r];
+    double* v = tval + off[r];
+    const int n = (int)cnt[r];
+    for (int i = 1; i < n; ++i) {
+      const int ci = c[i];
+      const double vi = v[i];
+      int j = i - 1;
+      while (j >= 0 && c[j] > ci) { c[j + 1] = c[j]; v[j + 1] = v[j]; --j; }
+      c[j + 1] = ci;
+      v[j + 1] = vi;
+    }
+    rowptr[r] = (int)off[r];
+    if (r == M - 1) rowptr[M] = (int)(off[r] + cnt[r]);
+  }
+}
+
+void transpose(const DevCSR& A, DevCSR& T, hipStream_t s) {
+  const int64_t M = A.rows;
+  DevBuf<int64_t> cnt(M), off(M);
+  DevBuf<int> slot(M);
+  HIP_OK(hipMemsetAsync(cnt.get(), 0, M * sizeof(int64_t), s));
+  HIP_OK(hipMemsetAsync(slot.get(), 0, M * sizeof(int), s));
+  hipLaunchKernelGGL(k_tr_count, dim3(grid_for(M, 256)), dim3(256), 0, s, M, A.rowptr.get(), A.col.get(), cnt.get());
+  HIP_LAUNCH_OK();
+  const int64_t nnz = exclusive_scan_i64(cnt.get(), off.get(), M, s);
+  T.rows = M;
+  T.nnz = nnz;
+  T.rowptr.alloc(M + 1);
+  T.col.alloc(nnz > 0 ? nnz : 1);
+  T.val.alloc(nnz > 0 ? nnz : 1);
+  hipLaunchKernelGGL(k_tr_fill, dim3(grid_for(M, 256)), dim3(256), 0, s, M, A.rowptr.get(), A.col.get(),
+                     A.val.get(), off.get(), slot.get(), T.col.get(), T.val.get());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_tr_sort, dim3(grid_for(M, 64)), dim3(64), 0, s, M, off.get(), cnt.get(), T.col.get(),
+                     T.val.get(), T.rowptr.get());
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Small vector kernels
+// ---------------------------------------------------------------------------
+__global__ void k_adj_prep(int64_t M, double* __restrict__ lam, const double* __restrict__ cobs, double cscale,
+                           double dt6, double* __restrict__ kb) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    double l = lam[i];
+    if (cscale != 0.0) l = l + cobs[i] * cscale;
+    lam[i] = l;
+    kb[i] = dt6 * l;
+  }
+}
+
+__global__ void k_adj_fill(int64_t n, double v, double* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+constexpr int kDotBlocks = 512;
+constexpr int kMaxTheta = 8;
+constexpr int kMaxGTerms = 8;
+
+struct DotTerms {
+  int n;                          // number of parameter-dependent terms
+  int term[kMaxGTerms];           // term index a
+  int dynslot[kMaxGTerms];        // d if the term is time dependent, else -1
+  const int* rowptr[kMaxGTerms];
+  const int* col[kMaxGTerms];
+  const double* val[kMaxGTerms];
+  const double* K[kMaxGTerms];
+};
+
+// partial[blk][j] = sum over this block's rows of kb[r] (T_j x + K_j)[r]
+__global__ __launch_bounds__(256) void k_dot_terms(int64_t M, DotTerms t, const double* __restrict__ kb,
+                                                   const double* __restrict__ x, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  for (int j = 0; j < t.n; ++j) {
+    double acc = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+      double s = 0.0;
+      for (int e = t.rowptr[j][r]; e < t.rowptr[j][r + 1]; ++e) s += t.val[j][e] * x[t.col[j][e]];
+      if (t.K[j]) s += t.K[j][r];
+      acc += kb[r] * s;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kMaxGTerms + j] = sh[0];
+    __syncthreads();
+  }
+}
+
+// grad[th] += sum_j dc_j/dth * sum_blk partial[blk][j], fixed order
+__global__ void k_grad_accumulate(DotTerms t, const double* __restrict__ partial, int nblk,
+                                  const double* __restrict__ dstatic /* [nt][ntheta] */,
+                                  const double* __restrict__ dcoef, int64_t krow, int ndyn, int ntheta,
+                                  double* __restrict__ grad) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int j = 0; j < t.n; ++j) {
+    double p = 0.0;
+    for (int b = 0; b < nblk; ++b) p += partial[(int64_t)b * kMaxGTerms + j];
+    for (int th = 0; th < ntheta; ++th) {
+      // a time-dependent term's coefficient is its static weight plus the
+      // table value; both may depend on theta
+      double dc = dstatic[t.term[j] * ntheta + th];
+      if (t.dynslot[j] >= 0 && dcoef) dc += dcoef[(krow * ndyn + t.dynslot[j]) * ntheta + th];
+      grad[th] += dc * p;
+    }
+  }
+}
+
+// out[0] += scale * dot(a, b) in a fixed order (two passes)
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_dot_finish(const double* __restrict__ part, int nblk, double scale, double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  out[0] += scale * s;
+}
+
+void dot_accumulate(const double* a, const double* b, int64_t n, double scale, double* part, double* out,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, n, a, b, part);
+  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(1), 0, s, part, kDotBlocks, scale, out);
+}
+
+// Forward RK4 step of the fused propagator: v (M+1) -> vout (M+1); x2/x3/x4
+// receive the stage inputs when non-NULL, else scratch buffers are used.
+void forward_step(const sun_prop_s& p, const double* v, double* vout, double* x2, double* x3, double* x4,
+                  double* acc, const double* coef, int64_t n, double dt, hipStream_t s) {
+  prop_stage(p, 0, v, v, acc, x2, coef, 2 * n, dt, s);
+  prop_stage(p, 1, x2, v, acc, x3, coef, 2 * n + 1, dt, s);
+  prop_stage(p, 2, x3, v, acc, x4, coef, 2 * n + 1, dt, s);
+  if (vout != v) HIP_OK(hipMemcpyAsync(vout, v, (p.M + 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  prop_stage(p, 3, x4, vout, acc, vout, coef, 2 * n + 2, dt, s);
+}
+
+}  // namespace
+
+extern "C" int sun_adjoint_create(sun_lind l, const double* static_w, const int32_t* dyn, int32_t ndyn,
+                                  void* stream, sun_adj* out) {
+  return guarded([&] {
+    SUN_REQUIRE(out != nullptr, SUN_EINVAL, "out is NULL");
+    *out = nullptr;
+    SUN_REQUIRE(l != nullptr && static_w != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(ndyn >= 0 && ndyn <= 1, SUN_ENOTSUP, "the adjoint supports at most one time-dependent term");
+    SUN_REQUIRE(ndyn == 0 || dyn != nullptr, SUN_EINVAL, "dyn is NULL");
+    const int nt = l->nH + l->P;
+    SUN_REQUIRE(nt <= kMaxGTerms, SUN_ENOTSUP, "at most 8 terms");
+    hipStream_t s = as_stream(stream);
+    auto a = new sun_adj_s();
+    try {
+      a->lind = l;
+      a->nt = nt;
+      a->ndyn = ndyn;
+      a->M = l->basis->M;
+      a->static_w.assign(static_w, static_w + nt);
+      a->dyn.assign(dyn, dyn + ndyn);
+      sun_lind_s& T = a->lindT;
+      T.basis = l->basis;
+      T.nH = l->nH;
+      T.P = l->P;
+      T.QH.resize(l->nH);
+      T.R.resize(l->P);
+      T.K.resize(l->P);
+      for (int h = 0; h < l->nH; ++h) transpose(l->QH[h], T.QH[h], s);
+      for (int p = 0; p < l->P; ++p) {
+        transpose(l->R[p], T.R[p], s);
+        T.K[p].alloc(a->M);
+        HIP_OK(hipMemsetAsync(T.K[p].get(), 0, a->M * sizeof(double), s));
+      }
+      int st = sun_prop_create(l, static_w, dyn, ndyn, stream, &a->fwd);
+      if (st != SUN_OK) SUN_THROW(st, std::string("forward propagator: ") + sun_last_error());
+      st = sun_prop_create(&a->lindT, static_w, dyn, ndyn, stream, &a->bwd);
+      if (st != SUN_OK) SUN_THROW(st, std::string("transposed propagator: ") + sun_last_error());
+      HIP_OK(hipStreamSynchronize(s));
+    } catch (...) {
+      delete a;
+      throw;
+    }
+    *out = a;
+  });
+}
+
+namespace {
+
+struct Work {
+  DevBuf<double> ck;        // checkpoints [(nck) * (M+1)]
+  DevBuf<double> per;       // states of one interval [(C+1) * (M+1)]
+  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb, kb2, part, dpart, dev_grad, dev_J, dstat;
+};
+
+}  // namespace
+
+extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, const double* dstatic,
+                               const double* dcoef, int32_t ntheta, const double* cobs, double dt, int64_t steps,
+                               int64_t S_avg, int64_t ckpt_every, double* J_out, double* grad_out, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(a != nullptr && v0 != nullptr && cobs != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(ntheta >= 0 && ntheta <= kMaxTheta, SUN_ENOTSUP, "at most 8 parameters");
+    SUN_REQUIRE(ntheta == 0 || dstatic != nullptr, SUN_EINVAL, "dstatic is NULL");
+    SUN_REQUIRE(a->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    SUN_REQUIRE(steps >= 1 && S_avg >= 1 && S_avg <= steps, SUN_EINVAL, "need 1 <= S_avg <= steps");
+    SUN_REQUIRE(ckpt_every >= 1, SUN_EINVAL, "ckpt_every must be >= 1");
+    SUN_REQUIRE(J_out != nullptr, SUN_EINVAL, "J_out is NULL");
+    hipStream_t s = as_stream(stream);
+    const sun_prop_s& F = *a->fwd;
+    const sun_prop_s& B = *a->bwd;
+    const int64_t M = a->M, M1 = M + 1;
+    const int64_t C = std::min(ckpt_every, steps);
+    const int64_t nck = (steps + C - 1) / C;           // checkpoints at n = 0, C, 2C, ...
+    Work w;
+    w.ck.alloc(nck * M1);
+    w.per.alloc((C + 1) * M1);
+    for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.acc, &w.lam, &w.lacc, &w.kb, &w.kb2}) b->alloc(M1);
+    w.part.alloc(kDotBlocks * kMaxGTerms);
+    w.dpart.alloc(kDotBlocks);
+    w.dev_grad.alloc(kMaxTheta);
+    w.dev_J.alloc(1);
+    w.dstat.alloc(a->nt * (ntheta > 0 ? ntheta : 1));
+    HIP_OK(hipMemsetAsync(w.dev_grad.get(), 0, kMaxTheta * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(w.dev_J.get(), 0, sizeof(double), s));
+    if (ntheta > 0)
+      HIP_OK(hipMemcpyAsync(w.dstat.get(), dstatic, a->nt * ntheta * sizeof(double), hipMemcpyHostToDevice, s));
+    for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.lam, &w.lacc, &w.kb, &w.kb2}) {
+      hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(M1, 256)), dim3(256), 0, s, M1, 0.0, b->get());
+      hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, b->get() + M);
+    }
+    HIP_LAUNCH_OK();
+    // ---- forward sweep with checkpoints --------------------------------------
+    double* cur = w.per.get();
+    double* nxt = w.per.get() + M1;
+    HIP_OK(hipMemcpyAsync(cur, v0, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, cur + M);
+    hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, nxt + M);
+    for (int64_t n = 0; n < steps; ++n) {
+      if (n % C == 0) HIP_OK(hipMemcpyAsync(w.ck.get() + (n / C) * M1, cur, M1 * sizeof(double),
+                                            hipMemcpyDeviceToDevice, s));
+      forward_step(F, cur, nxt, w.x2.get(), w.x3.get(), w.x4.get(), w.acc.get(), coef, n, dt, s);
+      std::swap(cur, nxt);
+    }
+    // ---- parameter-dependent terms ---------------------------------------
+    DotTerms dt_terms{};
+    {
+      std::vector<bool> used(a->nt, false);
+      for (int d = 0; d < a->ndyn; ++d) used[a->dyn[d]] = true;
+      for (int t = 0; t < a->nt; ++t)
+        for (int th = 0; th < ntheta; ++th)
+          if (dstatic[t * ntheta + th] != 0.0) used[t] = true;
+      const sun_lind_s* l = a->lind;
+      for (int t = 0; t < a->nt; ++t) {
+        if (!used[t]) continue;
+        const int j = dt_terms.n++;
+        const DevCSR& m = t < l->nH ? l->QH[t] : l->R[t - l->nH];
+        dt_terms.term[j] = t;
+        dt_terms.dynslot[j] = -1;
+        for (int d = 0; d < a->ndyn; ++d)
+          if (a->dyn[d] == t) dt_terms.dynslot[j] = d;
+        dt_terms.rowptr[j] = m.rowptr.get();
+        dt_terms.col[j] = m.col.get();
+        dt_terms.val[j] = m.val.get();
+        dt_terms.K[j] = t < l->nH ? nullptr : l->K[t - l->nH].get();
+      }
+      if (ntheta == 0) dt_terms.n = 0;
+    }
+    auto grad_stage = [&](const double* kbv, const double* x, int64_t krow) {
+      if (dt_terms.n == 0) return;
+      hipLaunchKernelGGL(k_dot_terms, dim3(kDotBlocks), dim3(256), 0, s, M, dt_terms, kbv, x, w.part.get());
+      hipLaunchKernelGGL(k_grad_accumulate, dim3(1), dim3(1), 0, s, dt_terms, w.part.get(), kDotBlocks,
+                         w.dstat.get(), dcoef, krow, a->ndyn, ntheta, w.dev_grad.get());
+    };
+    // ---- backward sweep -----------------------------------------------------
+    const int64_t first_avg = steps - S_avg + 1;      // J averages v_n for n >= first_avg
+    const double dt6 = dt / 6.0;
+    double* lam = w.lam.get();
+    double* lacc = w.lacc.get();
+    for (int64_t ci = nck - 1; ci >= 0; --ci) {
+      const int64_t n0 = ci * C, n1 = std::min(steps, n0 + C);
+      // recompute the states v_{n0} .. v_{n1} of this interval
+      double* P0 = w.per.get();
+      HIP_OK(hipMemcpyAsync(P0, w.ck.get() + ci * M1, M1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      for (int64_t n = n0; n < n1; ++n)
+        forward_step(F, P0 + (n - n0) * M1, P0 + (n + 1 - n0) * M1, w.x2.get(), w.x3.get(), w.x4.get(),
+                     w.acc.get(), coef, n, dt, s);
+      for (int64_t n = n1 - 1; n >= n0; --n) {
+        const double* vn = P0 + (n - n0) * M1;
+        const double* vn1 = P0 + (n + 1 - n0) * M1;
+        const bool in_avg = (n + 1) >= first_avg;
+        if (in_avg) dot_accumulate(cobs, vn1, M, 1.0 / (double)S_avg, w.dpart.get(), w.dev_J.get(), s);
+        // lambda += c/S (direct dependence of J on v_{n+1}); kb4 = dt/6 lambda
+        hipLaunchKernelGGL(k_adj_prep, dim3(grid_for(M, 256)), dim3(256), 0, s, M, lam, cobs,
+                           in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb.get());
+        // forward stage inputs of step n
+        prop_stage(F, 0, vn, vn, w.acc.get(), w.x2.get(), coef, 2 * n, dt, s);
+        prop_stage(F, 1, w.x2.get(), vn, w.acc.get(), w.x3.get(), coef, 2 * n + 1, dt, s);
+        prop_stage(F, 2, w.x3.get(), vn, w.acc.get(), w.x4.get(), coef, 2 * n + 1, dt, s);
+        // stage 4: kb4 with x4 at t_{n+1}
+        grad_stage(w.kb.get(), w.x4.get(), 2 * n + 2);
+        prop_stage(B, 4, w.kb.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 2, dt, s);   // kb2 <- kb3
+        grad_stage(w.kb2.get(), w.x3.get(), 2 * n + 1);
+        prop_stage(B, 5, w.kb2.get(), lam, lacc, w.kb.get(), coef, 2 * n + 1, dt, s);   // kb <- kb2
+        grad_stage(w.kb.get(), w.x2.get(), 2 * n + 1);
+        prop_stage(B, 6, w.kb.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 1, dt, s);   // kb2 <- kb1
+        grad_stage(w.kb2.get(), vn, 2 * n);
+        prop_stage(B, 7, w.kb2.get(), lam, lacc, nullptr, coef, 2 * n, dt, s);
+        std::swap(lam, lacc);
+      }
+    }
+    HIP_LAUNCH_OK();
+    double hg[kMaxTheta];
+    HIP_OK(hipMemcpyAsync(hg, w.dev_grad.get(), sizeof(hg), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(J_out, w.dev_J.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (grad_out)
+      for (int th = 0; th < ntheta; ++th) grad_out[th] = hg[th];
+  });
+}
+
+extern "C" int sun_adjoint_objective(sun_adj a, const double* v0, const double* coef, const double* cobs,
+                                     double dt, int64_t steps, int64_t S_avg, double* J_out, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(a != nullptr && v0 != nullptr && cobs != nullptr && J_out != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(a->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    SUN_REQUIRE(steps >= 1 && S_avg >= 1 && S_avg <= steps, SUN_EINVAL, "need 1 <= S_avg <= steps");
+    hipStream_t s = as_stream(stream);
+    const sun_prop_s& F = *a->fwd;
+    const int64_t M = a->M, M1 = M + 1;
+    DevBuf<double> v(M1), vn(M1), x2(M1), x3(M1), x4(M1), acc(M1), part(kDotBlocks), J(1);
+    for (DevBuf<double>* b : {&v, &vn, &x2, &x3, &x4}) {
+      hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(M1, 256)), dim3(256), 0, s, M1, 0.0, b->get());
+      hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, b->get() + M);
+    }
+    HIP_OK(hipMemsetAsync(J.get(), 0, sizeof(double), s));
+    HIP_OK(hipMemcpyAsync(v.get(), v0, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double* cur = v.get();
+    double* nxt = vn.get();
+    for (int64_t n = 0; n < steps; ++n) {
+      forward_step(F, cur, nxt, x2.get(), x3.get(), x4.get(), acc.get(), coef, n, dt, s);
+      std::swap(cur, nxt);
+      if (n + 1 >= steps - S_avg + 1) dot_accumulate(cobs, cur, M, 1.0 / (double)S_avg, part.get(), J.get(), s);
+    }
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(J_out, J.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" void sun_adjoint_free(sun_adj a) { delete a; }

@@ -1,0 +1,472 @@
+// Batched RK4 propagation: many parameter instances of the Bloch ODE
+// (eq. 9; Sec. IV step 3.1) advanced together, one launch per RK4 stage for
+// all instances of all groups.
+//
+// Instances are grouped by their assembled system (one sun_lind per group,
+// e.g. one group per Hilbert-space dimension N).  Instance b of group g has
+// the generator
+//     G_b(t) = sum_a c_{b,a}(t) T_a,   K_b(t) = sum_{a dissipator} c_{b,a}(t) K_a,
+//     c_{b,a}(t_k) = w[b][a] + u[b][a] * wave[k]
+// on the half-step grid t_k (k = 0..2*steps), which covers a drive
+// eps_b(t) = E + A_b cos(omega t) on one term and a per-instance rate gamma_b
+// on another.
+//
+// Layout.  Each group keeps one fused CSR whose row r lists the entries of
+// T_0 row r, then T_1 row r, ... (the free vector of a dissipator term as an
+// extra column M), with the segment boundaries per row.  The state of a
+// group is row-major [M+1][ld] with the instance index fastest (ld = number
+// of instances rounded up to the tile width), and X[M][b] = 1.  A wavefront
+// is split into 64/T lane groups of T lanes; each lane group handles one row
+// and T consecutive instances, so every nonzero's gather reads T contiguous
+// doubles of one state row, and the matrix row is read once per tile of T
+// instances.  Work items (group, block of rows, tile of instances) are
+// walked by a grid-stride loop of a fixed-size grid.
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace sun;
+
+namespace {
+
+constexpr int kMaxBTerms = 8;
+
+struct GroupDev {
+  const int* rowptr;     // [M+1]
+  const int* segptr;     // [M * nt]: start of segment a of row r at segptr[r * nt + a]
+  const int* col;
+  const double* val;
+  const double* w;       // [B * nt]
+  const double* u;       // [B * nt]
+  const double* wave;    // [2 * steps + 1]
+  double* v;             // [(M+1) * ld]
+  double* xa;
+  double* xb;
+  double* acc;           // [M * ld]
+  double dt;
+  int M, B, ld, nt, tile, rows_per_item;
+  int row_blocks, tiles;
+  int64_t item0;         // first work item of this group
+};
+
+}  // namespace
+
+struct sun_batch_s {
+  int ngroups = 0;
+  std::vector<const sun_lind_s*> lind;
+  std::vector<int> B, tile, rows_per_item;
+  std::vector<int64_t> M, nnz, steps, done;
+  std::vector<double> dt;
+  std::vector<const double*> w, u, wave;
+  std::vector<DevBuf<int>> rowptr, segptr, col;
+  std::vector<DevBuf<double>> val, v, xa, xb, acc;
+  std::vector<int> ld, nt;
+  DevBuf<GroupDev> gdev;
+  std::vector<GroupDev> ghost;
+  std::vector<int> order;   // groups sorted by decreasing remaining steps
+};
+
+namespace {
+
+// Fused per-term rows: count (mode 0) or fill (mode 1).
+struct TermPtrs {
+  int n;
+  const int* rowptr[kMaxBTerms];
+  const int* col[kMaxBTerms];
+  const double* val[kMaxBTerms];
+  const double* K[kMaxBTerms];
+};
+
+__global__ void k_batch_fuse(int64_t M, TermPtrs t, int mode, int64_t* __restrict__ cnt,
+                             const int64_t* __restrict__ off, int* __restrict__ segptr, int* __restrict__ col,
+                             double* __restrict__ val) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t w = mode ? off[r] : 0, n = 0;
+    for (int a = 0; a < t.n; ++a) {
+      if (mode) segptr[r * t.n + a] = (int)(w + n);
+      for (int e = t.rowptr[a][r]; e < t.rowptr[a][r + 1]; ++e) {
+        if (mode) { col[w + n] = t.col[a][e]; val[w + n] = t.val[a][e]; }
+        ++n;
+      }
+      if (t.K[a] && t.K[a][r] != 0.0) {
+        if (mode) { col[w + n] = (int)M; val[w + n] = t.K[a][r]; }
+        ++n;
+      }
+    }
+    if (!mode) cnt[r] = n;
+  }
+}
+
+__global__ void k_b_i64_to_i32(int64_t n, const int64_t* __restrict__ a, int64_t total, int* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (int)a[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) b[n] = (int)total;
+}
+
+// instance-major [B][M] <-> row-major [M+1][ld] (row M set to 1)
+__global__ void k_to_rowmajor(int M, int B, int ld, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t total = (int64_t)(M + 1) * ld;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(i / ld), b = (int)(i % ld);
+    dst[i] = (r == M) ? 1.0 : (b < B ? src[(int64_t)b * M + r] : 0.0);
+  }
+}
+
+__global__ void k_from_rowmajor(int M, int B, int ld, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t total = (int64_t)M * B;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(i / M), r = (int)(i % M);
+    dst[i] = src[(int64_t)r * ld + b];
+  }
+}
+
+__global__ void k_b_fill(int64_t n, double v, double* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// One RK4 stage for every active group.  stage_in/stage_out select the
+// buffers: stage 0 reads v writes xa, 1 reads xa writes xb, 2 reads xb writes
+// xa, 3 reads xa writes v.
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_batch_stage(const GroupDev* __restrict__ groups, const int* __restrict__ gorder,
+                                                     int nactive, int64_t nitems, const int64_t* __restrict__ step) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t it = __builtin_amdgcn_readfirstlane((int)wave0); it < nitems; it += nwaves) {
+    // locate the group of this item (few groups: linear scan over the active ones)
+    int gi = 0;
+    for (int q = 1; q < nactive; ++q)
+      if (groups[gorder[q]].item0 <= it) gi = q;
+    const GroupDev& G = groups[gorder[gi]];
+    const int64_t local = it - G.item0;
+    const int rb = (int)(local / G.tiles), tb = (int)(local % G.tiles);
+    const int T = G.tile;
+    const int sub = lane / T, bl = lane % T;
+    const int b = tb * T + bl;
+    const int nt = G.nt;
+    const int64_t k0 = 2 * step[gorder[gi]];
+    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+    const double ph = G.wave[k0 + krow];
+    double coefb[kMaxBTerms];
+#pragma unroll
+    for (int a = 0; a < kMaxBTerms; ++a)
+      coefb[a] = (a < nt && b < G.B) ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
+    const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
+    double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
+    const int rpw = 64 / T;   // rows handled side by side in one wavefront
+    const int r_begin = rb * G.rows_per_item;
+    const int r_end = min(G.M, r_begin + G.rows_per_item);
+    const int ld = G.ld;
+    for (int r = r_begin + sub; r < r_end; r += rpw) {
+      const int e_end = G.rowptr[r + 1];
+      double ysum = 0.0;
+      for (int a = 0; a < nt; ++a) {
+        const int s0 = G.segptr[(int64_t)r * nt + a];
+        const int s1 = (a + 1 < nt) ? G.segptr[(int64_t)r * nt + a + 1] : e_end;
+        double s = 0.0;
+        int e = s0;
+        for (; e + 4 <= s1; e += 4) {
+          const int c0 = G.col[e], c1 = G.col[e + 1], c2 = G.col[e + 2], c3 = G.col[e + 3];
+          const double v0 = G.val[e], v1 = G.val[e + 1], v2 = G.val[e + 2], v3 = G.val[e + 3];
+          const double x0 = xin[(int64_t)c0 * ld + b], x1 = xin[(int64_t)c1 * ld + b];
+          const double x2 = xin[(int64_t)c2 * ld + b], x3 = xin[(int64_t)c3 * ld + b];
+          s += v0 * x0;
+          s += v1 * x1;
+          s += v2 * x2;
+          s += v3 * x3;
+        }
+        for (; e < s1; ++e) s += G.val[e] * xin[(int64_t)G.col[e] * ld + b];
+        ysum += coefb[a] * s;
+      }
+      if (b < G.B) {
+        const int64_t ix = (int64_t)r * ld + b;
+        const double vr = G.v[ix];
+        const double dt = G.dt;
+        if (STAGE == 0) {
+          xout[ix] = vr + (0.5 * dt) * ysum;
+          G.acc[ix] = ysum;
+        } else if (STAGE == 1) {
+          xout[ix] = vr + (0.5 * dt) * ysum;
+          G.acc[ix] = G.acc[ix] + 2.0 * ysum;
+        } else if (STAGE == 2) {
+          xout[ix] = vr + dt * ysum;
+          G.acc[ix] = G.acc[ix] + 2.0 * ysum;
+        } else {
+          xout[ix] = vr + (dt / 6.0) * (G.acc[ix] + ysum);
+        }
+      }
+    }
+  }
+}
+
+void refresh_items(sun_batch_s& bt) {
+  int64_t item = 0;
+  for (int g = 0; g < bt.ngroups; ++g) {
+    GroupDev& G = bt.ghost[g];
+    G.tile = bt.tile[g];
+    G.rows_per_item = bt.rows_per_item[g];
+    G.ld = bt.ld[g];
+    G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
+    G.tiles = (G.B + G.tile - 1) / G.tile;
+  }
+  for (int gi : bt.order) {
+    GroupDev& G = bt.ghost[gi];
+    G.item0 = item;
+    item += (int64_t)G.row_blocks * G.tiles;
+  }
+}
+
+void upload(sun_batch_s& bt, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(bt.gdev.get(), bt.ghost.data(), bt.ngroups * sizeof(GroupDev), hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+void alloc_state(sun_batch_s& bt, int g, hipStream_t s) {
+  const int64_t M = bt.M[g];
+  const int ld = bt.ld[g];
+  bt.v[g].alloc((M + 1) * ld);
+  bt.xa[g].alloc((M + 1) * ld);
+  bt.xb[g].alloc((M + 1) * ld);
+  bt.acc[g].alloc(M * (int64_t)ld);
+  for (DevBuf<double>* p : {&bt.v[g], &bt.xa[g], &bt.xb[g]}) {
+    hipLaunchKernelGGL(k_b_fill, dim3(grid_for(M * ld, 256)), dim3(256), 0, s, M * (int64_t)ld, 0.0, p->get());
+    HIP_LAUNCH_OK();
+    hipLaunchKernelGGL(k_b_fill, dim3(grid_for(ld, 256)), dim3(256), 0, s, (int64_t)ld, 1.0, p->get() + M * ld);
+    HIP_LAUNCH_OK();
+  }
+  HIP_OK(hipMemsetAsync(bt.acc[g].get(), 0, M * ld * sizeof(double), s));
+  GroupDev& G = bt.ghost[g];
+  G.v = bt.v[g].get();
+  G.xa = bt.xa[g].get();
+  G.xb = bt.xb[g].get();
+  G.acc = bt.acc[g].get();
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int32_t* B, const double* const* w,
+                                const double* const* u, const double* const* wave, const double* dt,
+                                const int64_t* steps, void* stream, sun_batch* out) {
+  return guarded([&] {
+    SUN_REQUIRE(out != nullptr, SUN_EINVAL, "out is NULL");
+    *out = nullptr;
+    SUN_REQUIRE(ngroups >= 1 && lind && B && w && u && wave && dt && steps, SUN_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    auto bt = new sun_batch_s();
+    try {
+      bt->ngroups = ngroups;
+      bt->lind.resize(ngroups);
+      bt->B.resize(ngroups);
+      bt->tile.assign(ngroups, 64);
+      bt->rows_per_item.assign(ngroups, 64);
+      bt->M.resize(ngroups);
+      bt->nnz.resize(ngroups);
+      bt->steps.resize(ngroups);
+      bt->done.assign(ngroups, 0);
+      bt->dt.resize(ngroups);
+      bt->w.resize(ngroups);
+      bt->u.resize(ngroups);
+      bt->wave.resize(ngroups);
+      bt->rowptr.resize(ngroups);
+      bt->segptr.resize(ngroups);
+      bt->col.resize(ngroups);
+      bt->val.resize(ngroups);
+      bt->v.resize(ngroups);
+      bt->xa.resize(ngroups);
+      bt->xb.resize(ngroups);
+      bt->acc.resize(ngroups);
+      bt->ld.resize(ngroups);
+      bt->nt.resize(ngroups);
+      bt->ghost.resize(ngroups);
+      for (int g = 0; g < ngroups; ++g) {
+        const sun_lind_s* l = lind[g];
+        SUN_REQUIRE(l != nullptr, SUN_EINVAL, "group system is NULL");
+        SUN_REQUIRE(B[g] >= 1, SUN_EINVAL, "every group needs at least one instance");
+        SUN_REQUIRE(steps[g] >= 0 && dt[g] > 0.0, SUN_EINVAL, "steps must be >= 0 and dt > 0");
+        SUN_REQUIRE(w[g] && u[g] && wave[g], SUN_EINVAL, "coefficient arrays are NULL");
+        const int nt = l->nH + l->P;
+        SUN_REQUIRE(nt <= kMaxBTerms, SUN_ENOTSUP, "at most 8 terms per group");
+        bt->lind[g] = l;
+        bt->B[g] = B[g];
+        bt->M[g] = l->basis->M;
+        bt->steps[g] = steps[g];
+        bt->dt[g] = dt[g];
+        bt->w[g] = w[g];
+        bt->u[g] = u[g];
+        bt->wave[g] = wave[g];
+        bt->nt[g] = nt;
+        TermPtrs t{};
+        t.n = nt;
+        for (int a = 0; a < nt; ++a) {
+          const DevCSR& m = a < l->nH ? l->QH[a] : l->R[a - l->nH];
+          t.rowptr[a] = m.rowptr.get();
+          t.col[a] = m.col.get();
+          t.val[a] = m.val.get();
+          t.K[a] = a < l->nH ? nullptr : l->K[a - l->nH].get();
+        }
+        const int64_t M = bt->M[g];
+        DevBuf<int64_t> cnt(M), off(M);
+        hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, t, 0, cnt.get(), nullptr,
+                           nullptr, nullptr, nullptr);
+        HIP_LAUNCH_OK();
+        bt->nnz[g] = exclusive_scan_i64(cnt.get(), off.get(), M, s);
+        SUN_REQUIRE(bt->nnz[g] < (int64_t)INT32_MAX, SUN_ENOTSUP, "group matrix has 2^31 or more nonzeros");
+        bt->rowptr[g].alloc(M + 1);
+        bt->segptr[g].alloc(M * nt);
+        bt->col[g].alloc(bt->nnz[g] > 0 ? bt->nnz[g] : 1);
+        bt->val[g].alloc(bt->nnz[g] > 0 ? bt->nnz[g] : 1);
+        hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, t, 1, nullptr, off.get(),
+                           bt->segptr[g].get(), bt->col[g].get(), bt->val[g].get());
+        HIP_LAUNCH_OK();
+        hipLaunchKernelGGL(k_b_i64_to_i32, dim3(grid_for(M, 256)), dim3(256), 0, s, M, off.get(), bt->nnz[g],
+                           bt->rowptr[g].get());
+        HIP_LAUNCH_OK();
+        HIP_OK(hipStreamSynchronize(s));
+        bt->ld[g] = round_up(B[g], 64);
+        GroupDev& G = bt->ghost[g];
+        G = GroupDev{};
+        G.rowptr = bt->rowptr[g].get();
+        G.segptr = bt->segptr[g].get();
+        G.col = bt->col[g].get();
+        G.val = bt->val[g].get();
+        G.w = w[g];
+        G.u = u[g];
+        G.wave = wave[g];
+        G.dt = dt[g];
+        G.M = (int)M;
+        G.B = B[g];
+        G.nt = nt;
+        alloc_state(*bt, g, s);
+      }
+      bt->order.resize(ngroups);
+      for (int g = 0; g < ngroups; ++g) bt->order[g] = g;
+      bt->gdev.alloc(ngroups);
+      refresh_items(*bt);
+      upload(*bt, s);
+    } catch (...) {
+      delete bt;
+      throw;
+    }
+    *out = bt;
+  });
+}
+
+extern "C" int sun_batch_set_state(sun_batch bt, int32_t g, const double* V, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(bt != nullptr && V != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
+    hipStream_t s = as_stream(stream);
+    const int64_t total = (bt->M[g] + 1) * bt->ld[g];
+    hipLaunchKernelGGL(k_to_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g], bt->B[g],
+                       bt->ld[g], V, bt->v[g].get());
+    HIP_LAUNCH_OK();
+    bt->done[g] = 0;
+  });
+}
+
+extern "C" int sun_batch_get_state(sun_batch bt, int32_t g, double* V, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(bt != nullptr && V != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
+    hipStream_t s = as_stream(stream);
+    const int64_t total = bt->M[g] * bt->B[g];
+    hipLaunchKernelGGL(k_from_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g], bt->B[g],
+                       bt->ld[g], bt->v[g].get(), V);
+    HIP_LAUNCH_OK();
+  });
+}
+
+extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t rows_per_item, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
+    SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
+    SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64, SUN_EINVAL, "tile must be 8, 16, 32 or 64");
+    SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= 65536, SUN_EINVAL, "rows_per_item out of range");
+    hipStream_t s = as_stream(stream);
+    HIP_OK(hipStreamSynchronize(s));
+    bt->tile[g] = tile;
+    bt->rows_per_item[g] = rows_per_item;
+    refresh_items(*bt);
+    upload(*bt, s);
+  });
+}
+
+extern "C" int sun_batch_info(sun_batch bt, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,
+                              int32_t* rows_per_item) {
+  return guarded([&] {
+    SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
+    SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
+    if (M) *M = bt->M[g];
+    if (nnz) *nnz = bt->nnz[g];
+    if (tile) *tile = bt->tile[g];
+    if (rows_per_item) *rows_per_item = bt->rows_per_item[g];
+  });
+}
+
+extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
+    SUN_REQUIRE(nsteps >= 0, SUN_EINVAL, "nsteps must be >= 0");
+    SUN_REQUIRE(only_group >= -1 && only_group < bt->ngroups, SUN_EINVAL, "group index out of range");
+    hipStream_t s = as_stream(stream);
+    // per group: how many steps this call advances it
+    std::vector<int64_t> todo(bt->ngroups, 0);
+    for (int g = 0; g < bt->ngroups; ++g)
+      if (only_group < 0 || only_group == g) todo[g] = std::min(nsteps, bt->steps[g] - bt->done[g]);
+    std::vector<int> ord(bt->ngroups);
+    for (int g = 0; g < bt->ngroups; ++g) ord[g] = g;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return todo[a] > todo[b]; });
+    bt->order = ord;
+    refresh_items(*bt);
+    upload(*bt, s);
+    int64_t maxn = todo[ord[0]];
+    if (maxn <= 0) return;
+    // device copies: group order and per-group absolute step index
+    DevBuf<int> gorder(bt->ngroups);
+    DevBuf<int64_t> stepidx(bt->ngroups);
+    HIP_OK(hipMemcpyAsync(gorder.get(), ord.data(), bt->ngroups * sizeof(int), hipMemcpyHostToDevice, s));
+    // prefix sums of work items in launch order
+    std::vector<int64_t> items_upto(bt->ngroups + 1, 0);
+    for (int q = 0; q < bt->ngroups; ++q) {
+      const GroupDev& G = bt->ghost[ord[q]];
+      items_upto[q + 1] = items_upto[q] + (int64_t)G.row_blocks * G.tiles;
+    }
+    // the step index of every group lives in a device table: one row per step
+    std::vector<int64_t> table((size_t)maxn * bt->ngroups);
+    for (int64_t n = 0; n < maxn; ++n)
+      for (int g = 0; g < bt->ngroups; ++g) table[(size_t)n * bt->ngroups + g] = bt->done[g] + n;
+    DevBuf<int64_t> steptab(table.size());
+    HIP_OK(hipMemcpyAsync(steptab.get(), table.data(), table.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    int dev = 0, ncu = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int64_t n = 0; n < maxn; ++n) {
+      int nactive = 0;
+      while (nactive < bt->ngroups && todo[ord[nactive]] > n) ++nactive;
+      const int64_t nitems = items_upto[nactive];
+      const int64_t waves_needed = nitems;
+      int64_t grid = std::min<int64_t>((waves_needed + 3) / 4, (int64_t)ncu * 8);
+      if (grid < 1) grid = 1;
+      const int64_t* st = steptab.get() + n * bt->ngroups;
+      hipLaunchKernelGGL(k_batch_stage<0>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
+                         nactive, nitems, st);
+      hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
+                         nactive, nitems, st);
+      hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
+                         nactive, nitems, st);
+      hipLaunchKernelGGL(k_batch_stage<3>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
+                         nactive, nitems, st);
+    }
+    HIP_LAUNCH_OK();
+    for (int g = 0; g < bt->ngroups; ++g) bt->done[g] += todo[g];
+    // the step table and group order are freed on return
+    HIP_OK(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" void sun_batch_free(sun_batch bt) { delete bt; }

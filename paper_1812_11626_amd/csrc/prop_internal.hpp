@@ -1,0 +1,47 @@
+// Propagator object and stage launcher shared by the plain, profiled and
+// adjoint propagation entry points.
+#pragma once
+
+#include "internal.hpp"
+
+using sun::DevBuf;
+
+struct sun_prop_s {
+  const sun_lind_s* lind = nullptr;
+  int64_t M = 0;
+  int ndyn = 0;
+  int64_t nnz = 0;
+  DevBuf<int> rowptr, col, seg, blk_row;
+  DevBuf<double> val;
+  int64_t nblocks = 0;
+  int block_nnz = 1024;
+  int threads = 256;
+  int xcd_remap = 0;
+  DevBuf<double> vaug, xa, xb, acc;
+  // sliced-ELL layout (used when ndyn <= 1)
+  int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows
+  int sigma = 4096;          // rows sorted by length inside windows of sigma rows
+  int long_len = 64;         // rows longer than this use the wave-per-row path
+  int min_col_bytes = 1;     // narrowest column-delta width allowed (1, 2 or 4)
+  int64_t nshort = 0, nlong = 0, nslices = 0, sell_nnz = 0, sell_col_bytes = 0;
+  DevBuf<int> sell_row, sell_len, sell_off, sell_coff, sell_base, long_rows;
+  DevBuf<unsigned char> sell_cb;
+  DevBuf<double> sell_val;
+};
+
+namespace sun {
+
+// One launch of stage `stage` of the fused generator on the given vectors.
+// Forward RK4 stages 0..3 (see propagate.hip):
+//   k = G(t) xin;  0: xout = vin + dt/2 k, acc = k;  1: xout = vin + dt/2 k,
+//   acc += 2k;  2: xout = vin + dt k, acc += 2k;  3: xout = vin + dt/6 (acc + k).
+// Reverse-mode stages 4..7 (the propagator must hold the transposed
+// generator; vin = lambda, acc = lambda accumulator, xout = next cotangent):
+//   k = G(t)^T xin;  4: acc = vin + k, xout = dt/3 vin + dt k;
+//   5: acc += k, xout = dt/3 vin + dt/2 k;  6: acc += k, xout = dt/6 vin + dt/2 k;
+//   7: acc += k.
+// Vectors have M+1 entries with entry M equal to 1.
+void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
+                const double* coef, int64_t coef_row, double dt, hipStream_t s);
+
+}  // namespace sun

@@ -31,28 +31,8 @@
 
 using namespace sun;
 
-struct sun_prop_s {
-  const sun_lind_s* lind = nullptr;
-  int64_t M = 0;
-  int ndyn = 0;
-  int64_t nnz = 0;
-  DevBuf<int> rowptr, col, seg, blk_row;
-  DevBuf<double> val;
-  int64_t nblocks = 0;
-  int block_nnz = 1024;
-  int threads = 256;
-  int xcd_remap = 0;
-  DevBuf<double> vaug, xa, xb, acc;
-  // sliced-ELL layout (used when ndyn <= 1)
-  int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows
-  int sigma = 4096;          // rows sorted by length inside windows of sigma rows
-  int long_len = 64;         // rows longer than this use the wave-per-row path
-  int min_col_bytes = 1;     // narrowest column-delta width allowed (1, 2 or 4)
-  int64_t nshort = 0, nlong = 0, nslices = 0, sell_nnz = 0, sell_col_bytes = 0;
-  DevBuf<int> sell_row, sell_len, sell_off, sell_coff, sell_base, long_rows;
-  DevBuf<unsigned char> sell_cb;
-  DevBuf<double> sell_val;
-};
+#include "prop_internal.hpp"
+
 
 namespace {
 
@@ -153,20 +133,41 @@ __global__ void k_fill(int64_t n, double v, double* __restrict__ a) {
 // The fused stage kernel
 // ---------------------------------------------------------------------------
 template <int STAGE>
-__device__ inline void rk4_update(int r, double k, const double* v, double* acc, double* xout, double dt) {
-  const double vr = v[r];
+__device__ inline void stage_store(int r, double k, double vr, double ar, double* acc, double* xout, double dt) {
   if (STAGE == 0) {
     xout[r] = vr + (0.5 * dt) * k;
     acc[r] = k;
   } else if (STAGE == 1) {
     xout[r] = vr + (0.5 * dt) * k;
-    acc[r] = acc[r] + 2.0 * k;
+    acc[r] = ar + 2.0 * k;
   } else if (STAGE == 2) {
     xout[r] = vr + dt * k;
-    acc[r] = acc[r] + 2.0 * k;
+    acc[r] = ar + 2.0 * k;
+  } else if (STAGE == 3) {
+    xout[r] = vr + (dt / 6.0) * (ar + k);
+  } else if (STAGE == 4) {
+    acc[r] = vr + k;
+    xout[r] = (dt / 3.0) * vr + dt * k;
+  } else if (STAGE == 5) {
+    acc[r] = ar + k;
+    xout[r] = (dt / 3.0) * vr + (0.5 * dt) * k;
+  } else if (STAGE == 6) {
+    acc[r] = ar + k;
+    xout[r] = (dt / 6.0) * vr + (0.5 * dt) * k;
   } else {
-    xout[r] = vr + (dt / 6.0) * (acc[r] + k);
+    acc[r] = ar + k;
   }
+}
+
+// whether a stage reads the accumulator
+template <int STAGE>
+__device__ constexpr bool reads_acc() { return STAGE != 0 && STAGE != 4; }
+
+template <int STAGE>
+__device__ inline void rk4_update(int r, double k, const double* v, double* acc, double* xout, double dt) {
+  const double vr = v[r];
+  const double ar = reads_acc<STAGE>() ? acc[r] : 0.0;
+  stage_store<STAGE>(r, k, vr, ar, acc, xout, dt);
 }
 
 template <int STAGE, int NT>
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(NT) void k_rk4_stage(
       rz = rowptr[rr + 1];
       rs = ndyn ? seg[rr] : rz;
       vr = v[rr];
-      if (STAGE != 0) ar = acc[rr];
+      if (reads_acc<STAGE>()) ar = acc[rr];
     }
     // phase 1: stream the block's nonzeros, kIt per lane per round, with all
     // index/value loads issued before the dependent gathers
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_rk4_stage(
         rz = rowptr[r + 1];
         rs = ndyn ? seg[r] : rz;
         vr = v[r];
-        if (STAGE != 0) ar = acc[r];
+        if (reads_acc<STAGE>()) ar = acc[r];
       }
       int send = rs - e0;
       const int z = rz - e0;
@@ -245,18 +246,7 @@ __global__ __launch_bounds__(NT) void k_rk4_stage(
         for (int i = s0; i < send; ++i) sd += prod[i];
         k += eps[d] * sd;
       }
-      if (STAGE == 0) {
-        xout[r] = vr + (0.5 * dt) * k;
-        acc[r] = k;
-      } else if (STAGE == 1) {
-        xout[r] = vr + (0.5 * dt) * k;
-        acc[r] = ar + 2.0 * k;
-      } else if (STAGE == 2) {
-        xout[r] = vr + dt * k;
-        acc[r] = ar + 2.0 * k;
-      } else {
-        xout[r] = vr + (dt / 6.0) * (ar + k);
-      }
+      stage_store<STAGE>(r, k, vr, ar, acc, xout, dt);
     }
   } else {
     // rows too long for the LDS buffer: the whole workgroup reduces one row
@@ -454,22 +444,6 @@ __global__ void k_pack_cols(int64_t nslices, const int* __restrict__ sell_off, c
   }
 }
 
-template <int STAGE>
-__device__ inline void stage_store(int r, double k, double vr, double ar, double* acc, double* xout, double dt) {
-  if (STAGE == 0) {
-    xout[r] = vr + (0.5 * dt) * k;
-    acc[r] = k;
-  } else if (STAGE == 1) {
-    xout[r] = vr + (0.5 * dt) * k;
-    acc[r] = ar + 2.0 * k;
-  } else if (STAGE == 2) {
-    xout[r] = vr + dt * k;
-    acc[r] = ar + 2.0 * k;
-  } else {
-    xout[r] = vr + (dt / 6.0) * (ar + k);
-  }
-}
-
 template <class T>
 __device__ inline int load_delta(const unsigned char* p, int64_t e) {
   return (int)__builtin_nontemporal_load(reinterpret_cast<const T*>(p) + e);
@@ -554,7 +528,7 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     double vr = 0.0, ar = 0.0;
     if (own) {
       vr = v[r];
-      if (STAGE != 0) ar = acc[r];
+      if (reads_acc<STAGE>()) ar = acc[r];
     }
     const unsigned char* cb = cb_all + (coff & ~63);
     const int* gbase = gbase_all + off / kSlice;
@@ -582,7 +556,7 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     }
     if (lane == 0) {
       const double vr = v[r];
-      const double ar = STAGE != 0 ? acc[r] : 0.0;
+      const double ar = reads_acc<STAGE>() ? acc[r] : 0.0;
       stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
     }
   }
@@ -681,19 +655,18 @@ int stage_capacity(int block_nnz, int threads) {
 }
 
 template <int STAGE, int NT>
-void launch_stage_nt(const sun_prop_s& p, const double* xin, double* xout, const double* coef, int64_t row,
-                     double dt, hipStream_t s) {
+void launch_stage_nt(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                     const double* coef, int64_t row, double dt, hipStream_t s) {
   const int cap = stage_capacity(p.block_nnz, NT);
   const int grid = p.xcd_remap ? (int)(((p.nblocks + 7) / 8) * 8) : (int)p.nblocks;
   hipLaunchKernelGGL((k_rk4_stage<STAGE, NT>), dim3(grid), dim3(NT), cap * sizeof(double), s,
                      p.rowptr.get(), p.seg.get(), p.ndyn, p.col.get(), p.val.get(), p.blk_row.get(),
-                     (int)p.nblocks, p.xcd_remap, cap, xin, p.vaug.get(), p.acc.get(), xout, coef, row, dt,
-                     (int)p.M);
+                     (int)p.nblocks, p.xcd_remap, cap, xin, vin, acc, xout, coef, row, dt, (int)p.M);
 }
 
 template <int STAGE>
-void launch_stage(const sun_prop_s& p, const double* xin, double* xout, const double* coef, int64_t row,
-                  double dt, hipStream_t s) {
+void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                    const double* coef, int64_t row, double dt, hipStream_t s) {
   if (p.layout == 1) {
     const int64_t waves = p.nslices + p.nlong;
     const unsigned grid = (unsigned)((waves + 3) / 4);
@@ -701,17 +674,42 @@ void launch_stage(const sun_prop_s& p, const double* xin, double* xout, const do
                        p.sell_base.get(), p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_val.get(),
                        p.nslices, p.nshort,
                        p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(), p.val.get(), p.ndyn,
-                       xin, p.vaug.get(), p.acc.get(), xout, coef, row, dt);
+                       xin, vin, acc, xout, coef, row, dt);
     return;
   }
   switch (p.threads) {
-    case 64: launch_stage_nt<STAGE, 64>(p, xin, xout, coef, row, dt, s); break;
-    case 128: launch_stage_nt<STAGE, 128>(p, xin, xout, coef, row, dt, s); break;
-    default: launch_stage_nt<STAGE, 256>(p, xin, xout, coef, row, dt, s); break;
+    case 64: launch_stage_nt<STAGE, 64>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 128: launch_stage_nt<STAGE, 128>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    default: launch_stage_nt<STAGE, 256>(p, xin, vin, acc, xout, coef, row, dt, s); break;
   }
 }
 
+template <int STAGE>
+void launch_stage(const sun_prop_s& p, const double* xin, double* xout, const double* coef, int64_t row,
+                  double dt, hipStream_t s) {
+  launch_stage_v<STAGE>(p, xin, p.vaug.get(), p.acc.get(), xout, coef, row, dt, s);
+}
+
 }  // namespace
+
+namespace sun {
+
+void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
+                const double* coef, int64_t row, double dt, hipStream_t s) {
+  switch (stage) {
+    case 0: launch_stage_v<0>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 1: launch_stage_v<1>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 2: launch_stage_v<2>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 3: launch_stage_v<3>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 4: launch_stage_v<4>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 5: launch_stage_v<5>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 6: launch_stage_v<6>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    default: launch_stage_v<7>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+  }
+  HIP_LAUNCH_OK();
+}
+
+}  // namespace sun
 
 extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t* dyn, int32_t ndyn,
                                void* stream, sun_prop* out) {

@@ -26,3 +26,71 @@ def rel_vec_err(a, b):
 
 def flush(msg):
     print(msg, flush=True)
+
+
+def dimer_batch(sb, instances, steps=None):
+    """Group dimer instances by N and build a BatchedPropagator over the terms
+    [H0, H1, L] with c = (1, E + A_b cos(omega t), gamma_b).  Returns
+    (bp, groups) with groups = [(N, [instance indices], lind, dt, steps)]."""
+    import numpy as np
+    from workloads import dimer
+    byN = {}
+    for i, p in enumerate(instances):
+        byN.setdefault(p.N, []).append(i)
+    specs, groups = [], []
+    for N in sorted(byN):
+        idx = byN[N]
+        p0 = instances[idx[0]]
+        ops = dimer.dimer_operators(p0)
+        basis = sb.build_basis(N)
+        lind = sb.Lindbladian(basis, [ops["H0"], ops["H1"]], [ops["L"]])
+        st = p0.steps if steps is None else (steps[N] if isinstance(steps, dict) else steps)
+        w = np.array([[1.0, instances[i].E, instances[i].gamma_eff] for i in idx])
+        u = np.array([[0.0, instances[i].A, 0.0] for i in idx])
+        wave = dimer.drive_table_dA(p0, steps=st)
+        specs.append(dict(lind=lind, w=w, u=u, wave=wave, dt=p0.dt, steps=st))
+        groups.append((N, idx, lind, p0.dt, st))
+    return sb.BatchedPropagator(specs), groups
+
+
+def fock_bloch(N, i=0):
+    """Bloch vector of |i><i| (oracle-side construction, tests only)."""
+    import numpy as np
+    from oracle import lindblad as lb
+    rho = np.zeros((N, N), complex)
+    rho[i, i] = 1
+    return lb.bloch_vector_sparse(rho)
+
+
+def dimer_adjoint_problem(sb, p, steps, S_avg, ckpt_every):
+    """AdjointProblem for the dimer with theta = (A, gamma, U): terms
+    [H_J, H_U, H1] and [L], coefficients (-J, U U_scale, E + A cos(omega t),
+    gamma gamma_scale).  Returns (problem, lind, basis)."""
+    import copy
+    import numpy as np
+    import torch
+    from workloads import dimer
+    ops = dimer.dimer_operators(p)
+    N = p.N
+    basis = sb.build_basis(N)
+    lind = sb.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
+    e0 = np.zeros(N)
+    e0[p.rho0_index] = 1.0
+    v0 = basis.expand(dimer.ZCSR.from_diagonals(N, {0: e0}))[0].real.contiguous()
+    cobs = basis.expand(ops["H1"])[0].real.contiguous()
+
+    def pmap(theta):
+        A, g, U = (float(x) for x in theta)
+        q = copy.copy(p)
+        q.A = A
+        coef = dimer.drive_table(q, steps=steps)[:, None]
+        dcoef = np.zeros((2 * steps + 1, 1, 3))
+        dcoef[:, 0, 0] = dimer.drive_table_dA(q, steps=steps)
+        static_w = [-p.J, U * p.U_scale, 0.0, g * p.gamma_scale]
+        dstatic = np.zeros((4, 3))
+        dstatic[1, 2] = p.U_scale
+        dstatic[3, 1] = p.gamma_scale
+        return dict(static_w=static_w, dyn=[2], coef=coef, dstatic=dstatic, dcoef=dcoef)
+
+    prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S_avg, ckpt_every)
+    return prob, lind, basis

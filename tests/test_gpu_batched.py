@@ -1,0 +1,109 @@
+"""Batched form: many (A, gamma, N) instances in one launch per RK4 stage.
+
+Every instance must match, to 1e-12 relative, the oracle's RK4 on its own
+generator (dense tier, small N) or the plain GPU propagation of that
+instance (the 512-instance workload, sampled), and the result must not
+depend on the tiling.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import dimer_batch, flush, fock_bloch, rel_vec_err
+from oracle import basis as ob, lindblad as lb, propagate as pr
+from workloads import dimer
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _small_instances():
+    out = []
+    rng = np.random.default_rng(77)
+    for N, cnt in ((4, 3), (5, 2)):
+        for _ in range(cnt):
+            p = dimer.plain_config(N)
+            p.A = float(rng.uniform(0.5, 3.0))
+            p.gamma = float(rng.uniform(0.05, 0.5))
+            p.steps_per_period = 200 if N == 4 else 300
+            out.append(p)
+    return out
+
+
+def _oracle_instance(p, steps, v0):
+    ops = dimer.dimer_operators(p)
+    F = ob.generators(p.N)
+    G0 = lb.q_hamiltonian(F, ops["H0"].to_dense()) + p.gamma_eff * lb.q_dissipator(F, ops["L"].to_dense())
+    G1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    K = p.gamma_eff * lb.k_dissipator(F, ops["L"].to_dense())
+    eps = dimer.drive_table(p, steps=steps)
+    return pr.rk4_bloch(G0, [G1], K, v0, eps[:, None], p.dt, steps)
+
+
+def test_small_groups_against_dense_oracle(lib):
+    flush("[batched] small groups vs oracle")
+    inst = _small_instances()
+    steps = {4: 60, 5: 40}
+    bp, groups = dimer_batch(lib, inst, steps)
+    for g, (N, idx, _, _, _) in enumerate(groups):
+        V = np.stack([fock_bloch(N, i % N) for i in range(len(idx))])
+        bp.set_state(g, torch.as_tensor(V))
+    bp.run(1000)        # every group stops at its own step count
+    for g, (N, idx, _, _, st) in enumerate(groups):
+        got = bp.get_state(g).cpu().numpy()
+        for j, i in enumerate(idx):
+            want = _oracle_instance(inst[i], st, fock_bloch(N, j % N))
+            assert rel_vec_err(got[j], want) <= TOL, (N, j)
+
+
+def test_tiling_does_not_change_results(lib):
+    flush("[batched] tiling invariance")
+    inst = _small_instances()
+    bp, groups = dimer_batch(lib, inst, {4: 30, 5: 30})
+    starts = [torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))) for (N, idx, _, _, _) in groups]
+    results = []
+    for tile, rows in ((64, 64), (8, 1), (16, 7), (32, 512)):
+        for g in range(len(groups)):
+            bp.tune(g, tile, rows)
+            bp.set_state(g, starts[g])
+        bp.run(30)
+        results.append([bp.get_state(g).cpu().numpy() for g in range(len(groups))])
+    for r in results[1:]:
+        for a, b in zip(r, results[0]):
+            assert np.array_equal(a, b)
+
+
+def test_full_workload_sampled_against_plain(lib):
+    """The 512-instance workload (N in {51,...,301}), 24 steps, 3 sampled
+    instances per group against plain single-instance GPU propagation."""
+    flush("[batched] 512 instances vs plain (sampled)")
+    inst = dimer.batched_instances()
+    assert len(inst) == 512
+    steps = 24
+    bp, groups = dimer_batch(lib, inst, steps)
+    for g, (N, idx, _, _, _) in enumerate(groups):
+        bp.set_state(g, torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))))
+    bp.run(steps)
+    for g, (N, idx, lind, dt, st) in enumerate(groups):
+        got = bp.get_state(g).cpu().numpy()
+        for j in (0, len(idx) // 2, len(idx) - 1):
+            p = inst[idx[j]]
+            prop = lind.propagator([1.0, 0.0, p.gamma_eff], [1])
+            v = torch.as_tensor(fock_bloch(N, 0)).cuda()
+            eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+            prop.propagate(v, eps, dt, steps)
+            assert rel_vec_err(got[j], v.cpu().numpy()) <= TOL, (N, j)
+
+
+def test_autotuner_picks_valid_tiling(lib, tmp_path, monkeypatch):
+    monkeypatch.setenv("SUN_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    inst = _small_instances()
+    bp, groups = dimer_batch(lib, inst, {4: 20, 5: 20})
+    chosen = lib.autotune_batched(bp, probe_steps=2)
+    for g in range(len(groups)):
+        info = bp.info(g)
+        assert info["tile"] == chosen[g]["tile"] and info["rows_per_item"] == chosen[g]["rows_per_item"]
+    again = lib.autotune_batched(bp)
+    assert all(c["cached"] for c in again.values())
