@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block-nnz", type=int, default=0)
     ap.add_argument("--threads", type=int, default=256)
+    ap.add_argument("--pmc-mode", action="store_true",
+                    help="short run for rocprofv3 --pmc (stage kernel + calibration copy)")
     return ap.parse_args()
 
 
@@ -85,6 +87,144 @@ def cpu_baseline(p, ops, budget_s=12.0):
                       f"(scipy sparse x dense, single thread), {el:.1f} s"}
 
 
+def _fock_v0(sb, basis, N, i=0):
+    from workloads import dimer
+    e = np.zeros(N)
+    e[i] = 1.0
+    return basis.expand(dimer.ZCSR.from_diagonals(N, {0: e}))[0].real.contiguous()
+
+
+def batched_report(sb, torch, steps=200):
+    """Batched form: the 512-instance dimer workload (N in {51,...,301},
+    A ~ U[0.5,3], gamma ~ logU[0.01,0.5]), one launch per RK4 stage for all
+    instances, autotuned tiles; against sequential plain solves."""
+    from workloads import dimer
+    inst = dimer.batched_instances()
+    byN = {}
+    for i, p in enumerate(inst):
+        byN.setdefault(p.N, []).append(i)
+    specs, meta = [], []
+    t0 = time.perf_counter()
+    for N in sorted(byN):
+        idx = byN[N]
+        p0 = inst[idx[0]]
+        ops = dimer.dimer_operators(p0)
+        basis = sb.build_basis(N)
+        lind = sb.Lindbladian(basis, [ops["H0"], ops["H1"]], [ops["L"]])
+        w = np.array([[1.0, inst[i].E, inst[i].gamma_eff] for i in idx])
+        u = np.array([[0.0, inst[i].A, 0.0] for i in idx])
+        specs.append(dict(lind=lind, w=w, u=u, wave=dimer.drive_table_dA(p0), dt=p0.dt, steps=p0.steps))
+        meta.append((N, idx, basis, lind, p0))
+    bp = sb.BatchedPropagator(specs)
+    for g, (N, idx, basis, lind, p0) in enumerate(meta):
+        v0 = _fock_v0(sb, basis, N)
+        bp.set_state(g, v0.unsqueeze(0).repeat(len(idx), 1))
+    setup_s = time.perf_counter() - t0
+    tuned = sb.autotune_batched(bp, probe_steps=4, log=log)
+    bp.run(2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bp.run(steps)
+    el = time.perf_counter() - t1
+    inst_steps = sum(len(idx) * steps for (_, idx, _, _, _) in meta)
+    batched_rate = inst_steps / el
+    # sequential plain solves: per-step time of one plain instance per N
+    seq_time = 0.0
+    per_N = {}
+    for g, (N, idx, basis, lind, p0) in enumerate(meta):
+        p = inst[idx[0]]
+        prop = lind.propagator([1.0, 0.0, p.gamma_eff], [1])
+        v = _fock_v0(sb, basis, N)
+        nst = 200
+        eps = torch.as_tensor(dimer.drive_table(p, steps=nst)).cuda().contiguous()
+        prop.propagate(v, eps, p.dt, 20)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        prop.propagate(v, eps, p.dt, nst)
+        torch.cuda.synchronize()
+        tstep = (time.perf_counter() - ta) / nst
+        per_N[N] = {"instances": len(idx), "steps_per_period": p0.steps_per_period, "plain_us_per_step": 1e6 * tstep,
+                    "tile": tuned[g]["tile"], "rows_per_item": tuned[g]["rows_per_item"]}
+        seq_time += len(idx) * tstep
+    seq_rate = sum(len(idx) for (_, idx, _, _, _) in meta) / seq_time
+    total_20T = sum(len(idx) * p0.steps for (_, idx, _, _, p0) in meta)
+    log(f"batched: {batched_rate:.0f} instance-steps/s vs sequential plain {seq_rate:.0f}")
+    return {"workload": "dimer-batched-512 (N in {51,101,151,201,301}, A~U[0.5,3], gamma~logU[0.01,0.5]/N)",
+            "instances": len(inst), "steps_timed_per_group": steps,
+            "instance_steps_per_s": batched_rate, "ms_per_step_all_groups": 1e3 * el / steps,
+            "sequential_plain_instance_steps_per_s": seq_rate, "speedup_vs_sequential_plain": batched_rate / seq_rate,
+            "groups": per_N, "setup_s": setup_s,
+            "full_20_periods_instance_steps": total_20T,
+            "full_20_periods_estimated_s": total_20T / batched_rate}
+
+
+def adjoint_report(sb, torch, periods=2):
+    """Adjoint form at N = 301: d<n1-n2>_(last period)/d(A, gamma, U) by the
+    discrete adjoint; time of gradient / time of the forward objective."""
+    import copy
+    from workloads import dimer
+    p = dimer.adjoint_config(301)
+    steps = periods * p.steps_per_period
+    S = p.steps_per_period
+    ops = dimer.dimer_operators(p)
+    basis = sb.build_basis(p.N)
+    lind = sb.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
+    v0 = _fock_v0(sb, basis, p.N)
+    cobs = basis.expand(ops["H1"])[0].real.contiguous()
+
+    def pmap(theta):
+        A, g, U = (float(x) for x in theta)
+        q = copy.copy(p)
+        q.A = A
+        dcoef = np.zeros((2 * steps + 1, 1, 3))
+        dcoef[:, 0, 0] = dimer.drive_table_dA(q, steps=steps)
+        dstatic = np.zeros((4, 3))
+        dstatic[1, 2] = p.U_scale
+        dstatic[3, 1] = p.gamma_scale
+        return dict(static_w=[-p.J, U * p.U_scale, 0.0, g * p.gamma_scale], dyn=[2],
+                    coef=dimer.drive_table(q, steps=steps)[:, None], dstatic=dstatic, dcoef=dcoef)
+
+    prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S, ckpt_every=S)
+    theta = np.array([p.A, p.gamma, p.U])
+    adj, coef, dstatic, dcoef = prob._setup(theta)
+    adj.objective(prob.v0, coef, prob.cobs, p.dt, 16, 8)       # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J_f = adj.objective(prob.v0, coef, prob.cobs, p.dt, steps, S)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J, g = adj.run(prob.v0, coef, dstatic, dcoef, prob.cobs, p.dt, steps, S, S)
+    t_grad = time.perf_counter() - t0
+    log(f"adjoint N=301: forward {t_fwd:.2f} s, gradient {t_grad:.2f} s, ratio {t_grad/t_fwd:.2f}")
+    return {"workload": f"dimer-adjoint-N301 ({periods} periods x {p.steps_per_period} steps, "
+                        f"loss = <n1-n2> averaged over the last period, theta = (A, gamma, U))",
+            "steps": steps, "J": J, "J_forward_only": J_f, "grad": {"A": g[0], "gamma": g[1], "U": g[2]},
+            "forward_s": t_fwd, "gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
+            "forward_steps_per_s": steps / t_fwd,
+            "full_100_periods_estimated_gradient_s": t_grad * (100 / periods)}
+
+
+def pmc_mode(sb, torch, steps):
+    """Short run for hardware-counter collection: the stage kernel on the
+    N = 1001 workload, then a plain 512 MiB device copy (known size) that
+    calibrates the byte counters."""
+    from workloads import dimer
+    p = dimer.plain_config(1001)
+    ops = dimer.dimer_operators(p)
+    basis = sb.build_basis(1001)
+    lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+    v = _fock_v0(sb, basis, 1001)
+    eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+    prop.propagate(v, eps, p.dt, steps)
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_mode": True, "steps": steps, "copy_bytes_read": a.numel() * 8,
+                      "copy_bytes_written": b.numel() * 8, "layout": prop.layout()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -96,6 +236,9 @@ def main():
     from workloads import dimer
 
     sb.require_gpu()
+    if args.pmc_mode:
+        pmc_mode(sb, torch, min(args.steps, 20))
+        return
     N = args.N
     p = dimer.plain_config(N)
     ops = dimer.dimer_operators(p)
@@ -114,6 +257,7 @@ def main():
     t2 = time.perf_counter()
     if args.block_nnz:
         prop.tune(args.block_nnz, args.threads, False)
+    layout = prop.layout()
     rho0 = np.zeros((N, N), complex)
     rho0[0, 0] = 1.0
     v0, _ = basis.expand(sb.DeviceOperator.from_csr(
@@ -151,7 +295,11 @@ def main():
     nnz_u = union_nnz(lind, torch)
     bytes_per_launch = 12 * nnz_u + 4 * (M + 1) + 20 * M
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    layout_bytes = 12 * info["nnz_fused"] + 4 * (M + 1) + 4 * M + 48 * M
+    # bytes the layout really streams per launch: matrix + per-row metadata
+    # (+ the long rows' CSR entries) and the row-wise vectors
+    layout_bytes = layout["matrix_bytes_per_launch"] + 12 * (info["nnz_fused"] - layout["stored_entries"]) \
+        if layout["layout"] == "sliced" else layout["matrix_bytes_per_launch"]
+    layout_bytes += 48 * M
     log(f"stage avg {avg_launch_s*1e6:.2f} us, union nnz {nnz_u}, achieved {achieved:.0f} GB/s")
 
     out = {
@@ -175,15 +323,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_rk4_stage", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches_timed": launches,
-                     "layout_bytes_per_launch": layout_bytes},
+                     "layout_bytes_per_launch_est": layout_bytes, "layout": layout},
         "assembly_ms": {"build_basis": 1e3 * (t1 - t0), "expand_lindbladian_and_layout": 1e3 * (t2 - t1),
                         "v0": 1e3 * (t3 - t2)},
         "state_finite": finite,
     }
 
     # ---- batched and adjoint forms, reported against plain -----------------
-    out["batched"] = None
-    out["adjoint"] = None
+    out["batched"] = None if args.no_batched else batched_report(sb, torch)
+    out["adjoint"] = None if args.no_adjoint else adjoint_report(sb, torch)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -208,10 +208,10 @@ class Propagator:
         check(self._lib.sun_prop_tune(self.handle, int(block_nnz), int(threads), int(bool(xcd_remap)),
                                       _stream()))
 
-    def tune_sliced(self, sigma: int = 1024, long_len: int = 64, min_col_bytes: int = 1):
+    def tune_sliced(self, sigma: int = 4096, long_len: int = 64, min_col_bytes: int = 1, xcd_remap: bool = True):
         """Select the sliced-ELL layout with these knobs."""
         check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes),
-                                             _stream()))
+                                             int(bool(xcd_remap)), _stream()))
 
     def layout(self):
         lay, stored, nlong, nb = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -119,12 +119,20 @@ __global__ void k_adj_prep(int64_t M, double* __restrict__ lam, const double* __
   }
 }
 
+// a[i * stride + off] = v for i < n (sets the constant entry x[M] = 1 of
+// vectors stored back to back)
+__global__ void k_adj_fill_strided(int64_t n, int64_t stride, int64_t off, double v, double* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i * stride + off] = v;
+}
+
 __global__ void k_adj_fill(int64_t n, double v, double* __restrict__ a) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
 }
 
 constexpr int kDotBlocks = 512;
+constexpr int kTermDotBlocks = 8192;
 constexpr int kMaxTheta = 8;
 constexpr int kMaxGTerms = 8;
 
@@ -138,44 +146,72 @@ struct DotTerms {
   const double* K[kMaxGTerms];
 };
 
-// partial[blk][j] = sum over this block's rows of kb[r] (T_j x + K_j)[r]
+// partial[j][blk] = sum over this block's rows of kb[r] (T_j x + K_j)[r];
+// blockIdx.y selects the term j.  Groups of 4 lanes take one row each
+// (adjacent reads of the row, then a fixed shuffle tree).
+constexpr int kRowLanes = 4;
+
 __global__ __launch_bounds__(256) void k_dot_terms(int64_t M, DotTerms t, const double* __restrict__ kb,
                                                    const double* __restrict__ x, double* __restrict__ partial) {
   __shared__ double sh[256];
-  for (int j = 0; j < t.n; ++j) {
-    double acc = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
-      double s = 0.0;
-      for (int e = t.rowptr[j][r]; e < t.rowptr[j][r + 1]; ++e) s += t.val[j][e] * x[t.col[j][e]];
-      if (t.K[j]) s += t.K[j][r];
-      acc += kb[r] * s;
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kMaxGTerms + j] = sh[0];
+  const int j = blockIdx.y;
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / kRowLanes;
+  const int* __restrict__ rp = t.rowptr[j];
+  const int* __restrict__ cl = t.col[j];
+  const double* __restrict__ vl = t.val[j];
+  const double* __restrict__ Kj = t.K[j];
+  double acc = 0.0;
+  for (int64_t r = grp; r < M; r += ngrp) {
+    double s = 0.0;
+    for (int e = rp[r] + sub; e < rp[r + 1]; e += kRowLanes) s += vl[e] * x[cl[e]];
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kRowLanes);
+    if (Kj) s += Kj[r];
+    acc += (sub == 0) ? kb[r] * s : 0.0;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
+  if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = sh[0];
 }
 
-// grad[th] += sum_j dc_j/dth * sum_blk partial[blk][j], fixed order
-__global__ void k_grad_accumulate(DotTerms t, const double* __restrict__ partial, int nblk,
-                                  const double* __restrict__ dstatic /* [nt][ntheta] */,
-                                  const double* __restrict__ dcoef, int64_t krow, int ndyn, int ntheta,
-                                  double* __restrict__ grad) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+
+// Sum of n partials by one workgroup in a fixed order (strided per lane,
+// then a tree), result in sh[0] of lane 0.
+__device__ inline double block_sum_fixed(const double* __restrict__ part, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// grad[th] += sum_j dc_j/dth * sum_blk partial[j][blk], in a fixed order
+__global__ __launch_bounds__(256) void k_grad_accumulate(DotTerms t, const double* __restrict__ partial, int nblk,
+                                                         const double* __restrict__ dstatic,
+                                                         const double* __restrict__ dcoef, int64_t krow, int ndyn,
+                                                         int ntheta, double* __restrict__ grad) {
+  __shared__ double sh[256];
   for (int j = 0; j < t.n; ++j) {
-    double p = 0.0;
-    for (int b = 0; b < nblk; ++b) p += partial[(int64_t)b * kMaxGTerms + j];
-    for (int th = 0; th < ntheta; ++th) {
-      // a time-dependent term's coefficient is its static weight plus the
-      // table value; both may depend on theta
-      double dc = dstatic[t.term[j] * ntheta + th];
-      if (t.dynslot[j] >= 0 && dcoef) dc += dcoef[(krow * ndyn + t.dynslot[j]) * ntheta + th];
-      grad[th] += dc * p;
+    const double p = block_sum_fixed(partial + (int64_t)j * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+      for (int th = 0; th < ntheta; ++th) {
+        // a time-dependent term's coefficient is its static weight plus the
+        // table value; both may depend on theta
+        double dc = dstatic[t.term[j] * ntheta + th];
+        if (t.dynslot[j] >= 0 && dcoef) dc += dcoef[(krow * ndyn + t.dynslot[j]) * ntheta + th];
+        grad[th] += dc * p;
+      }
     }
   }
 }
@@ -196,17 +232,20 @@ __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double* __
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_dot_finish(const double* __restrict__ part, int nblk, double scale, double* __restrict__ out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b];
-  out[0] += scale * s;
+__global__ __launch_bounds__(256) void k_dot_finish(const double* __restrict__ part, int nblk, double scale,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[256];
+  const double s = block_sum_fixed(part, nblk, sh);
+  if (threadIdx.x == 0) out[0] += scale * s;
 }
+
+int dot_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 255) / 256)); }
 
 void dot_accumulate(const double* a, const double* b, int64_t n, double scale, double* part, double* out,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, n, a, b, part);
-  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(1), 0, s, part, kDotBlocks, scale, out);
+  const int nb = dot_blocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, a, b, part);
+  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(256), 0, s, part, nb, scale, out);
 }
 
 // Forward RK4 step of the fused propagator: v (M+1) -> vout (M+1); x2/x3/x4
@@ -216,8 +255,7 @@ void forward_step(const sun_prop_s& p, const double* v, double* vout, double* x2
   prop_stage(p, 0, v, v, acc, x2, coef, 2 * n, dt, s);
   prop_stage(p, 1, x2, v, acc, x3, coef, 2 * n + 1, dt, s);
   prop_stage(p, 2, x3, v, acc, x4, coef, 2 * n + 1, dt, s);
-  if (vout != v) HIP_OK(hipMemcpyAsync(vout, v, (p.M + 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  prop_stage(p, 3, x4, vout, acc, vout, coef, 2 * n + 2, dt, s);
+  prop_stage(p, 3, x4, v, acc, vout, coef, 2 * n + 2, dt, s);   // vout[M] must already be 1
 }
 
 }  // namespace
@@ -269,9 +307,14 @@ extern "C" int sun_adjoint_create(sun_lind l, const double* static_w, const int3
 
 namespace {
 
+// Stage inputs x2, x3, x4 of a whole checkpoint interval are kept when they
+// need at most this many bytes; otherwise they are recomputed per step.
+constexpr double kStageStoreBytes = 24.0 * (1ull << 30);
+
 struct Work {
   DevBuf<double> ck;        // checkpoints [(nck) * (M+1)]
   DevBuf<double> per;       // states of one interval [(C+1) * (M+1)]
+  DevBuf<double> stg;       // stage inputs of one interval [C][3][M+1] (optional)
   DevBuf<double> x2, x3, x4, acc, lam, lacc, kb, kb2, part, dpart, dev_grad, dev_J, dstat;
 };
 
@@ -297,8 +340,18 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     Work w;
     w.ck.alloc(nck * M1);
     w.per.alloc((C + 1) * M1);
+    hipLaunchKernelGGL(k_adj_fill_strided, dim3(grid_for(C + 1, 256)), dim3(256), 0, s, C + 1, M1, M, 1.0,
+                       w.per.get());
+    HIP_LAUNCH_OK();
+    const bool keep_stages = 3.0 * (double)C * (double)M1 * 8.0 <= kStageStoreBytes;
+    if (keep_stages) {
+      w.stg.alloc(3 * C * M1);
+      hipLaunchKernelGGL(k_adj_fill_strided, dim3(grid_for(3 * C, 256)), dim3(256), 0, s, 3 * C, M1, M, 1.0,
+                         w.stg.get());
+      HIP_LAUNCH_OK();
+    }
     for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.acc, &w.lam, &w.lacc, &w.kb, &w.kb2}) b->alloc(M1);
-    w.part.alloc(kDotBlocks * kMaxGTerms);
+    w.part.alloc((int64_t)kTermDotBlocks * kMaxGTerms);
     w.dpart.alloc(kDotBlocks);
     w.dev_grad.alloc(kMaxTheta);
     w.dev_J.alloc(1);
@@ -348,11 +401,13 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
       }
       if (ntheta == 0) dt_terms.n = 0;
     }
+    // 64 rows in flight per workgroup, at most 1024 workgroups per term
+    const int nbd = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M + 63) / 64));
     auto grad_stage = [&](const double* kbv, const double* x, int64_t krow) {
       if (dt_terms.n == 0) return;
-      hipLaunchKernelGGL(k_dot_terms, dim3(kDotBlocks), dim3(256), 0, s, M, dt_terms, kbv, x, w.part.get());
-      hipLaunchKernelGGL(k_grad_accumulate, dim3(1), dim3(1), 0, s, dt_terms, w.part.get(), kDotBlocks,
-                         w.dstat.get(), dcoef, krow, a->ndyn, ntheta, w.dev_grad.get());
+      hipLaunchKernelGGL(k_dot_terms, dim3(nbd, dt_terms.n), dim3(256), 0, s, M, dt_terms, kbv, x, w.part.get());
+      hipLaunchKernelGGL(k_grad_accumulate, dim3(1), dim3(256), 0, s, dt_terms, w.part.get(), nbd, w.dstat.get(),
+                         dcoef, krow, a->ndyn, ntheta, w.dev_grad.get());
     };
     // ---- backward sweep -----------------------------------------------------
     const int64_t first_avg = steps - S_avg + 1;      // J averages v_n for n >= first_avg
@@ -364,9 +419,11 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
       // recompute the states v_{n0} .. v_{n1} of this interval
       double* P0 = w.per.get();
       HIP_OK(hipMemcpyAsync(P0, w.ck.get() + ci * M1, M1 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      for (int64_t n = n0; n < n1; ++n)
-        forward_step(F, P0 + (n - n0) * M1, P0 + (n + 1 - n0) * M1, w.x2.get(), w.x3.get(), w.x4.get(),
-                     w.acc.get(), coef, n, dt, s);
+      for (int64_t n = n0; n < n1; ++n) {
+        double* sx = keep_stages ? w.stg.get() + 3 * (n - n0) * M1 : nullptr;
+        forward_step(F, P0 + (n - n0) * M1, P0 + (n + 1 - n0) * M1, sx ? sx : w.x2.get(),
+                     sx ? sx + M1 : w.x3.get(), sx ? sx + 2 * M1 : w.x4.get(), w.acc.get(), coef, n, dt, s);
+      }
       for (int64_t n = n1 - 1; n >= n0; --n) {
         const double* vn = P0 + (n - n0) * M1;
         const double* vn1 = P0 + (n + 1 - n0) * M1;
@@ -375,16 +432,24 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
         // lambda += c/S (direct dependence of J on v_{n+1}); kb4 = dt/6 lambda
         hipLaunchKernelGGL(k_adj_prep, dim3(grid_for(M, 256)), dim3(256), 0, s, M, lam, cobs,
                            in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb.get());
-        // forward stage inputs of step n
-        prop_stage(F, 0, vn, vn, w.acc.get(), w.x2.get(), coef, 2 * n, dt, s);
-        prop_stage(F, 1, w.x2.get(), vn, w.acc.get(), w.x3.get(), coef, 2 * n + 1, dt, s);
-        prop_stage(F, 2, w.x3.get(), vn, w.acc.get(), w.x4.get(), coef, 2 * n + 1, dt, s);
+        // forward stage inputs of step n (kept from the interval recompute,
+        // or recomputed here)
+        const double *x2 = w.x2.get(), *x3 = w.x3.get(), *x4 = w.x4.get();
+        if (keep_stages) {
+          x2 = w.stg.get() + 3 * (n - n0) * M1;
+          x3 = x2 + M1;
+          x4 = x2 + 2 * M1;
+        } else {
+          prop_stage(F, 0, vn, vn, w.acc.get(), w.x2.get(), coef, 2 * n, dt, s);
+          prop_stage(F, 1, w.x2.get(), vn, w.acc.get(), w.x3.get(), coef, 2 * n + 1, dt, s);
+          prop_stage(F, 2, w.x3.get(), vn, w.acc.get(), w.x4.get(), coef, 2 * n + 1, dt, s);
+        }
         // stage 4: kb4 with x4 at t_{n+1}
-        grad_stage(w.kb.get(), w.x4.get(), 2 * n + 2);
+        grad_stage(w.kb.get(), x4, 2 * n + 2);
         prop_stage(B, 4, w.kb.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 2, dt, s);   // kb2 <- kb3
-        grad_stage(w.kb2.get(), w.x3.get(), 2 * n + 1);
+        grad_stage(w.kb2.get(), x3, 2 * n + 1);
         prop_stage(B, 5, w.kb2.get(), lam, lacc, w.kb.get(), coef, 2 * n + 1, dt, s);   // kb <- kb2
-        grad_stage(w.kb.get(), w.x2.get(), 2 * n + 1);
+        grad_stage(w.kb.get(), x2, 2 * n + 1);
         prop_stage(B, 6, w.kb.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 1, dt, s);   // kb2 <- kb1
         grad_stage(w.kb2.get(), vn, 2 * n);
         prop_stage(B, 7, w.kb2.get(), lam, lacc, nullptr, coef, 2 * n, dt, s);

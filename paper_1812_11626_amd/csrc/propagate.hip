@@ -510,11 +510,19 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     const int* __restrict__ long_rows, int64_t nlong, const int* __restrict__ rowptr, const int* __restrict__ seg,
     const int* __restrict__ col, const double* __restrict__ val, int ndyn,
     const double* __restrict__ xin, const double* v, double* acc, double* xout,
-    const double* __restrict__ coef, int64_t coef_row, double dt) {
+    const double* __restrict__ coef, int64_t coef_row, double dt, int xcd_remap) {
   const int lane = threadIdx.x & 63;
+  // Workgroups are dispatched round-robin over the 8 XCDs; with xcd_remap
+  // each XCD takes one contiguous range of slices, so the x entries its
+  // rows gather stay in that XCD's L2.
+  int64_t blk = blockIdx.x;
+  if (xcd_remap) {
+    const int64_t q = ((int64_t)gridDim.x + 7) >> 3;
+    blk = (blk & 7) * q + (blk >> 3);
+  }
   // wavefront index, made explicitly uniform so that slice metadata become
   // scalar loads and width tests scalar branches
-  const int64_t wid = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double eps = ndyn ? coef[coef_row] : 0.0;
   if (wid < nslices) {
     const int64_t i = wid * kSlice + lane;
@@ -669,12 +677,13 @@ void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, d
                     const double* coef, int64_t row, double dt, hipStream_t s) {
   if (p.layout == 1) {
     const int64_t waves = p.nslices + p.nlong;
-    const unsigned grid = (unsigned)((waves + 3) / 4);
+    unsigned grid = (unsigned)((waves + 3) / 4);
+    if (p.sell_remap) grid = (grid + 7) / 8 * 8;
     hipLaunchKernelGGL((k_rk4_sell<STAGE, 8>), dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
                        p.sell_base.get(), p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_val.get(),
                        p.nslices, p.nshort,
                        p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(), p.val.get(), p.ndyn,
-                       xin, vin, acc, xout, coef, row, dt);
+                       xin, vin, acc, xout, coef, row, dt, p.sell_remap);
     return;
   }
   switch (p.threads) {
@@ -812,7 +821,7 @@ extern "C" int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int
 }
 
 extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,
-                                    void* stream) {
+                                    int32_t xcd_remap, void* stream) {
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
     SUN_REQUIRE(p->ndyn <= 1, SUN_ENOTSUP, "the sliced layout supports at most one time-dependent term");
@@ -824,6 +833,7 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     p->sigma = sigma;
     p->long_len = long_len;
     p->min_col_bytes = min_col_bytes;
+    p->sell_remap = xcd_remap ? 1 : 0;
     p->layout = 1;
     build_sell(*p, as_stream(stream));
   });

@@ -196,14 +196,15 @@ def test_sliced_layout_matches_stream_layout(lib):
     ref = v0.clone()
     prop.propagate(ref, eps, p.dt, 300)
     ref = ref.cpu().numpy()
-    for sigma, long_len, cb in ((1024, 64, 1), (1024, 64, 4), (64, 8, 2), (4096, 1, 1), (256, 4096, 1)):
-        prop.tune_sliced(sigma, long_len, cb)
+    for sigma, long_len, cb, rm in ((1024, 64, 1, 1), (1024, 64, 4, 0), (64, 8, 2, 1), (4096, 1, 1, 0),
+                                    (256, 4096, 1, 1)):
+        prop.tune_sliced(sigma, long_len, cb, rm)
         v = v0.clone()
         prop.propagate(v, eps, p.dt, 300)
         assert rel_vec_err(v.cpu().numpy(), ref) <= 1e-14, (sigma, long_len, cb)
     a = v0.clone()
     b = v0.clone()
-    prop.tune_sliced(1024, 64)
+    prop.tune_sliced(1024, 64, 1, 1)
     prop.propagate(a, eps, p.dt, 300)
     prop.propagate(b, eps, p.dt, 300)
     assert torch.equal(a, b)
