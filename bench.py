@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block-nnz", type=int, default=0)
     ap.add_argument("--threads", type=int, default=256)
+    ap.add_argument("--only", choices=("plain", "batched", "adjoint"), default=None,
+                    help="run one leg only (for profiling); prints that leg's report")
     ap.add_argument("--pmc-mode", action="store_true",
                     help="short run for rocprofv3 --pmc (stage kernel + calibration copy)")
     return ap.parse_args()
@@ -64,6 +66,36 @@ def union_nnz(lind, torch):
         rows = torch.repeat_interleave(torch.arange(M, device="cuda"), rowptr[1:] - rowptr[:-1])
         keys.append(rows * M + col)
     return int(torch.unique(torch.cat(keys)).numel())
+
+
+STAGE_SOURCES = ("paper_1812_11626_amd/csrc/propagate.hip", "paper_1812_11626_amd/csrc/prop_internal.hpp")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_rk4_sell_dimer-plain-N1001_counters.md")
+
+
+def stage_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in STAGE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from the committed counter summary, if it
+    was taken on the current stage-kernel source (else None)."""
+    try:
+        fields = {}
+        with open(COUNTER_SUMMARY) as fh:
+            for line in fh:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+        if fields.get("source_sha256") != stage_source_hash():
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(p, ops, budget_s=12.0):
@@ -239,6 +271,12 @@ def main():
     if args.pmc_mode:
         pmc_mode(sb, torch, min(args.steps, 20))
         return
+    if args.only == "batched":
+        print(json.dumps(batched_report(sb, torch)), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(adjoint_report(sb, torch, periods=1)), flush=True)
+        return
     N = args.N
     p = dimer.plain_config(N)
     ops = dimer.dimer_operators(p)
@@ -320,7 +358,7 @@ def main():
                    "dt": p.dt, "U_eff": p.U_eff, "gamma_eff": p.gamma_eff, "A": p.A, "E": p.E,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_rk4_stage", "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches_timed": launches,
                      "layout_bytes_per_launch_est": layout_bytes, "layout": layout},

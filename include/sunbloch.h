@@ -186,8 +186,9 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  * long_len in [1, 4096]; ndyn <= 1 only).  In layout 1 the column index of
  * each stored entry is kept as an offset from a per-(slice, entry) base, in
  * 1, 2 or 4 bytes per slice, the narrowest that fits; min_col_bytes (1, 2, 4)
- * bounds that width from below (4 = uncompressed); xcd_remap gives each XCD
- * one contiguous range of slices.  Defaults 1024/256/0 and 4096/64/1/1. */
+ * bounds that width from below (4 = uncompressed); xcd_remap bit 0 gives each
+ * XCD one contiguous range of slices, bit 1 reads the matrix stream with
+ * ordinary (cached) instead of non-temporal loads.  Defaults 1024/256/0 and 4096/64/1/1. */
 int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
                   void* stream);
 int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,

@@ -444,14 +444,20 @@ __global__ void k_pack_cols(int64_t nslices, const int* __restrict__ sell_off, c
   }
 }
 
-template <class T>
+template <bool NTL, class X>
+__device__ inline X stream_load(const X* p) {
+  if constexpr (NTL) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <class T, bool NTL>
 __device__ inline int load_delta(const unsigned char* p, int64_t e) {
-  return (int)__builtin_nontemporal_load(reinterpret_cast<const T*>(p) + e);
+  return (int)stream_load<NTL>(reinterpret_cast<const T*>(p) + e);
 }
 
 // Sum of one lane's row over a slice whose column deltas are of type T.
 // wd, cb, gbase and vp - lane are wavefront-uniform.
-template <class T, int U>
+template <class T, int U, bool NTL>
 __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restrict__ gbase,
                                      const double* __restrict__ vp, int wd, int lane, int slen, int len,
                                      const double* __restrict__ xin, double& a0, double& a1) {
@@ -464,8 +470,8 @@ __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restr
     double cv[U], xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ci[u] = gbase[k + u] + load_delta<T>(cb, (int64_t)(k + u) * kSlice + lane);
-      cv[u] = __builtin_nontemporal_load(vp + (int64_t)(k + u) * kSlice);
+      ci[u] = gbase[k + u] + load_delta<T, NTL>(cb, (int64_t)(k + u) * kSlice + lane);
+      cv[u] = stream_load<NTL>(vp + (int64_t)(k + u) * kSlice);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) xv[u] = xin[ci[u]];
@@ -484,8 +490,8 @@ __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restr
 #pragma unroll
       for (int u = 0; u < R; ++u) {
         const bool in = k + u < wd;   // uniform
-        ci[u] = in ? gbase[k + u] + load_delta<T>(cb, (int64_t)(k + u) * kSlice + lane) : gbase[0];
-        cv[u] = in ? __builtin_nontemporal_load(vp + (int64_t)(k + u) * kSlice) : 0.0;
+        ci[u] = in ? gbase[k + u] + load_delta<T, NTL>(cb, (int64_t)(k + u) * kSlice + lane) : gbase[0];
+        cv[u] = in ? stream_load<NTL>(vp + (int64_t)(k + u) * kSlice) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < R; ++u) xv[u] = xin[ci[u]];
@@ -502,7 +508,7 @@ __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restr
 }
 
 // One wavefront per slice (or per long row).  Workgroups of 4 wavefronts.
-template <int STAGE, int U>
+template <int STAGE, int U, bool NTL>
 __global__ __launch_bounds__(256) void k_rk4_sell(
     const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
     const unsigned char* __restrict__ cb_all, const int* __restrict__ sell_row, const int* __restrict__ sell_len,
@@ -543,9 +549,9 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     const double* vp = sval + off + lane;
     double a0 = 0.0, a1 = 0.0;
     switch (coff & 3) {
-      case 0: slice_row_sum<uint8_t, U>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      case 1: slice_row_sum<uint16_t, U>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      default: slice_row_sum<uint32_t, U>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
     }
     if (own) stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
   } else if (wid < nslices + nlong) {
@@ -679,11 +685,11 @@ void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, d
     const int64_t waves = p.nslices + p.nlong;
     unsigned grid = (unsigned)((waves + 3) / 4);
     if (p.sell_remap) grid = (grid + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_rk4_sell<STAGE, 8>), dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
+    auto kern = p.sell_temporal ? k_rk4_sell<STAGE, 8, false> : k_rk4_sell<STAGE, 8, true>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
                        p.sell_base.get(), p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_val.get(),
-                       p.nslices, p.nshort,
-                       p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(), p.val.get(), p.ndyn,
-                       xin, vin, acc, xout, coef, row, dt, p.sell_remap);
+                       p.nslices, p.nshort, p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(),
+                       p.val.get(), p.ndyn, xin, vin, acc, xout, coef, row, dt, p.sell_remap);
     return;
   }
   switch (p.threads) {
@@ -833,7 +839,8 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     p->sigma = sigma;
     p->long_len = long_len;
     p->min_col_bytes = min_col_bytes;
-    p->sell_remap = xcd_remap ? 1 : 0;
+    p->sell_remap = (xcd_remap & 1) ? 1 : 0;
+    p->sell_temporal = (xcd_remap & 2) ? 1 : 0;
     p->layout = 1;
     build_sell(*p, as_stream(stream));
   });
