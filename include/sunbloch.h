@@ -123,8 +123,11 @@ enum { SUN_TERM_H = 0, SUN_TERM_L = 1 };
  * |q| <= 1e-12 max|Q| are removed.
  * H terms must be Hermitian (checked to 1e-12 max|H|, else SUN_EINVAL) and
  * L operators traceless (|Tr L| <= 1e-12 max|L|, else SUN_ENOTSUP).
- * Limits: every assembled row must have at most 8192 raw contributions
- * (else SUN_ENOTSUP); total nnz of each matrix < 2^31.
+ * Limits: every assembled row must have at most 16384 raw contributions
+ * (8192 on devices with less than 160 KB of LDS per workgroup; else
+ * SUN_ENOTSUP, detected from the per-row counts before any fill); total nnz
+ * of each matrix < 2^31.  Sparse operators (the dimer: <= 5N per row) are
+ * far inside the limit; dense L beyond N ~ 30 is not.
  * Synchronises `stream` (sizes are read back).  */
 int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH,
                            const sun_zcsr* L, int32_t P, void* stream,

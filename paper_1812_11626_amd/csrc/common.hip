@@ -131,6 +131,36 @@ __global__ __launch_bounds__(256) void k_sum_partial(const int64_t* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+__global__ __launch_bounds__(256) void k_maxi_partial(const int64_t* __restrict__ in, int64_t n,
+                                                      int64_t* __restrict__ part) {
+  __shared__ int64_t sh[256];
+  int64_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = in[i] > m ? in[i] : m;
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o && sh[threadIdx.x + o] > sh[threadIdx.x]) sh[threadIdx.x] = sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+int64_t device_max_i64(const int64_t* in, int64_t n, hipStream_t s) {
+  if (n <= 0) return 0;
+  const int nb = 512;
+  DevBuf<int64_t> part(nb), fin(1);
+  hipLaunchKernelGGL(k_maxi_partial, dim3(nb), dim3(256), 0, s, in, n, part.get());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_maxi_partial, dim3(1), dim3(256), 0, s, part.get(), (int64_t)nb, fin.get());
+  HIP_LAUNCH_OK();
+  int64_t r = 0;
+  HIP_OK(hipMemcpyAsync(&r, fin.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return r;
+}
+
 int64_t device_sum_i64(const int64_t* in, int64_t n, hipStream_t s) {
   if (n <= 0) return 0;
   const int nb = 512;

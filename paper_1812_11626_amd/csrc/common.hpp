@@ -131,6 +131,9 @@ int64_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream
 // max over a double array (non-negative values), result on host.
 double device_max(const double* in, int64_t n, hipStream_t s);
 
+// Max of a non-negative int64 array, result on host.
+int64_t device_max_i64(const int64_t* in, int64_t n, hipStream_t s);
+
 // Sum of an int64 array, result on host.
 int64_t device_sum_i64(const int64_t* in, int64_t n, hipStream_t s);
 

@@ -241,6 +241,13 @@ RowAssemblyResult assemble_rows(const G& g, int64_t rows, double rel_drop, bool 
   hipLaunchKernelGGL((k_rows_count<G, V>), dim3(grid_for(rows, 256)), dim3(256), 0, s, g, rows,
                      cnt.get());
   HIP_LAUNCH_OK();
+  const int cap = row_capacity();
+  res.max_row_raw = device_max_i64(cnt.get(), rows, s);
+  if (res.max_row_raw > cap) {
+    SUN_THROW(SUN_ENOTSUP, "a row has " + std::to_string(res.max_row_raw) +
+                               " raw contributions, more than the LDS sort holds (" + std::to_string(cap) +
+                               "); operator too dense for this build");
+  }
   res.raw = exclusive_scan_i64(cnt.get(), off.get(), rows, s);
   DevBuf<uint64_t> key(res.raw > 0 ? res.raw : 1), mkey(res.raw > 0 ? res.raw : 1);
   DevBuf<V> rval(res.raw > 0 ? res.raw : 1), mval(res.raw > 0 ? res.raw : 1);
@@ -251,7 +258,6 @@ RowAssemblyResult assemble_rows(const G& g, int64_t rows, double rel_drop, bool 
   HIP_LAUNCH_OK();
   DevBuf<int64_t> mcnt(rows);
   DevBuf<double> rowmax(rows);
-  const int cap = row_capacity();
   unsigned sgrid = (unsigned)(rows < 65536 ? rows : 65536);
   hipLaunchKernelGGL((k_rows_sort_merge<V>), dim3(sgrid), dim3(SORT_THREADS),
                      cap * sizeof(uint64_t), s, rows, off.get(), cnt.get(), key.get(),
