@@ -105,6 +105,25 @@ int sun_expand_operator(sun_basis b, const sun_zcsr* X, double* coef_re,
                         double* coef_im, double* trace, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Readout (Sec. II eq. 5; Sec. IV step 3.2)
+ * ---------------------------------------------------------------------- */
+/* Density matrix rho = 1/N + sum_j v_j F_j of a Bloch vector v (device
+ * double[M]) into rho_re, rho_im (device double[N*N], row-major; rho_im may
+ * be NULL to skip the imaginary part).  Asynchronous on `stream`. */
+int sun_bloch_density(sun_basis b, const double* v, double* rho_re, double* rho_im,
+                      void* stream);
+/* Expectation values Tr(rho_i X) = Tr(X)/N + sum_j v_ij x_j for nvec Bloch
+ * vectors v_i = v + i*ldv (device; ldv >= M when nvec > 1), where x_j =
+ * Tr(F_j X) are X's coefficients from sun_expand_operator (x_re, x_im device
+ * double[M]; x_im may be NULL when out_im is NULL) and trace = Tr(X) (host
+ * double[2] as re, im, or NULL for a traceless X).  out_re, out_im: device
+ * double[nvec] (out_im may be NULL).  One workgroup per vector, fixed-order
+ * reduction.  Asynchronous on `stream`. */
+int sun_bloch_expect(sun_basis b, const double* v, int64_t nvec, int64_t ldv,
+                     const double* x_re, const double* x_im, const double* trace,
+                     double* out_re, double* out_im, void* stream);
+
+/* ------------------------------------------------------------------------
  * Lindbladian expansion (Sec. II eqs. 6, 10, 11; Sec. IV steps 2.3-2.5)
  * ---------------------------------------------------------------------- */
 typedef struct sun_lind_s* sun_lind;
@@ -162,6 +181,18 @@ int sun_prop_create(sun_lind l, const double* static_w, const int32_t* dyn,
  * `stream`.  Four kernel launches per step (one per stage). */
 int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
                   int64_t steps, void* stream);
+/* Same as sun_propagate, recording along the way (Sec. IV step 3.2): after
+ * steps n = every, 2 every, ..., nrec every (nrec = steps / every, rounded
+ * down; any remaining steps are still taken) record r = n/every - 1 stores
+ *   states + r*ld   <- v_n          (states: device double[nrec*ld], ld >= M, or NULL)
+ *   obs[r]          <- x0 + x . v_n (x: device double[M]; obs: device double[nrec],
+ *                                    or NULL to skip; obs needs x)
+ * e.g. x_j = Tr(F_j X) from sun_expand_operator and x0 = Tr(X)/N give
+ * obs = Tr(rho X) (eq. 5).  The dot products are reduced in a fixed order;
+ * the states are bitwise those of sun_propagate calls of `every` steps. */
+int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt,
+                         int64_t steps, int64_t every, double* states, int64_t ld,
+                         const double* x, double x0, double* obs, void* stream);
 /* Same as sun_propagate, and additionally records a HIP event pair around
  * every stage launch on `stream`; on return (synchronised) stage_ms[i]
  * (host double[4]) holds the summed GPU time of stage i over all steps and

@@ -52,9 +52,12 @@ PROTOS = {
     "sun_lind_nnz": (C.c_int, [vp, i32, i32, P(i64)]),
     "sun_lind_export": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
     "sun_lind_free": (None, [vp]),
+    "sun_bloch_density": (C.c_int, [vp, vp, vp, vp, vp]),
+    "sun_bloch_expect": (C.c_int, [vp, vp, i64, i64, vp, vp, P(f64), vp, vp, vp]),
     "sun_prop_create": (C.c_int, [vp, P(f64), P(i32), i32, vp, P(vp)]),
     "sun_propagate": (C.c_int, [vp, vp, vp, f64, i64, vp]),
     "sun_propagate_profile": (C.c_int, [vp, vp, vp, f64, i64, vp, P(f64), P(i64)]),
+    "sun_propagate_record": (C.c_int, [vp, vp, vp, f64, i64, i64, vp, i64, vp, f64, vp, vp]),
     "sun_prop_info": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),

@@ -113,6 +113,37 @@ class Basis:
         check(self._lib.sun_expand_operator(self.handle, C.byref(s), _ptr(re), _ptr(im), tr, _stream()))
         return torch.complex(re, im), complex(tr[0], tr[1])
 
+    def density(self, v: torch.Tensor) -> torch.Tensor:
+        """rho = 1/N + sum_j v_j F_j (eq. 5) as a complex128 (N, N) tensor."""
+        assert v.dtype == torch.float64 and v.is_cuda and v.is_contiguous() and v.numel() == self.M
+        re = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda")
+        im = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda")
+        check(self._lib.sun_bloch_density(self.handle, _ptr(v), _ptr(re), _ptr(im), _stream()))
+        return torch.complex(re, im)
+
+    def observable(self, op):
+        """(x, x0): real coefficients x_j = Re Tr(F_j X) (float64 (M,) tensor)
+        and Re Tr(X)/N of a Hermitian X, as taken by Propagator.record."""
+        x, tr = self.expand(op)
+        return x.real.contiguous(), tr.real / self.N
+
+    def expect(self, v: torch.Tensor, op) -> torch.Tensor:
+        """Tr(rho X) for one Bloch vector (shape (M,)) or a stack (shape (n, M)
+        or any 2-D view with unit column stride); complex128 result."""
+        assert v.dtype == torch.float64 and v.is_cuda and v.shape[-1] == self.M and v.stride(-1) == 1
+        vv = v if v.dim() == 2 else v.reshape(1, self.M)
+        n = vv.shape[0]
+        x, tr = self.expand(op)
+        xr, xi = x.real.contiguous(), x.imag.contiguous()
+        t = (C.c_double * 2)(tr.real, tr.imag)
+        out_re = torch.empty(n, dtype=torch.float64, device="cuda")
+        out_im = torch.empty(n, dtype=torch.float64, device="cuda")
+        ld = vv.stride(0) if n > 1 else self.M
+        check(self._lib.sun_bloch_expect(self.handle, _ptr(vv), n, ld, _ptr(xr), _ptr(xi), t, _ptr(out_re),
+                                         _ptr(out_im), _stream()))
+        out = torch.complex(out_re, out_im)
+        return out if v.dim() == 2 else out[0]
+
 
 def build_basis(N: int) -> Basis:
     return Basis(N)
@@ -228,6 +259,27 @@ class Propagator:
             assert coef.numel() >= (2 * steps + 1) * self.ndyn
         check(self._lib.sun_propagate(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), _stream()))
         return v
+
+    def record(self, v: torch.Tensor, coef: torch.Tensor | None, dt: float, steps: int, every: int,
+               states: bool = True, observable=None):
+        """RK4 like ``propagate`` (in place on v), recording after every
+        ``every`` steps.  Returns (states (nrec, M) or None, obs (nrec,) or
+        None); observable = (x, x0) gives obs = x0 + x . v (e.g. from
+        Basis.observable)."""
+        assert v.dtype == torch.float64 and v.is_cuda and v.is_contiguous() and v.numel() == self.M
+        if self.ndyn:
+            assert coef is not None and coef.dtype == torch.float64 and coef.is_cuda and coef.is_contiguous()
+            assert coef.numel() >= (2 * steps + 1) * self.ndyn
+        nrec = int(steps) // int(every)
+        st = torch.empty((nrec, self.M), dtype=torch.float64, device="cuda") if states else None
+        x, x0, obs = None, 0.0, None
+        if observable is not None:
+            x, x0 = observable
+            assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == self.M
+            obs = torch.empty(nrec, dtype=torch.float64, device="cuda")
+        check(self._lib.sun_propagate_record(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), int(every),
+                                             _ptr(st), self.M, _ptr(x), float(x0), _ptr(obs), _stream()))
+        return st, obs
 
 
 def _profile(self, v, coef, dt, steps):

@@ -29,6 +29,7 @@ struct sun_prop_s {
   DevBuf<int> sell_row, sell_len, sell_off, sell_coff, sell_base, long_rows;
   DevBuf<unsigned char> sell_cb;
   DevBuf<double> sell_val;
+  DevBuf<double> rec_part;   // partial sums of the recorded observable
 };
 
 namespace sun {

@@ -32,6 +32,7 @@
 using namespace sun;
 
 #include "prop_internal.hpp"
+#include "readout.hpp"
 
 
 namespace {
@@ -895,6 +896,42 @@ extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double d
       launch_stage<1>(*p, xa, xb, coef, 2 * n + 1, dt, s);
       launch_stage<2>(*p, xb, xa, coef, 2 * n + 1, dt, s);
       launch_stage<3>(*p, xa, va, coef, 2 * n + 2, dt, s);
+    }
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  });
+}
+
+extern "C" int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt, int64_t steps,
+                                    int64_t every, double* states, int64_t ld, const double* x, double x0,
+                                    double* obs, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr && v != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(steps >= 0 && every >= 1, SUN_EINVAL, "steps must be >= 0 and every >= 1");
+    SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    SUN_REQUIRE(states == nullptr || ld >= p->M, SUN_EINVAL, "ld must be >= M");
+    SUN_REQUIRE(obs == nullptr || x != nullptr, SUN_EINVAL, "obs needs x");
+    if (steps == 0) return;
+    hipStream_t s = as_stream(stream);
+    const int64_t M = p->M;
+    const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M + 4095) / 4096));
+    if (obs && p->rec_part.n < (size_t)(2 * nb)) p->rec_part.alloc(2 * nb);
+    HIP_OK(hipMemcpyAsync(p->vaug.get(), v, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double* va = p->vaug.get();
+    double* xa = p->xa.get();
+    double* xb = p->xb.get();
+    int64_t rec = 0;
+    for (int64_t n = 0; n < steps; ++n) {
+      launch_stage<0>(*p, va, xa, coef, 2 * n, dt, s);
+      launch_stage<1>(*p, xa, xb, coef, 2 * n + 1, dt, s);
+      launch_stage<2>(*p, xb, xa, coef, 2 * n + 1, dt, s);
+      launch_stage<3>(*p, xa, va, coef, 2 * n + 2, dt, s);
+      if ((n + 1) % every == 0) {
+        if (states)
+          HIP_OK(hipMemcpyAsync(states + rec * ld, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (obs) expect_launch(M, va, 1, M, x, nullptr, x0, 0.0, obs + rec, nullptr, p->rec_part.get(), nb, s);
+        ++rec;
+      }
     }
     HIP_LAUNCH_OK();
     HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));

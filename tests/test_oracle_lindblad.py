@@ -169,3 +169,17 @@ def test_dimer_operators_structure():
     np.testing.assert_allclose(ops["HU"].to_dense(),
                                sub(0.5 * (n1 @ (n1 - np.eye(N * N)) + n2 @ (n2 - np.eye(N * N)))),
                                atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_entrywise_density_matches_generator_sum(N):
+    """The entry-by-entry reconstruction of rho from v equals eq. 5 summed
+    over the explicit generators, for a random (not necessarily positive) v;
+    the result has unit trace and is Hermitian."""
+    F = basis.generators(N)
+    v = random_ops.random_vector(N * N - 1, seed=40 + N)
+    rho = lb.density_from_bloch_dense(v, N)
+    np.testing.assert_allclose(rho, lb.density_from_bloch(F, v), atol=1e-15)
+    assert abs(np.trace(rho) - 1) < 1e-14
+    np.testing.assert_array_equal(rho, rho.conj().T)
+    np.testing.assert_allclose(lb.bloch_vector(F, rho), v, atol=1e-14)
