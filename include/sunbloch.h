@@ -220,13 +220,20 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  * long_len in [1, 4096]; ndyn <= 1 only).  In layout 1 the column index of
  * each stored entry is kept as an offset from a per-(slice, entry) base, in
  * 1, 2 or 4 bytes per slice, the narrowest that fits; min_col_bytes (1, 2, 4)
- * bounds that width from below (4 = uncompressed); xcd_remap bit 0 gives each
- * XCD one contiguous range of slices, bit 1 reads the matrix stream with
- * ordinary (cached) instead of non-temporal loads.  Defaults 1024/256/0 and 4096/64/1/1. */
+ * bounds that width from below (4 = uncompressed).  flags of
+ * sun_prop_tune_sliced: bit 0 gives each XCD one contiguous range of slices
+ * (so the state entries its rows gather stay in that XCD's L2); bit 1 reads
+ * the matrix stream with non-temporal loads (by default ordinary loads, which
+ * let the matrix stay in the memory-side cache between launches when it
+ * fits); bits 8-15 the number of consecutive slices one wavefront processes
+ * (0 = 1); bits 16-23 the entries a lane loads per round (0 = 8, or 4, 12,
+ * 16).  Other bits must be 0 (else SUN_EINVAL).  Defaults: block_nnz 1024,
+ * threads 256, xcd_remap 0; sigma 4096, long_len 64, min_col_bytes 1,
+ * flags 1. */
 int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
                   void* stream);
 int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,
-                         int32_t xcd_remap, void* stream);
+                         int32_t flags, void* stream);
 /* Current layout, number of stored matrix entries (with padding), rows on
  * the long-row path, and bytes of matrix data plus per-row metadata one
  * stage launch streams (sliced layout: excluding the long rows' entries). */

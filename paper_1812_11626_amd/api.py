@@ -239,10 +239,13 @@ class Propagator:
         check(self._lib.sun_prop_tune(self.handle, int(block_nnz), int(threads), int(bool(xcd_remap)),
                                       _stream()))
 
-    def tune_sliced(self, sigma: int = 4096, long_len: int = 64, min_col_bytes: int = 1, xcd_remap: bool = True):
+    def tune_sliced(self, sigma: int = 4096, long_len: int = 64, min_col_bytes: int = 1, xcd_remap: bool = True,
+                    nontemporal: bool = False, slices_per_wave: int = 1, unroll: int = 8):
         """Select the sliced-ELL layout with these knobs."""
-        check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes),
-                                             int(bool(xcd_remap)), _stream()))
+        flags = int(bool(xcd_remap)) | (int(bool(nontemporal)) << 1) | ((int(slices_per_wave) & 0xFF) << 8) \
+            | ((int(unroll) & 0xFF) << 16)
+        check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes), flags,
+                                             _stream()))
 
     def layout(self):
         lay, stored, nlong, nb = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -130,4 +130,6 @@ def test_propagate_argument_checks(lib):
     with pytest.raises(lib.SunError):
         prop.tune_sliced(4096, 64, 3)                                           # bad byte width
     with pytest.raises(lib.SunError):
+        prop.tune_sliced(unroll=5)                                              # unsupported unroll
+    with pytest.raises(lib.SunError):
         lind.propagator([1.0, 0.0, 0.1], [0, 1, 2, 0, 1])                       # > 4 dynamic terms

@@ -208,3 +208,27 @@ def test_sliced_layout_matches_stream_layout(lib):
     prop.propagate(a, eps, p.dt, 300)
     prop.propagate(b, eps, p.dt, 300)
     assert torch.equal(a, b)
+
+
+def test_sliced_kernel_variants_are_bitwise_identical(lib):
+    """XCD remapping, load hints, slices per wavefront and entries per load
+    round change only which wavefront handles a slice and how its loads are
+    issued, never the order of a row's sum: results are bitwise equal."""
+    N = 101
+    flush(f"[propagate] sliced variants N={N}")
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    _, _, prop = _gpu_system(lib, p, ops)
+    steps = 40
+    eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+    v0 = torch.as_tensor(_fock_v0(N)).cuda()
+    prop.tune_sliced()
+    ref = v0.clone()
+    prop.propagate(ref, eps, p.dt, steps)
+    for kw in (dict(xcd_remap=False), dict(nontemporal=True), dict(slices_per_wave=3), dict(unroll=4),
+               dict(unroll=12), dict(unroll=16, nontemporal=True), dict(slices_per_wave=2, xcd_remap=False)):
+        prop.tune_sliced(**kw)
+        v = v0.clone()
+        prop.propagate(v, eps, p.dt, steps)
+        assert torch.equal(v, ref), kw
+
