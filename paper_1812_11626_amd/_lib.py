@@ -68,7 +68,7 @@ PROTOS = {
     "sun_batch_get_state": (C.c_int, [vp, i32, vp, vp]),
     "sun_batch_run": (C.c_int, [vp, i64, i32, vp]),
     "sun_batch_info": (C.c_int, [vp, i32, P(i64), P(i64), P(i32), P(i32)]),
-    "sun_batch_tune": (C.c_int, [vp, i32, i32, i32, vp]),
+    "sun_batch_tune": (C.c_int, [vp, i32, i32, i32, i32, vp]),
     "sun_batch_free": (None, [vp]),
     "sun_adjoint_create": (C.c_int, [vp, P(f64), P(i32), i32, vp, P(vp)]),
     "sun_adjoint_run": (C.c_int, [vp, vp, vp, P(f64), vp, i32, vp, f64, i64, i64, i64, P(f64), P(f64), vp]),

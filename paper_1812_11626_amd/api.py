@@ -371,8 +371,11 @@ class BatchedPropagator:
     def run(self, nsteps: int, only_group: int = -1):
         check(self._lib.sun_batch_run(self.handle, int(nsteps), int(only_group), _stream()))
 
-    def tune(self, g: int, tile: int, rows_per_item: int):
-        check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), _stream()))
+    def tune(self, g: int, tile: int, rows_per_item: int, path: int = 0):
+        """Tiling of group g; path 0 = LDS-staged row blocks (when every row
+        fits), 1 = one wavefront per (rows, tile) reading the matrix from
+        global memory."""
+        check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), int(path), _stream()))
 
     def info(self, g: int):
         M, nnz, tile, rows = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()

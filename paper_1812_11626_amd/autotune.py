@@ -16,7 +16,7 @@ import time
 import torch
 
 TILES = (16, 32, 64)
-ROWS = (8, 32, 128, 512)
+ROWS = (32, 64, 128)
 
 
 def cache_path() -> str:
@@ -45,7 +45,7 @@ def _save(path, data):
 
 def _key(G) -> str:
     name = torch.cuda.get_device_name(0).replace(" ", "_")
-    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}"
+    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds"
 
 
 def autotune_batched(bp, tiles=TILES, rows=ROWS, probe_steps: int = 6, use_cache: bool = True,

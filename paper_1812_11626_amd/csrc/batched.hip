@@ -47,7 +47,10 @@ struct GroupDev {
   double dt;
   int M, B, ld, nt, tile, rows_per_item;
   int row_blocks, tiles;
-  int64_t item0;         // first work item of this group
+  int64_t item0;         // first work item of this group (per-wavefront path)
+  const int* blk_row;    // LDS path: row blocks [blk_row[i], blk_row[i+1])
+  int nblk;              // LDS path: number of row blocks (0: per-wavefront path)
+  int64_t bitem0;        // LDS path: first work item of this group
 };
 
 }  // namespace
@@ -65,6 +68,10 @@ struct sun_batch_s {
   DevBuf<GroupDev> gdev;
   std::vector<GroupDev> ghost;
   std::vector<int> order;   // groups sorted by decreasing remaining steps
+  std::vector<std::vector<int>> h_rowptr;   // host copies, for the LDS row-block partition
+  std::vector<DevBuf<int>> blk_row;
+  std::vector<int> nblk;    // row blocks of the LDS path (0: the group uses the per-wavefront path)
+  std::vector<int> path;    // 0: LDS path when every row fits, 1: per-wavefront path
 };
 
 namespace {
@@ -202,6 +209,121 @@ __global__ __launch_bounds__(256) void k_batch_stage(const GroupDev* __restrict_
   }
 }
 
+// LDS path: one workgroup per block of rows (at most kLdsRows rows and
+// kLdsCap stored entries).  The block's columns, values, row and segment
+// pointers are staged in LDS once and reused for every instance tile, so the
+// gathers of a row wait only on LDS reads; each lane group of T lanes sums
+// one row for T instances, term by term in row order (the same order and
+// arithmetic as k_batch_stage).
+constexpr int kLdsCap = 1024;
+constexpr int kLdsRows = 128;
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restrict__ groups,
+                                                         const int* __restrict__ gorder, int nactive,
+                                                         int64_t nitems, const int64_t* __restrict__ step) {
+  __shared__ int s_col[kLdsCap];
+  __shared__ double s_val[kLdsCap];
+  __shared__ int s_rp[kLdsRows + 1];
+  __shared__ int s_seg[kLdsRows * kMaxBTerms];
+  const int tid = threadIdx.x;
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    int gi = 0;
+    for (int q = 1; q < nactive; ++q)
+      if (groups[gorder[q]].bitem0 <= it) gi = q;
+    const GroupDev& G = groups[gorder[gi]];
+    const int blk = (int)(it - G.bitem0);
+    const int r0 = G.blk_row[blk], r1 = G.blk_row[blk + 1];
+    const int nr = r1 - r0;
+    const int e0 = G.rowptr[r0];
+    const int ne = G.rowptr[r1] - e0;
+    const int nt = G.nt;
+    __syncthreads();   // the previous item's LDS contents are no longer read
+    for (int i = tid; i < ne; i += 256) {
+      s_col[i] = G.col[e0 + i];
+      s_val[i] = G.val[e0 + i];
+    }
+    for (int i = tid; i <= nr; i += 256) s_rp[i] = G.rowptr[r0 + i] - e0;
+    for (int i = tid; i < nr * nt; i += 256) s_seg[i] = G.segptr[(int64_t)r0 * nt + i] - e0;
+    __syncthreads();
+    const int T = G.tile;
+    const int ngrp = 256 / T, lg = tid / T, bl = tid % T;
+    const int64_t k0 = 2 * step[gorder[gi]];
+    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+    const double ph = G.wave[k0 + krow];
+    const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
+    double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
+    const int ld = G.ld;
+    for (int tb = 0; tb < G.tiles; ++tb) {
+      const int b = tb * T + bl;
+      double coefb[kMaxBTerms];
+#pragma unroll
+      for (int a = 0; a < kMaxBTerms; ++a)
+        coefb[a] = (a < nt && b < G.B) ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
+      const double* xb = xin + b;
+      for (int lr = lg; lr < nr; lr += ngrp) {
+        const int ee = s_rp[lr + 1];
+        // the row's own state entries are loaded before its gathers
+        const int64_t ix = (int64_t)(r0 + lr) * ld + b;
+        const bool own = b < G.B;
+        const double vr = own ? G.v[ix] : 0.0;
+        const double ar = (own && STAGE != 0) ? G.acc[ix] : 0.0;
+        double ysum = 0.0;
+        for (int a = 0; a < nt; ++a) {
+          const int s0 = s_seg[lr * nt + a];
+          const int s1 = (a + 1 < nt) ? s_seg[lr * nt + a + 1] : ee;
+          double sacc = 0.0;
+          int e = s0;
+          for (; e + 4 <= s1; e += 4) {
+            const int c0 = s_col[e], c1 = s_col[e + 1], c2 = s_col[e + 2], c3 = s_col[e + 3];
+            const double v0 = s_val[e], v1 = s_val[e + 1], v2 = s_val[e + 2], v3 = s_val[e + 3];
+            const double x0 = xb[(int64_t)c0 * ld], x1 = xb[(int64_t)c1 * ld];
+            const double x2 = xb[(int64_t)c2 * ld], x3 = xb[(int64_t)c3 * ld];
+            sacc += v0 * x0;
+            sacc += v1 * x1;
+            sacc += v2 * x2;
+            sacc += v3 * x3;
+          }
+          for (; e < s1; ++e) sacc += s_val[e] * xb[(int64_t)s_col[e] * ld];
+          ysum += coefb[a] * sacc;
+        }
+        if (own) {
+          const double dt = G.dt;
+          if (STAGE == 0) {
+            xout[ix] = vr + (0.5 * dt) * ysum;
+            G.acc[ix] = ysum;
+          } else if (STAGE == 1) {
+            xout[ix] = vr + (0.5 * dt) * ysum;
+            G.acc[ix] = ar + 2.0 * ysum;
+          } else if (STAGE == 2) {
+            xout[ix] = vr + dt * ysum;
+            G.acc[ix] = ar + 2.0 * ysum;
+          } else {
+            xout[ix] = vr + (dt / 6.0) * (ar + ysum);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Row blocks of at most max_rows rows and kLdsCap entries; empty if a single
+// row has more than kLdsCap entries (the group then takes the per-wavefront
+// path).
+std::vector<int> lds_partition(const std::vector<int>& rp, int max_rows) {
+  std::vector<int> blk{0};
+  const int M = (int)rp.size() - 1;
+  int r0 = 0;
+  while (r0 < M) {
+    if (rp[r0 + 1] - rp[r0] > kLdsCap) return {};
+    int r1 = r0 + 1;
+    while (r1 < M && r1 - r0 < max_rows && rp[r1 + 1] - rp[r0] <= kLdsCap) ++r1;
+    blk.push_back(r1);
+    r0 = r1;
+  }
+  return blk;
+}
+
 void refresh_items(sun_batch_s& bt) {
   int64_t item = 0;
   for (int g = 0; g < bt.ngroups; ++g) {
@@ -212,10 +334,30 @@ void refresh_items(sun_batch_s& bt) {
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
     G.tiles = (G.B + G.tile - 1) / G.tile;
   }
+  int64_t bitem = 0;
   for (int gi : bt.order) {
     GroupDev& G = bt.ghost[gi];
+    G.nblk = bt.nblk[gi];
+    G.blk_row = bt.blk_row[gi].get();
     G.item0 = item;
-    item += (int64_t)G.row_blocks * G.tiles;
+    G.bitem0 = bitem;
+    if (G.nblk > 0) bitem += G.nblk;
+    else item += (int64_t)G.row_blocks * G.tiles;
+  }
+}
+
+// Per-wavefront and LDS work items of a group (one of the two is zero).
+int64_t wave_items(const GroupDev& G) { return G.nblk > 0 ? 0 : (int64_t)G.row_blocks * G.tiles; }
+
+void repartition(sun_batch_s& bt, int g) {
+  const std::vector<int> blk = bt.path[g] == 1 ? std::vector<int>{}
+                                               : lds_partition(bt.h_rowptr[g], std::min(bt.rows_per_item[g], kLdsRows));
+  bt.nblk[g] = blk.empty() ? 0 : (int)blk.size() - 1;
+  if (bt.nblk[g] > 0) {
+    bt.blk_row[g].alloc(blk.size());
+    HIP_OK(hipMemcpy(bt.blk_row[g].get(), blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice));
+  } else {
+    bt.blk_row[g].release();
   }
 }
 
@@ -283,6 +425,10 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->ld.resize(ngroups);
       bt->nt.resize(ngroups);
       bt->ghost.resize(ngroups);
+      bt->h_rowptr.resize(ngroups);
+      bt->blk_row.resize(ngroups);
+      bt->nblk.assign(ngroups, 0);
+      bt->path.assign(ngroups, 0);
       for (int g = 0; g < ngroups; ++g) {
         const sun_lind_s* l = lind[g];
         SUN_REQUIRE(l != nullptr, SUN_EINVAL, "group system is NULL");
@@ -327,6 +473,9 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
                            bt->rowptr[g].get());
         HIP_LAUNCH_OK();
         HIP_OK(hipStreamSynchronize(s));
+        bt->h_rowptr[g].resize(M + 1);
+        HIP_OK(hipMemcpy(bt->h_rowptr[g].data(), bt->rowptr[g].get(), (M + 1) * sizeof(int), hipMemcpyDeviceToHost));
+        repartition(*bt, g);
         bt->ld[g] = round_up(B[g], 64);
         GroupDev& G = bt->ghost[g];
         G = GroupDev{};
@@ -381,16 +530,20 @@ extern "C" int sun_batch_get_state(sun_batch bt, int32_t g, double* V, void* str
   });
 }
 
-extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t rows_per_item, void* stream) {
+extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t rows_per_item, int32_t path,
+                              void* stream) {
   return guarded([&] {
     SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
     SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64, SUN_EINVAL, "tile must be 8, 16, 32 or 64");
     SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= 65536, SUN_EINVAL, "rows_per_item out of range");
+    SUN_REQUIRE(path == 0 || path == 1, SUN_EINVAL, "path must be 0 or 1");
     hipStream_t s = as_stream(stream);
     HIP_OK(hipStreamSynchronize(s));
     bt->tile[g] = tile;
     bt->rows_per_item[g] = rows_per_item;
+    bt->path[g] = path;
+    repartition(*bt, g);
     refresh_items(*bt);
     upload(*bt, s);
   });
@@ -430,11 +583,12 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     DevBuf<int> gorder(bt->ngroups);
     DevBuf<int64_t> stepidx(bt->ngroups);
     HIP_OK(hipMemcpyAsync(gorder.get(), ord.data(), bt->ngroups * sizeof(int), hipMemcpyHostToDevice, s));
-    // prefix sums of work items in launch order
-    std::vector<int64_t> items_upto(bt->ngroups + 1, 0);
+    // prefix sums of work items in launch order (per-wavefront and LDS paths)
+    std::vector<int64_t> items_upto(bt->ngroups + 1, 0), blocks_upto(bt->ngroups + 1, 0);
     for (int q = 0; q < bt->ngroups; ++q) {
       const GroupDev& G = bt->ghost[ord[q]];
-      items_upto[q + 1] = items_upto[q] + (int64_t)G.row_blocks * G.tiles;
+      items_upto[q + 1] = items_upto[q] + wave_items(G);
+      blocks_upto[q + 1] = blocks_upto[q] + G.nblk;
     }
     // the step index of every group lives in a device table: one row per step
     std::vector<int64_t> table((size_t)maxn * bt->ngroups);
@@ -449,18 +603,36 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       int nactive = 0;
       while (nactive < bt->ngroups && todo[ord[nactive]] > n) ++nactive;
       const int64_t nitems = items_upto[nactive];
-      const int64_t waves_needed = nitems;
-      int64_t grid = std::min<int64_t>((waves_needed + 3) / 4, (int64_t)ncu * 8);
-      if (grid < 1) grid = 1;
+      const int64_t nblocks = blocks_upto[nactive];
+      const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((nitems + 3) / 4, (int64_t)ncu * 8));
+      const int64_t bgrid = std::max<int64_t>(1, std::min<int64_t>(nblocks, (int64_t)ncu * 8));
       const int64_t* st = steptab.get() + n * bt->ngroups;
-      hipLaunchKernelGGL(k_batch_stage<0>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
-                         nactive, nitems, st);
-      hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
-                         nactive, nitems, st);
-      hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
-                         nactive, nitems, st);
-      hipLaunchKernelGGL(k_batch_stage<3>, dim3((unsigned)grid), dim3(256), 0, s, bt->gdev.get(), gorder.get(),
-                         nactive, nitems, st);
+      const GroupDev* gd = bt->gdev.get();
+      const int* go = gorder.get();
+      if (nitems > 0) {
+        hipLaunchKernelGGL(k_batch_stage<0>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
+      }
+      if (nblocks > 0) {
+        hipLaunchKernelGGL(k_batch_stage_lds<0>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+      }
+      if (nitems > 0) {
+        hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
+      }
+      if (nblocks > 0) {
+        hipLaunchKernelGGL(k_batch_stage_lds<1>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+      }
+      if (nitems > 0) {
+        hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
+      }
+      if (nblocks > 0) {
+        hipLaunchKernelGGL(k_batch_stage_lds<2>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+      }
+      if (nitems > 0) {
+        hipLaunchKernelGGL(k_batch_stage<3>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
+      }
+      if (nblocks > 0) {
+        hipLaunchKernelGGL(k_batch_stage_lds<3>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+      }
     }
     HIP_LAUNCH_OK();
     for (int g = 0; g < bt->ngroups; ++g) bt->done[g] += todo[g];

@@ -64,14 +64,40 @@ def test_tiling_does_not_change_results(lib):
     bp, groups = dimer_batch(lib, inst, {4: 30, 5: 30})
     starts = [torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))) for (N, idx, _, _, _) in groups]
     results = []
-    for tile, rows in ((64, 64), (8, 1), (16, 7), (32, 512)):
+    for tile, rows, path in ((64, 64, 0), (8, 1, 0), (16, 7, 1), (32, 512, 1), (64, 3, 1), (16, 128, 0)):
         for g in range(len(groups)):
-            bp.tune(g, tile, rows)
+            bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
         bp.run(30)
         results.append([bp.get_state(g).cpu().numpy() for g in range(len(groups))])
     for r in results[1:]:
         for a, b in zip(r, results[0]):
+            assert np.array_equal(a, b)
+
+
+def test_lds_and_global_paths_agree_bitwise(lib):
+    """N = 51 and 101 groups (rows span many LDS blocks of <= 1024 entries):
+    the LDS-staged path and the per-wavefront path give the same bits."""
+    flush("[batched] LDS vs global path")
+    rng = np.random.default_rng(5)
+    inst = []
+    for N in (51, 101):
+        for _ in range(70):
+            p = dimer.plain_config(N)
+            p.A = float(rng.uniform(0.5, 3.0))
+            p.gamma = float(rng.uniform(0.01, 0.5))
+            inst.append(p)
+    bp, groups = dimer_batch(lib, inst, 12)
+    starts = [torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))) for (N, idx, _, _, _) in groups]
+    out = []
+    for tile, rows, path in ((64, 64, 0), (16, 128, 0), (32, 16, 1), (64, 8, 1)):
+        for g in range(len(groups)):
+            bp.tune(g, tile, rows, path)
+            bp.set_state(g, starts[g])
+        bp.run(12)
+        out.append([bp.get_state(g).cpu().numpy() for g in range(len(groups))])
+    for r in out[1:]:
+        for a, b in zip(r, out[0]):
             assert np.array_equal(a, b)
 
 
