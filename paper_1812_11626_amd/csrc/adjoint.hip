@@ -30,6 +30,7 @@ struct sun_adj_s {
   const sun_lind_s* lind = nullptr;
   sun_lind_s lindT;             // transposed terms, K = 0
   sun_prop fwd = nullptr, bwd = nullptr;
+  std::vector<sun_prop> termp;  // per term: the term alone (unit weight), for the parameter dot products
   std::vector<double> static_w;
   std::vector<int> dyn;
   int nt = 0, ndyn = 0;
@@ -37,6 +38,8 @@ struct sun_adj_s {
   ~sun_adj_s() {
     if (fwd) sun_prop_free(fwd);
     if (bwd) sun_prop_free(bwd);
+    for (sun_prop q : termp)
+      if (q) sun_prop_free(q);
   }
 };
 
@@ -132,53 +135,25 @@ __global__ void k_adj_fill(int64_t n, double v, double* __restrict__ a) {
 }
 
 constexpr int kDotBlocks = 512;
-constexpr int kTermDotBlocks = 8192;
 constexpr int kMaxTheta = 8;
 constexpr int kMaxGTerms = 8;
 
-struct DotTerms {
-  int n;                          // number of parameter-dependent terms
-  int term[kMaxGTerms];           // term index a
-  int dynslot[kMaxGTerms];        // d if the term is time dependent, else -1
-  const int* rowptr[kMaxGTerms];
-  const int* col[kMaxGTerms];
-  const double* val[kMaxGTerms];
-  const double* K[kMaxGTerms];
-};
-
-// partial[j][blk] = sum over this block's rows of kb[r] (T_j x + K_j)[r];
-// blockIdx.y selects the term j.  Groups of 4 lanes take one row each
-// (adjacent reads of the row, then a fixed shuffle tree).
-constexpr int kRowLanes = 4;
-
-__global__ __launch_bounds__(256) void k_dot_terms(int64_t M, DotTerms t, const double* __restrict__ kb,
-                                                   const double* __restrict__ x, double* __restrict__ partial) {
+// part[blk] += scale * (this block's share of a . b), accumulated over calls
+// in stream order (fixed order per slot).
+__global__ __launch_bounds__(256) void k_dot_acc(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                                 double scale, double* __restrict__ part) {
   __shared__ double sh[256];
-  const int j = blockIdx.y;
-  const int sub = threadIdx.x & (kRowLanes - 1);
-  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
-  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / kRowLanes;
-  const int* __restrict__ rp = t.rowptr[j];
-  const int* __restrict__ cl = t.col[j];
-  const double* __restrict__ vl = t.val[j];
-  const double* __restrict__ Kj = t.K[j];
-  double acc = 0.0;
-  for (int64_t r = grp; r < M; r += ngrp) {
-    double s = 0.0;
-    for (int e = rp[r] + sub; e < rp[r + 1]; e += kRowLanes) s += vl[e] * x[cl[e]];
-    for (int o = kRowLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kRowLanes);
-    if (Kj) s += Kj[r];
-    acc += (sub == 0) ? kb[r] * s : 0.0;
-  }
-  sh[threadIdx.x] = acc;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) part[blockIdx.x] += scale * sh[0];
 }
-
 
 // Sum of n partials by one workgroup in a fixed order (strided per lane,
 // then a tree), result in sh[0] of lane 0.
@@ -194,26 +169,6 @@ __device__ inline double block_sum_fixed(const double* __restrict__ part, int n,
   const double r = sh[0];
   __syncthreads();
   return r;
-}
-
-// grad[th] += sum_j dc_j/dth * sum_blk partial[j][blk], in a fixed order
-__global__ __launch_bounds__(256) void k_grad_accumulate(DotTerms t, const double* __restrict__ partial, int nblk,
-                                                         const double* __restrict__ dstatic,
-                                                         const double* __restrict__ dcoef, int64_t krow, int ndyn,
-                                                         int ntheta, double* __restrict__ grad) {
-  __shared__ double sh[256];
-  for (int j = 0; j < t.n; ++j) {
-    const double p = block_sum_fixed(partial + (int64_t)j * nblk, nblk, sh);
-    if (threadIdx.x == 0) {
-      for (int th = 0; th < ntheta; ++th) {
-        // a time-dependent term's coefficient is its static weight plus the
-        // table value; both may depend on theta
-        double dc = dstatic[t.term[j] * ntheta + th];
-        if (t.dynslot[j] >= 0 && dcoef) dc += dcoef[(krow * ndyn + t.dynslot[j]) * ntheta + th];
-        grad[th] += dc * p;
-      }
-    }
-  }
 }
 
 // out[0] += scale * dot(a, b) in a fixed order (two passes)
@@ -237,6 +192,14 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double* __restrict__ p
   __shared__ double sh[256];
   const double s = block_sum_fixed(part, nblk, sh);
   if (threadIdx.x == 0) out[0] += scale * s;
+}
+
+// out[i] = sum over the n partials part[i * n + k], k = 0..n-1, in a fixed
+// order; one workgroup per output.
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const double s = block_sum_fixed(part + (int64_t)blockIdx.x * n, n, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 int dot_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 255) / 256)); }
@@ -315,7 +278,7 @@ struct Work {
   DevBuf<double> ck;        // checkpoints [(nck) * (M+1)]
   DevBuf<double> per;       // states of one interval [(C+1) * (M+1)]
   DevBuf<double> stg;       // stage inputs of one interval [C][3][M+1] (optional)
-  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb, kb2, part, dpart, dev_grad, dev_J, dstat;
+  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb, kb2, gpart, jpart, dev_grad, dev_J, dstat;
 };
 
 }  // namespace
@@ -351,8 +314,10 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
       HIP_LAUNCH_OK();
     }
     for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.acc, &w.lam, &w.lacc, &w.kb, &w.kb2}) b->alloc(M1);
-    w.part.alloc((int64_t)kTermDotBlocks * kMaxGTerms);
-    w.dpart.alloc(kDotBlocks);
+    // per-block accumulator of the objective's dot products
+    const int nbj = dot_blocks(M);
+    w.jpart.alloc(nbj);
+    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(nbj, 256)), dim3(256), 0, s, (int64_t)nbj, 0.0, w.jpart.get());
     w.dev_grad.alloc(kMaxTheta);
     w.dev_J.alloc(1);
     w.dstat.alloc(a->nt * (ntheta > 0 ? ntheta : 1));
@@ -378,36 +343,54 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
       std::swap(cur, nxt);
     }
     // ---- parameter-dependent terms ---------------------------------------
-    DotTerms dt_terms{};
-    {
+    // Each term that depends on a parameter gets its own static propagator
+    // (unit weight, the term's free vector folded in); its dot products
+    // kb . (T_j x + K_j) accumulate, weighted by dc_j/dtheta, in per-wavefront
+    // slots gpart[th * nslot + off_j + w].
+    struct GTerm { int term, slot; const sun_prop_s* p; int64_t off; };
+    std::vector<GTerm> gterms;
+    int64_t nslot = 0;
+    if (ntheta > 0) {
       std::vector<bool> used(a->nt, false);
       for (int d = 0; d < a->ndyn; ++d) used[a->dyn[d]] = true;
       for (int t = 0; t < a->nt; ++t)
         for (int th = 0; th < ntheta; ++th)
           if (dstatic[t * ntheta + th] != 0.0) used[t] = true;
-      const sun_lind_s* l = a->lind;
+      if (a->termp.size() != (size_t)a->nt) a->termp.assign(a->nt, nullptr);
       for (int t = 0; t < a->nt; ++t) {
         if (!used[t]) continue;
-        const int j = dt_terms.n++;
-        const DevCSR& m = t < l->nH ? l->QH[t] : l->R[t - l->nH];
-        dt_terms.term[j] = t;
-        dt_terms.dynslot[j] = -1;
+        if (!a->termp[t]) {
+          std::vector<double> unit(a->nt, 0.0);
+          unit[t] = 1.0;
+          sun_prop q = nullptr;
+          const int st = sun_prop_create(const_cast<sun_lind_s*>(a->lind), unit.data(), nullptr, 0, stream, &q);
+          if (st != SUN_OK) SUN_THROW(st, std::string("term propagator: ") + sun_last_error());
+          a->termp[t] = q;
+        }
+        int slot = -1;
         for (int d = 0; d < a->ndyn; ++d)
-          if (a->dyn[d] == t) dt_terms.dynslot[j] = d;
-        dt_terms.rowptr[j] = m.rowptr.get();
-        dt_terms.col[j] = m.col.get();
-        dt_terms.val[j] = m.val.get();
-        dt_terms.K[j] = t < l->nH ? nullptr : l->K[t - l->nH].get();
+          if (a->dyn[d] == t) slot = d;
+        gterms.push_back({t, slot, a->termp[t], nslot});
+        nslot += prop_dot_slots(*a->termp[t]);
       }
-      if (ntheta == 0) dt_terms.n = 0;
     }
-    // 64 rows in flight per workgroup, at most 1024 workgroups per term
-    const int nbd = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (M + 63) / 64));
+    w.gpart.alloc(std::max<int64_t>(1, ntheta * nslot));
+    if (ntheta * nslot > 0)
+      hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(ntheta * nslot, 256)), dim3(256), 0, s, ntheta * nslot, 0.0,
+                         w.gpart.get());
+    std::vector<const sun_prop_s*> gp;
+    std::vector<int> gterm, gslot;
+    std::vector<int64_t> goff;
+    for (const GTerm& g : gterms) {
+      gp.push_back(g.p);
+      gterm.push_back(g.term);
+      gslot.push_back(g.slot);
+      goff.push_back(g.off);
+    }
     auto grad_stage = [&](const double* kbv, const double* x, int64_t krow) {
-      if (dt_terms.n == 0) return;
-      hipLaunchKernelGGL(k_dot_terms, dim3(nbd, dt_terms.n), dim3(256), 0, s, M, dt_terms, kbv, x, w.part.get());
-      hipLaunchKernelGGL(k_grad_accumulate, dim3(1), dim3(256), 0, s, dt_terms, w.part.get(), nbd, w.dstat.get(),
-                         dcoef, krow, a->ndyn, ntheta, w.dev_grad.get());
+      if (gp.empty()) return;
+      prop_dot(gp.data(), gterm.data(), gslot.data(), goff.data(), (int)gp.size(), x, kbv, w.dstat.get(), dcoef,
+               krow, a->ndyn, ntheta, w.gpart.get(), nslot, s);
     };
     // ---- backward sweep -----------------------------------------------------
     const int64_t first_avg = steps - S_avg + 1;      // J averages v_n for n >= first_avg
@@ -428,7 +411,8 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
         const double* vn = P0 + (n - n0) * M1;
         const double* vn1 = P0 + (n + 1 - n0) * M1;
         const bool in_avg = (n + 1) >= first_avg;
-        if (in_avg) dot_accumulate(cobs, vn1, M, 1.0 / (double)S_avg, w.dpart.get(), w.dev_J.get(), s);
+        if (in_avg)
+          hipLaunchKernelGGL(k_dot_acc, dim3(nbj), dim3(256), 0, s, M, cobs, vn1, 1.0 / (double)S_avg, w.jpart.get());
         // lambda += c/S (direct dependence of J on v_{n+1}); kb4 = dt/6 lambda
         hipLaunchKernelGGL(k_adj_prep, dim3(grid_for(M, 256)), dim3(256), 0, s, M, lam, cobs,
                            in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb.get());
@@ -456,6 +440,10 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
         std::swap(lam, lacc);
       }
     }
+    // fixed-order reductions of the accumulated partials
+    if (ntheta > 0 && nslot > 0)
+      hipLaunchKernelGGL(k_sum_rows, dim3(ntheta), dim3(256), 0, s, w.gpart.get(), (int)nslot, w.dev_grad.get());
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, w.jpart.get(), nbj, w.dev_J.get());
     HIP_LAUNCH_OK();
     double hg[kMaxTheta];
     HIP_OK(hipMemcpyAsync(hg, w.dev_grad.get(), sizeof(hg), hipMemcpyDeviceToHost, s));

@@ -49,4 +49,17 @@ namespace sun {
 void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
                 const double* coef, int64_t coef_row, double dt, hipStream_t s);
 
+// Adjoint parameter dot products on static generators T_j (j < n <= 8) in
+// sliced layout (no time-dependent term), all in one launch: adds, for
+// th < ntheta,  dc_jth * (kb . (T_j x))  (x[M] = 1 brings in T_j's free
+// vector), split over prop_dot_slots(*ps[j]) per-wavefront slots
+// gpart[th * ld + slot0[j] + w], with dc_jth = dstat[term[j] * ntheta + th]
+// (+ dcoef[(krow * ndyn + slot[j]) * ntheta + th] when slot[j] >= 0).  The
+// slot sums are to be reduced in a fixed order.
+constexpr int kMaxDotTerms = 8;
+int64_t prop_dot_slots(const sun_prop_s& p);
+void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, const int64_t* slot0, int n,
+              const double* x, const double* kb, const double* dstat, const double* dcoef, int64_t krow, int ndyn,
+              int ntheta, double* gpart, int64_t ld, hipStream_t s);
+
 }  // namespace sun

@@ -582,6 +582,86 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
   }
 }
 
+// Adjoint parameter dot products on the sliced layouts of static generators
+// T_j (each with its free vector folded in as column M, x[M] = 1), all terms
+// in one launch: the wavefronts are numbered term after term (wave0), and
+// each forms q = sum over its rows of kb[r] (T_j x)[r] (one slice, or one long
+// row), reduced over the wavefront in a fixed tree, and adds dc_th * q to its
+// own slot gpart[th * ld + slot0_j + w] for th < ntheta, with
+// dc_th = dstat[term_j * ntheta + th] (+ dcoef[(krow * ndyn + slot_j) * ntheta + th]
+// for a time-dependent term, slot_j >= 0).  Each slot is updated by one
+// wavefront per launch, in stream order.
+struct DotView {
+  const int *off, *coff, *gbase;
+  const unsigned char* cb;
+  const int *row, *len;
+  const double* sval;
+  int64_t nslices, nshort, nlong;
+  const int *long_rows, *rowptr, *col;
+  const double* val;
+  int term, slot;
+  int64_t wave0, slot0;
+};
+
+struct DotViews {
+  int n;
+  DotView v[kMaxDotTerms];
+};
+
+template <int U, bool NTL>
+__global__ __launch_bounds__(256) void k_dot_sell(DotViews dv, int64_t nwaves, const double* __restrict__ xin,
+                                                  const double* __restrict__ kb, const double* __restrict__ dstat,
+                                                  const double* __restrict__ dcoef, int64_t krow, int ndyn,
+                                                  int ntheta, double* __restrict__ gpart, int64_t ld, int xcd_remap) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (xcd_remap) {
+    const int64_t q = ((int64_t)gridDim.x + 7) >> 3;
+    blk = (blk & 7) * q + (blk >> 3);
+  }
+  const int64_t gw = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (gw >= nwaves) return;
+  int j = 0;
+  for (int q = 1; q < dv.n; ++q)
+    if (dv.v[q].wave0 <= gw) j = q;
+  const DotView& D = dv.v[j];
+  const int64_t wid = gw - D.wave0;
+  double qv = 0.0;
+  if (wid < D.nslices) {
+    const int64_t i = wid * kSlice + lane;
+    const int off = __builtin_amdgcn_readfirstlane(D.off[wid]);
+    const int wd = (__builtin_amdgcn_readfirstlane(D.off[wid + 1]) - off) / kSlice;
+    const int coff = __builtin_amdgcn_readfirstlane(D.coff[wid]);
+    const bool own = i < D.nshort;
+    const int r = own ? D.row[i] : 0;
+    const int lens = D.len[i];
+    const int slen = lens & 0xFFFF, len = lens >> 16;
+    const double kr = own ? kb[r] : 0.0;
+    const unsigned char* cb = D.cb + (coff & ~63);
+    const int* gbase = D.gbase + off / kSlice;
+    const double* vp = D.sval + off + lane;
+    double a0 = 0.0, a1 = 0.0;
+    switch (coff & 3) {
+      case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+    }
+    qv = own ? kr * (a0 + a1) : 0.0;
+  } else {
+    const int r = D.long_rows[wid - D.nslices];
+    double a0 = 0.0;
+    for (int e = D.rowptr[r] + lane; e < D.rowptr[r + 1]; e += 64) a0 += D.val[e] * xin[D.col[e]];
+    for (int o = 32; o > 0; o >>= 1) a0 += __shfl_xor(a0, o, 64);
+    qv = lane == 0 ? kb[r] * a0 : 0.0;
+  }
+  for (int o = 32; o > 0; o >>= 1) qv += __shfl_xor(qv, o, 64);
+  if (lane < ntheta) {
+    double dc = dstat[D.term * ntheta + lane];
+    if (D.slot >= 0 && dcoef) dc += dcoef[(krow * ndyn + D.slot) * ntheta + lane];
+    gpart[lane * ld + D.slot0 + wid] += dc * qv;
+  }
+}
+
 void build_sell(sun_prop_s& p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old layout
   const int64_t M = p.M;
@@ -737,6 +817,49 @@ void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double*
     case 6: launch_stage_v<6>(p, xin, vin, acc, xout, coef, row, dt, s); break;
     default: launch_stage_v<7>(p, xin, vin, acc, xout, coef, row, dt, s); break;
   }
+  HIP_LAUNCH_OK();
+}
+
+int64_t prop_dot_slots(const sun_prop_s& p) { return p.nslices + p.nlong; }
+
+void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, const int64_t* slot0, int n,
+              const double* x, const double* kb, const double* dstat, const double* dcoef, int64_t krow, int ndyn,
+              int ntheta, double* gpart, int64_t ld, hipStream_t s) {
+  SUN_REQUIRE(n >= 1 && n <= kMaxDotTerms, SUN_EINVAL, "1 to 8 terms per dot launch");
+  DotViews dv{};
+  dv.n = n;
+  int64_t nw = 0;
+  for (int j = 0; j < n; ++j) {
+    const sun_prop_s& p = *ps[j];
+    SUN_REQUIRE(p.layout == 1 && p.ndyn == 0, SUN_EINVAL, "dot products need static generators in sliced layout");
+    DotView& D = dv.v[j];
+    D.off = p.sell_off.get();
+    D.coff = p.sell_coff.get();
+    D.gbase = p.sell_base.get();
+    D.cb = p.sell_cb.get();
+    D.row = p.sell_row.get();
+    D.len = p.sell_len.get();
+    D.sval = p.sell_val.get();
+    D.nslices = p.nslices;
+    D.nshort = p.nshort;
+    D.nlong = p.nlong;
+    D.long_rows = p.long_rows.get();
+    D.rowptr = p.rowptr.get();
+    D.col = p.col.get();
+    D.val = p.val.get();
+    D.term = term[j];
+    D.slot = slot[j];
+    D.wave0 = nw;
+    D.slot0 = slot0[j];
+    nw += p.nslices + p.nlong;
+  }
+  if (nw == 0) return;
+  unsigned grid = (unsigned)((nw + 3) / 4);
+  const int remap = ps[0]->sell_remap;
+  if (remap) grid = (grid + 7) / 8 * 8;
+  auto kern = ps[0]->sell_nt ? k_dot_sell<8, true> : k_dot_sell<8, false>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, dv, nw, x, kb, dstat, dcoef, krow, ndyn, ntheta, gpart, ld,
+                     remap);
   HIP_LAUNCH_OK();
 }
 
