@@ -68,16 +68,21 @@ def union_nnz(lind, torch):
     return int(torch.unique(torch.cat(keys)).numel())
 
 
-STAGE_SOURCES = ("paper_1812_11626_amd/csrc/propagate.hip", "paper_1812_11626_amd/csrc/prop_internal.hpp")
+STAGE_SOURCE = "paper_1812_11626_amd/csrc/propagate.hip"
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_rk4_sell_dimer-plain-N1001_counters.md")
 
 
 def stage_source_hash() -> str:
+    """SHA-256 of the stage kernel's source: the text between the
+    "[stage-kernel source: begin]" / "end" markers of propagate.hip."""
     import hashlib
+    import re
+    with open(os.path.join(ROOT, STAGE_SOURCE)) as fh:
+        text = fh.read()
+    parts = re.findall(r"// \[stage-kernel source: begin\]\n(.*?)// \[stage-kernel source: end\]", text, re.S)
     h = hashlib.sha256()
-    for rel in STAGE_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+    for part in parts:
+        h.update(part.encode())
     return h.hexdigest()
 
 

@@ -75,11 +75,14 @@ int sun_basis_dims(sun_basis b, int32_t* N, int64_t* M);
  * analytically).  Host outputs; synchronises `stream`. */
 int sun_basis_counts(sun_basis b, void* stream, int64_t* nnz_f, int64_t* nnz_d);
 /* Export the nonzero entries of f (which = 0) or d (which = 1) in
- * lexicographic order of (m, n, s): idx device int32[cap][3], val device
- * double[cap].  *written (host) receives the number of entries; if it
+ * lexicographic order of (m, n, s): with canonical = 0 every index order of
+ * the full tensor; with canonical = 1 only m < n < s for f (antisymmetric,
+ * zero when two indices repeat) and m <= n <= s for d (symmetric), from which
+ * the full tensor follows by permutation.  idx device int32[cap][3], val
+ * device double[cap].  *written (host) receives the number of entries; if it
  * exceeds cap, nothing is written and SUN_ERANGE is returned.  Supports
  * N <= 64 (each row of the tensor must have at most 8192 entries). */
-int sun_basis_export(sun_basis b, int32_t which, int32_t* idx, double* val,
+int sun_basis_export(sun_basis b, int32_t which, int32_t canonical, int32_t* idx, double* val,
                      int64_t cap, int64_t* written, void* stream);
 void sun_basis_free(sun_basis b);
 

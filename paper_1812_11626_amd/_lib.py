@@ -45,7 +45,7 @@ PROTOS = {
     "sun_build_basis": (C.c_int, [i32, vp, P(vp)]),
     "sun_basis_dims": (C.c_int, [vp, P(i32), P(i64)]),
     "sun_basis_counts": (C.c_int, [vp, vp, P(i64), P(i64)]),
-    "sun_basis_export": (C.c_int, [vp, i32, vp, vp, i64, P(i64), vp]),
+    "sun_basis_export": (C.c_int, [vp, i32, i32, vp, vp, i64, P(i64), vp]),
     "sun_basis_free": (None, [vp]),
     "sun_expand_operator": (C.c_int, [vp, P(ZCSR), vp, vp, P(f64), vp]),
     "sun_expand_lindbladian": (C.c_int, [vp, P(ZCSR), i32, P(ZCSR), i32, vp, P(vp)]),

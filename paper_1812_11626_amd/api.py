@@ -91,16 +91,19 @@ class Basis:
         check(self._lib.sun_basis_counts(self.handle, _stream(), C.byref(nf), C.byref(nd)))
         return nf.value, nd.value
 
-    def export(self, which: str):
-        """Nonzero entries of f ('f') or d ('d'): (idx int32 (nnz,3), val float64)."""
+    def export(self, which: str, canonical: bool = False):
+        """Nonzero entries of f ('f') or d ('d'): (idx int32 (nnz,3), val
+        float64), all index orders, or with canonical=True only m<n<s (f) /
+        m<=n<=s (d)."""
         w = {"f": 0, "d": 1}[which]
+        c = int(bool(canonical))
         n = C.c_int64()
-        st = self._lib.sun_basis_export(self.handle, w, None, None, 0, C.byref(n), _stream())
+        st = self._lib.sun_basis_export(self.handle, w, c, None, None, 0, C.byref(n), _stream())
         if st not in (_lib.SUN_OK, _lib.SUN_ERANGE):
             check(st)
         idx = torch.empty((max(n.value, 1), 3), dtype=torch.int32, device="cuda")
         val = torch.empty(max(n.value, 1), dtype=torch.float64, device="cuda")
-        check(self._lib.sun_basis_export(self.handle, w, _ptr(idx), _ptr(val), n.value, C.byref(n), _stream()))
+        check(self._lib.sun_basis_export(self.handle, w, c, _ptr(idx), _ptr(val), n.value, C.byref(n), _stream()))
         return idx[: n.value], val[: n.value]
 
     def expand(self, op):

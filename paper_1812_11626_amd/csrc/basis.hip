@@ -105,11 +105,13 @@ __global__ __launch_bounds__(256) void k_count_fd(BasisDev B, unsigned long long
 // Row generator for the export: row a, key = b*M + c, value f or d.
 struct ExportGen {
   BasisDev B;
-  int which;  // 0 = f, 1 = d
+  int which;      // 0 = f, 1 = d
+  int canonical;  // 1: only m < n < s (f) or m <= n <= s (d)
   template <class E>
   __device__ void run(int a, E& emit) const {
     for (int t = 0; t < B.N; ++t) {
       enum_slice(B, a, t, [&](int b, int c, cplx T) {
+        if (canonical && (which == 0 ? !(a < b && b < c) : !(a <= b && b <= c))) return;
         double v = which == 0 ? 2.0 * T.im : 2.0 * T.re;
         if (v != 0.0) emit((uint64_t)b * (uint64_t)B.M + (uint64_t)c, v);
       });
@@ -195,14 +197,15 @@ extern "C" int sun_basis_counts(sun_basis b, void* stream, int64_t* nnz_f, int64
   });
 }
 
-extern "C" int sun_basis_export(sun_basis b, int32_t which, int32_t* idx, double* val, int64_t cap,
-                                int64_t* written, void* stream) {
+extern "C" int sun_basis_export(sun_basis b, int32_t which, int32_t canonical, int32_t* idx, double* val,
+                                int64_t cap, int64_t* written, void* stream) {
   return guarded([&] {
     SUN_REQUIRE(b != nullptr, SUN_EINVAL, "basis is NULL");
     SUN_REQUIRE(which == 0 || which == 1, SUN_EINVAL, "which must be 0 (f) or 1 (d)");
+    SUN_REQUIRE(canonical == 0 || canonical == 1, SUN_EINVAL, "canonical must be 0 or 1");
     SUN_REQUIRE(b->N <= 64, SUN_ENOTSUP, "export supports N <= 64");
     hipStream_t s = as_stream(stream);
-    ExportGen g{b->view(), which};
+    ExportGen g{b->view(), which, canonical};
     DevBuf<int> rowptr;
     DevBuf<uint64_t> key;
     DevBuf<double> v;

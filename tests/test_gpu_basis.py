@@ -42,6 +42,12 @@ def test_export_index_sets_bit_exact(lib, N):
         assert gidx.shape == oidx.shape, (name, gidx.shape, oidx.shape)
         assert np.array_equal(gidx, oidx), name
         np.testing.assert_allclose(gval, oval, rtol=0, atol=1e-14)
+        # canonical subset: m < n < s for f, m <= n <= s for d
+        keep = (oidx[:, 0] < oidx[:, 1]) & (oidx[:, 1] < oidx[:, 2]) if name == "f" else \
+            (oidx[:, 0] <= oidx[:, 1]) & (oidx[:, 1] <= oidx[:, 2])
+        cidx, cval = b.export(name, canonical=True)
+        assert np.array_equal(cidx.cpu().numpy().astype(np.int64), oidx[keep]), name
+        np.testing.assert_allclose(cval.cpu().numpy(), oval[keep], rtol=0, atol=1e-14)
 
 
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 8, 12, 21, 51, 101, 301, 1001])
@@ -57,5 +63,5 @@ def test_export_rejects_small_capacity(lib):
     from paper_1812_11626_amd import _lib
     b = lib.build_basis(4)
     n = ctypes.c_int64()
-    st = _lib.load().sun_basis_export(b.handle, 0, None, None, 3, ctypes.byref(n), None)
+    st = _lib.load().sun_basis_export(b.handle, 0, 0, None, None, 3, ctypes.byref(n), None)
     assert st == _lib.SUN_ERANGE and n.value == 174

@@ -102,13 +102,16 @@ def test_lds_and_global_paths_agree_bitwise(lib):
 
 
 def test_full_workload_sampled_against_plain(lib):
-    """The 512-instance workload (N in {51,...,301}), 24 steps, 3 sampled
-    instances per group against plain single-instance GPU propagation."""
+    """The 512-instance workload (N in {51,...,301}), 24 steps, in the
+    launch configuration the benchmark times (autotuned tiles): 3 sampled
+    instances per group against plain single-instance GPU propagation, and
+    the middle one against the oracle's density-matrix RK4 (eq. 1)."""
     flush("[batched] 512 instances vs plain (sampled)")
     inst = dimer.batched_instances()
     assert len(inst) == 512
     steps = 24
     bp, groups = dimer_batch(lib, inst, steps)
+    lib.autotune_batched(bp, probe_steps=2, use_cache=False)
     for g, (N, idx, _, _, _) in enumerate(groups):
         bp.set_state(g, torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))))
     bp.run(steps)
@@ -121,6 +124,13 @@ def test_full_workload_sampled_against_plain(lib):
             eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
             prop.propagate(v, eps, dt, steps)
             assert rel_vec_err(got[j], v.cpu().numpy()) <= TOL, (N, j)
+        p = inst[idx[len(idx) // 2]]
+        ops = dimer.dimer_operators(p)
+        rho0 = np.zeros((N, N), complex)
+        rho0[0, 0] = 1.0
+        rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho0,
+                         dimer.drive_table(p, steps=steps)[:, None], dt, steps)
+        assert rel_vec_err(got[len(idx) // 2], lb.bloch_vector_sparse(rho)) <= TOL, N
 
 
 def test_autotuner_picks_valid_tiling(lib, tmp_path, monkeypatch):
