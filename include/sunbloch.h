@@ -143,8 +143,11 @@ enum { SUN_TERM_H = 0, SUN_TERM_L = 1 };
  * generated on the fly from their closed forms; nothing of size O(N^3) is
  * stored.  Exact cancellations are dropped from each matrix: entries with
  * |q| <= 1e-12 max|Q| are removed.
- * H terms must be Hermitian (checked to 1e-12 max|H|, else SUN_EINVAL) and
- * L operators traceless (|Tr L| <= 1e-12 max|L|, else SUN_ENOTSUP).
+ * H terms must be Hermitian (checked to 1e-12 max|H|, else SUN_EINVAL).  The
+ * expansion of eqs. 10-11 runs over the traceless generators; an L with a
+ * trace, L = c 1 + L' (c = Tr(L)/N), is handled by the identity
+ * D_L = D_L' - i[H_c, .] with H_c = (i/2)(conj(c) L' - c L'^+): R_p is then
+ * the R of L' plus the Q of H_c (eq. 6), and K_p is unchanged.
  * Limits: every assembled row must have at most 16384 raw contributions
  * (8192 on devices with less than 160 KB of LDS per workgroup; else
  * SUN_ENOTSUP, detected from the per-row counts before any fill); total nnz
@@ -172,7 +175,8 @@ typedef struct sun_prop_s* sun_prop;
  * (dissipators).  The generator is
  *     G(t) = sum_a w_a T_a + sum_{d<ndyn} c_d(t) T_{dyn[d]},
  *     K(t) = sum_{a in L} w_a K_a + sum_{d: dyn[d] in L} c_d(t) K_{dyn[d]}
- * static_w: host double[nH+P]; dyn: host int32[ndyn], ndyn <= 4.
+ * static_w: host double[nH+P] (the weights of dissipators, i.e. their rates,
+ * must be >= 0, else SUN_EINVAL); dyn: host int32[ndyn], ndyn <= 4.
  * Builds the fused device layout (static part merged into one CSR, the
  * free vector folded in as an extra column, then one segment per dynamic
  * term) and the row-block partition of the streaming kernel. */

@@ -333,6 +333,33 @@ struct SpgemmGen {
   }
 };
 
+// Rows of R = -(1/2) Re(B^T A) followed by the entries of the same row of an
+// extra real matrix E (the gauge term of a dissipator with a trace); the row
+// pipeline merges equal columns in a fixed order.
+struct SpgemmPlusGen {
+  SpgemmGen g;
+  const int* eptr;
+  const int* ecol;
+  const double* eval;
+  template <class E>
+  __device__ void run(int s, E& emit) const {
+    g.run(s, emit);
+    for (int e = eptr[s]; e < eptr[s + 1]; ++e)
+      if (eval[e] != 0.0) emit((uint64_t)ecol[e], eval[e]);
+  }
+};
+
+// Expansion of the gauge Hamiltonian H_c = (i/2)(conj(c) L' - c L'^+) of a
+// dissipator L = c 1 + L' (c = Tr(L)/N): h_j = Tr(F_j H_c) = -Im(conj(c) l_j)
+// with l_j = Tr(F_j L) = Tr(F_j L'); the same map on the collapsed diagonal.
+__global__ void k_gauge_coef(int64_t M, int N, const cplx* __restrict__ x, const cplx* __restrict__ xd, cplx c,
+                             cplx* __restrict__ h, cplx* __restrict__ hd) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    h[i] = cx(c.im * x[i].re - c.re * x[i].im, 0.0);
+    if (i < N) hd[i] = cx(c.im * xd[i].re - c.re * xd[i].im, 0.0);
+  }
+}
+
 // K = (1/N) Im(B^T l)
 __global__ void k_free_vector(int64_t M, int N, const int* __restrict__ bptr, const int* __restrict__ bcol,
                               const cplx* __restrict__ bval, const cplx* __restrict__ l,
@@ -445,9 +472,23 @@ void assemble_dissipator(const sun_basis_s& b, const sun_zcsr& L, DevCSR& out, D
                          hipStream_t s) {
   Expansion e;
   expand_operator(b, L, e, false, s);
+  // A trace c = Tr(L)/N is moved into a Hamiltonian term:
+  //   D_{c 1 + L'} = D_{L'} - i[H_c, .],  H_c = (i/2)(conj(c) L' - c L'^+),
+  // and L' has the same coefficients l_j as L (the generators are traceless).
   const double tr = fmax(fabs(e.trace.re), fabs(e.trace.im));
-  SUN_REQUIRE(tr <= 1e-12 * b.N * (e.maxabs > 0 ? e.maxabs : 1.0), SUN_ENOTSUP,
-              "dissipator with nonzero trace (shift L by Tr(L)/N first)");
+  const bool gauge = tr > 1e-12 * b.N * (e.maxabs > 0 ? e.maxabs : 1.0);
+  DevCSR Hc;
+  if (gauge) {
+    const cplx c = cx(e.trace.re / b.N, e.trace.im / b.N);
+    DevBuf<cplx> h(b.M), hd(b.N);
+    hipLaunchKernelGGL(k_gauge_coef, dim3(grid_for(b.M, 256)), dim3(256), 0, s, b.M, b.N, e.x.get(), e.xd.get(),
+                       c, h.get(), hd.get());
+    HIP_LAUNCH_OK();
+    RowAssemblyResult rh = contract<double>(b, e, h.get(), hd.get(), cx(1.0), cx(0.0), 0.0, true, s, Hc.rowptr,
+                                            Hc.col, Hc.val);
+    Hc.rows = b.M;
+    Hc.nnz = rh.nnz;
+  }
   DevBuf<cplx> xc(b.M), xdc(b.N);
   hipLaunchKernelGGL(k_conj, dim3(grid_for(b.M, 256)), dim3(256), 0, s, b.M, e.x.get(), xc.get());
   HIP_LAUNCH_OK();
@@ -463,8 +504,13 @@ void assemble_dissipator(const sun_basis_s& b, const sun_zcsr& L, DevCSR& out, D
   A.rows = b.M;
   A.nnz = ra.nnz;
   SpgemmGen g{BT.rowptr.get(), BT.col.get(), BT.val.get(), A.rowptr.get(), A.col.get(), A.val.get()};
-  RowAssemblyResult rr = assemble_rows<SpgemmGen, double, int>(g, b.M, kRelDrop, true, s, &out.rowptr,
-                                                                out.col, out.val);
+  RowAssemblyResult rr;
+  if (gauge) {
+    SpgemmPlusGen gp{g, Hc.rowptr.get(), Hc.col.get(), Hc.val.get()};
+    rr = assemble_rows<SpgemmPlusGen, double, int>(gp, b.M, kRelDrop, true, s, &out.rowptr, out.col, out.val);
+  } else {
+    rr = assemble_rows<SpgemmGen, double, int>(g, b.M, kRelDrop, true, s, &out.rowptr, out.col, out.val);
+  }
   out.rows = b.M;
   out.nnz = rr.nnz;
   K.alloc(b.M);

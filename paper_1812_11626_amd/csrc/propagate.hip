@@ -887,6 +887,8 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
     SUN_REQUIRE(ndyn == 0 || dyn != nullptr, SUN_EINVAL, "dyn is NULL");
     const int nt = l->nH + l->P;
     SUN_REQUIRE(nt <= kMaxTerms, SUN_ENOTSUP, "at most 32 terms");
+    for (int a = l->nH; a < nt; ++a)
+      SUN_REQUIRE(static_w[a] >= 0.0, SUN_EINVAL, "dissipation rates must be >= 0");
     hipStream_t s = as_stream(stream);
     const int64_t M = l->basis->M;
     auto p = new sun_prop_s();

@@ -27,12 +27,39 @@ def test_non_hermitian_hamiltonian_rejected(lib):
     assert "Hermitian" in str(e.value) and e.value.code == -1
 
 
-def test_dissipator_with_trace_rejected(lib):
+def test_dissipator_with_trace_matches_definition(lib):
+    """A dissipator with a trace (taken through the gauge identity on the GPU)
+    against the oracle's R and K from explicit traces of D_L itself: a dense
+    random L at N = 5 and a banded one at N = 31."""
+    N = 5
+    b = lib.build_basis(N)
+    L = random_ops.random_complex_csr(N, 0.8, seed=2, traceless=False)
+    assert abs(np.trace(L.to_dense())) > 0.1
+    lind = lib.Lindbladian(b, [], [L])
+    rp, c, v, K = lind.export("L", 0)
+    F = ob.generators(N)
+    assert rel_matrix_err(to_scipy(rp, c, v, N * N - 1), lb.q_dissipator(F, L.to_dense())) <= 1e-12
+    assert rel_vec_err(K.cpu().numpy(), lb.k_dissipator(F, L.to_dense())) <= 1e-12
+    N = 31
+    rng = np.random.default_rng(8)
+    diags = {k: rng.standard_normal(N - abs(k)) + 1j * rng.standard_normal(N - abs(k)) for k in (-1, 0, 1)}
+    diags[0] = diags[0] + (2.0 - 0.5j)                 # a sizeable trace
+    Lb = dimer.ZCSR.from_diagonals(N, diags)
+    lind = lib.Lindbladian(lib.build_basis(N), [], [Lb])
+    rp, c, v, K = lind.export("L", 0)
+    M = N * N - 1
+    assert rel_matrix_err(to_scipy(rp, c, v, M), lb.q_full("L", Lb)) <= 1e-12
+    assert rel_vec_err(K.cpu().numpy(), lb.k_vector(Lb)) <= 1e-12
+
+
+def test_negative_rate_rejected(lib):
+    p = dimer.plain_config(4)
+    ops = dimer.dimer_operators(p)
     b = lib.build_basis(4)
-    L = random_ops.random_complex_csr(4, 0.8, seed=2, traceless=False)
+    lind = lib.Lindbladian(b, [ops["H0"], ops["H1"]], [ops["L"]])
     with pytest.raises(lib.SunError) as e:
-        lib.Lindbladian(b, [], [L])
-    assert e.value.code == -4
+        lind.propagator([1.0, 0.0, -0.1], [1])
+    assert e.value.code == -1
 
 
 def test_malformed_csr_rejected(lib):

@@ -126,6 +126,11 @@ def test_sparse_tier_matches_dense_tier(N):
     np.testing.assert_allclose(lb.k_vector(L), Kd, atol=1e-13)
     cols = [0, N * N - 2, N]
     np.testing.assert_allclose(lb.q_columns("L", L, cols), Rd[:, cols], atol=1e-12)
+    # a dissipator with a trace, taken by both tiers from the definition
+    Lt = random_ops.random_complex_csr(N, 0.6, seed=41 + N, traceless=False)
+    assert abs(np.trace(Lt.to_dense())) > 1e-3
+    np.testing.assert_allclose(lb.q_full("L", Lt).toarray(), lb.q_dissipator(F, Lt.to_dense()), atol=1e-12)
+    np.testing.assert_allclose(lb.k_vector(Lt), lb.k_dissipator(F, Lt.to_dense()), atol=1e-13)
 
 
 @pytest.mark.parametrize("N", [4, 11])
@@ -183,3 +188,25 @@ def test_entrywise_density_matches_generator_sum(N):
     assert abs(np.trace(rho) - 1) < 1e-14
     np.testing.assert_array_equal(rho, rho.conj().T)
     np.testing.assert_allclose(lb.bloch_vector(F, rho), v, atol=1e-14)
+
+
+def test_gauge_identity_for_dissipator_with_trace():
+    """For L = c 1 + L' (c = Tr L / N): D_L(X) = D_L'(X) - i[H_c, X] with
+    H_c = (i/2)(conj(c) L' - c L'^+) Hermitian, for a random X; hence the
+    Bloch matrices satisfy R(L) = R(L') + Q(H_c) and K(L) = K(L')."""
+    N = 4
+    rng = np.random.default_rng(12)
+    L = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    c = np.trace(L) / N
+    Lp = L - c * np.eye(N)
+    Hc = 0.5j * (np.conj(c) * Lp - c * Lp.conj().T)
+    np.testing.assert_allclose(Hc, Hc.conj().T, atol=1e-15)
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    np.testing.assert_allclose(lb.dissipator(L, X), lb.dissipator(Lp, X) - 1j * (Hc @ X - X @ Hc), atol=1e-13)
+    F = basis.generators(N)
+    np.testing.assert_allclose(lb.q_dissipator(F, L), lb.q_dissipator(F, Lp) + lb.q_hamiltonian(F, Hc), atol=1e-13)
+    np.testing.assert_allclose(lb.k_dissipator(F, L), lb.k_dissipator(F, Lp), atol=1e-14)
+    # the coefficients of H_c follow from those of L: h_j = -Im(conj(c) l_j)
+    l = lb.expand(F, L)
+    np.testing.assert_allclose(lb.expand(F, Hc).real, -np.imag(np.conj(c) * l), atol=1e-14)
+
