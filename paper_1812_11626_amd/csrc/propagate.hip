@@ -515,8 +515,7 @@ __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restr
   a1 = s1;
 }
 
-// One wavefront per `spw` consecutive slices or long rows.  Workgroups of 4
-// wavefronts.
+// One wavefront per slice (or per long row).  Workgroups of 4 wavefronts.
 template <int STAGE, int U, bool NTL>
 __global__ __launch_bounds__(256) void k_rk4_sell(
     const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
@@ -525,7 +524,7 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     const int* __restrict__ long_rows, int64_t nlong, const int* __restrict__ rowptr, const int* __restrict__ seg,
     const int* __restrict__ col, const double* __restrict__ val, int ndyn,
     const double* __restrict__ xin, const double* v, double* acc, double* xout,
-    const double* __restrict__ coef, int64_t coef_row, double dt, int xcd_remap, int spw) {
+    const double* __restrict__ coef, int64_t coef_row, double dt, int xcd_remap) {
   const int lane = threadIdx.x & 63;
   // Workgroups are dispatched round-robin over the 8 XCDs; with xcd_remap
   // each XCD takes one contiguous range of slices, so the x entries its
@@ -536,55 +535,51 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     blk = (blk & 7) * q + (blk >> 3);
   }
   // wavefront index, made explicitly uniform so that slice metadata become
-  // scalar loads and width tests scalar branches; each wavefront takes the
-  // `spw` consecutive work items (slices, then long rows) starting at spw*wid
+  // scalar loads and width tests scalar branches
   const int64_t wid = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double eps = ndyn ? coef[coef_row] : 0.0;
-  const int64_t it_end = min((wid + 1) * spw, nslices + nlong);
-  for (int64_t it = wid * spw; it < it_end; ++it) {
-    if (it < nslices) {
-      const int64_t i = it * kSlice + lane;
-      const int off = __builtin_amdgcn_readfirstlane(sell_off[it]);
-      const int wd = (__builtin_amdgcn_readfirstlane(sell_off[it + 1]) - off) / kSlice;   // slice width
-      const int coff = __builtin_amdgcn_readfirstlane(sell_coff[it]);
-      const bool own = i < nshort;
-      const int r = own ? sell_row[i] : 0;
-      const int lens = sell_len[i];
-      const int slen = lens & 0xFFFF, len = lens >> 16;
-      double vr = 0.0, ar = 0.0;
-      if (own) {
-        vr = v[r];
-        if (reads_acc<STAGE>()) ar = acc[r];
-      }
-      const unsigned char* cb = cb_all + (coff & ~63);
-      const int* gbase = gbase_all + off / kSlice;
-      const double* vp = sval + off + lane;
-      double a0 = 0.0, a1 = 0.0;
-      switch (coff & 3) {
-        case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-        case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-        default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      }
-      if (own) stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
-    } else {
-      const int r = long_rows[it - nslices];
-      const int a = rowptr[r], z = rowptr[r + 1];
-      const int sb = ndyn ? seg[r] : z;
-      double a0 = 0.0, a1 = 0.0;
-      for (int e = a + lane; e < z; e += 64) {
-        const double pr = val[e] * xin[col[e]];
-        a0 += e < sb ? pr : 0.0;
-        a1 += e < sb ? 0.0 : pr;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        a0 += __shfl_down(a0, o, 64);
-        a1 += __shfl_down(a1, o, 64);
-      }
-      if (lane == 0) {
-        const double vr = v[r];
-        const double ar = reads_acc<STAGE>() ? acc[r] : 0.0;
-        stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
-      }
+  if (wid < nslices) {
+    const int64_t i = wid * kSlice + lane;
+    const int off = __builtin_amdgcn_readfirstlane(sell_off[wid]);
+    const int wd = (__builtin_amdgcn_readfirstlane(sell_off[wid + 1]) - off) / kSlice;   // slice width
+    const int coff = __builtin_amdgcn_readfirstlane(sell_coff[wid]);
+    const bool own = i < nshort;
+    const int r = own ? sell_row[i] : 0;
+    const int lens = sell_len[i];
+    const int slen = lens & 0xFFFF, len = lens >> 16;
+    double vr = 0.0, ar = 0.0;
+    if (own) {
+      vr = v[r];
+      if (reads_acc<STAGE>()) ar = acc[r];
+    }
+    const unsigned char* cb = cb_all + (coff & ~63);
+    const int* gbase = gbase_all + off / kSlice;
+    const double* vp = sval + off + lane;
+    double a0 = 0.0, a1 = 0.0;
+    switch (coff & 3) {
+      case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+    }
+    if (own) stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
+  } else if (wid < nslices + nlong) {
+    const int r = long_rows[wid - nslices];
+    const int a = rowptr[r], z = rowptr[r + 1];
+    const int sb = ndyn ? seg[r] : z;
+    double a0 = 0.0, a1 = 0.0;
+    for (int e = a + lane; e < z; e += 64) {
+      const double pr = val[e] * xin[col[e]];
+      a0 += e < sb ? pr : 0.0;
+      a1 += e < sb ? 0.0 : pr;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      a0 += __shfl_down(a0, o, 64);
+      a1 += __shfl_down(a1, o, 64);
+    }
+    if (lane == 0) {
+      const double vr = v[r];
+      const double ar = reads_acc<STAGE>() ? acc[r] : 0.0;
+      stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
     }
   }
 }
@@ -778,13 +773,15 @@ template <int STAGE>
 void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
                     const double* coef, int64_t row, double dt, hipStream_t s) {
   if (p.layout == 1) {
-    const int64_t waves = (p.nslices + p.nlong + p.sell_spw - 1) / p.sell_spw;
+    const int64_t waves = p.nslices + p.nlong;
     unsigned grid = (unsigned)((waves + 3) / 4);
     if (p.sell_remap) grid = (grid + 7) / 8 * 8;
     auto kern = k_rk4_sell<STAGE, 8, false>;
     switch (p.sell_unroll * 2 + p.sell_nt) {
       case 8: kern = k_rk4_sell<STAGE, 4, false>; break;
       case 9: kern = k_rk4_sell<STAGE, 4, true>; break;
+      case 12: kern = k_rk4_sell<STAGE, 6, false>; break;
+      case 13: kern = k_rk4_sell<STAGE, 6, true>; break;
       case 17: kern = k_rk4_sell<STAGE, 8, true>; break;
       case 24: kern = k_rk4_sell<STAGE, 12, false>; break;
       case 25: kern = k_rk4_sell<STAGE, 12, true>; break;
@@ -795,7 +792,7 @@ void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, d
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
                        p.sell_base.get(), p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_val.get(),
                        p.nslices, p.nshort, p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(),
-                       p.val.get(), p.ndyn, xin, vin, acc, xout, coef, row, dt, p.sell_remap, p.sell_spw);
+                       p.val.get(), p.ndyn, xin, vin, acc, xout, coef, row, dt, p.sell_remap);
     return;
   }
   switch (p.threads) {
@@ -992,14 +989,12 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     p->sigma = sigma;
     p->long_len = long_len;
     p->min_col_bytes = min_col_bytes;
-    const int spw = (flags >> 8) & 0xFF;
     const int u = (flags >> 16) & 0xFF;
-    SUN_REQUIRE(u == 0 || u == 4 || u == 8 || u == 12 || u == 16, SUN_EINVAL,
-                "entries per load round (flags bits 16-23) must be 0, 4, 8, 12 or 16");
-    SUN_REQUIRE((flags & ~0xFFFF03) == 0, SUN_EINVAL, "unknown flag bits");
+    SUN_REQUIRE(u == 0 || u == 4 || u == 6 || u == 8 || u == 12 || u == 16, SUN_EINVAL,
+                "entries per load round (flags bits 16-23) must be 0, 4, 6, 8, 12 or 16");
+    SUN_REQUIRE((flags & ~0xFF0003) == 0, SUN_EINVAL, "unknown flag bits");
     p->sell_remap = (flags & 1) ? 1 : 0;
     p->sell_nt = (flags & 2) ? 1 : 0;
-    p->sell_spw = spw >= 1 ? spw : 1;
     p->sell_unroll = u ? u : 8;
     p->layout = 1;
     build_sell(*p, as_stream(stream));

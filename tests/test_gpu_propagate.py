@@ -211,9 +211,9 @@ def test_sliced_layout_matches_stream_layout(lib):
 
 
 def test_sliced_kernel_variants_are_bitwise_identical(lib):
-    """XCD remapping, load hints, slices per wavefront and entries per load
-    round change only which wavefront handles a slice and how its loads are
-    issued, never the order of a row's sum: results are bitwise equal."""
+    """XCD remapping, load hints and entries per load round change only which
+    wavefront handles a slice and how its loads are issued, never the order
+    of a row's sum: results are bitwise equal."""
     N = 101
     flush(f"[propagate] sliced variants N={N}")
     p = dimer.plain_config(N)
@@ -225,8 +225,8 @@ def test_sliced_kernel_variants_are_bitwise_identical(lib):
     prop.tune_sliced()
     ref = v0.clone()
     prop.propagate(ref, eps, p.dt, steps)
-    for kw in (dict(xcd_remap=False), dict(nontemporal=True), dict(slices_per_wave=3), dict(unroll=4),
-               dict(unroll=12), dict(unroll=16, nontemporal=True), dict(slices_per_wave=2, xcd_remap=False)):
+    for kw in (dict(xcd_remap=False), dict(nontemporal=True), dict(unroll=4), dict(unroll=12),
+               dict(unroll=16, nontemporal=True), dict(unroll=4, xcd_remap=False)):
         prop.tune_sliced(**kw)
         v = v0.clone()
         prop.propagate(v, eps, p.dt, steps)
