@@ -280,10 +280,11 @@ int sun_batch_get_state(sun_batch b, int32_t g, double* V, void* stream);
 int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream);
 /* Per-group tiling.  tile = instances per lane group (8, 16, 32 or 64; a
  * lane group of `tile` lanes sums one row for `tile` instances).  path 0
- * (default): one workgroup per block of at most min(rows_per_item, 128) rows
- * and 1024 stored entries, whose columns, values and row/segment pointers
- * are staged in LDS once and reused for every instance tile; taken when
- * every row of the group has at most 1024 entries, else path 1.  path 1: one
+ * (default): one workgroup per (instance tile, block of at most
+ * min(rows_per_item, 128) rows and 1024 stored entries), the block's
+ * columns, values and row/segment pointers staged in LDS; each XCD sweeps
+ * its own eighth of every group's (tile, block) items in tile-major order;
+ * taken when every row of the group has at most 1024 entries, else path 1.  path 1: one
  * wavefront per (block of rows_per_item rows, instance tile), reading the
  * matrix from global memory.  Defaults 64, 64, 0.  Both paths add every
  * term's entries in row order: results do not depend on the tiling or path. */

@@ -50,7 +50,6 @@ struct GroupDev {
   int64_t item0;         // first work item of this group (per-wavefront path)
   const int* blk_row;    // LDS path: row blocks [blk_row[i], blk_row[i+1])
   int nblk;              // LDS path: number of row blocks (0: per-wavefront path)
-  int64_t bitem0;        // LDS path: first work item of this group
 };
 
 }  // namespace
@@ -209,42 +208,66 @@ __global__ __launch_bounds__(256) void k_batch_stage(const GroupDev* __restrict_
   }
 }
 
-// LDS path: one workgroup per block of rows (at most kLdsRows rows and
-// kLdsCap stored entries).  The block's columns, values, row and segment
-// pointers are staged in LDS once and reused for every instance tile, so the
-// gathers of a row wait only on LDS reads; each lane group of T lanes sums
-// one row for T instances, term by term in row order (the same order and
-// arithmetic as k_batch_stage).
+// LDS path: one workgroup per (instance tile, block of rows), the block at
+// most kLdsRows rows and kLdsCap stored entries.  The block's columns,
+// values, row and segment pointers are staged in LDS, so the gathers of a row
+// wait only on LDS reads; each lane group of T lanes sums one row for T
+// instances, term by term in row order (the same order and arithmetic as
+// k_batch_stage).
 constexpr int kLdsCap = 1024;
 constexpr int kLdsRows = 128;
 
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restrict__ groups,
                                                          const int* __restrict__ gorder, int nactive,
-                                                         int64_t nitems, const int64_t* __restrict__ step) {
+                                                         const int64_t* __restrict__ step) {
   __shared__ int s_col[kLdsCap];
   __shared__ double s_val[kLdsCap];
   __shared__ int s_rp[kLdsRows + 1];
   __shared__ int s_seg[kLdsRows * kMaxBTerms];
   const int tid = threadIdx.x;
-  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // Work item = (instance tile, row block) of one group, numbered tile-major.
+  // Workgroups are dispatched round-robin over the 8 XCDs (blockIdx % 8); XCD
+  // x takes the x-th eighth of every active group's items and walks it in
+  // order, so it sweeps the rows of one instance tile: the state rows that
+  // neighbouring rows gather (T doubles each) stay in its L2.  The grid is a
+  // multiple of 8.
+  const int x = blockIdx.x & 7;
+  const int64_t K = gridDim.x >> 3;
+  int64_t total = 0;
+  for (int q = 0; q < nactive; ++q) {
+    const GroupDev& G = groups[gorder[q]];
+    const int64_t n = (int64_t)G.nblk * G.tiles;
+    total += n * (x + 1) / 8 - n * x / 8;
+  }
+  for (int64_t i = blockIdx.x >> 3; i < total; i += K) {
     int gi = 0;
-    for (int q = 1; q < nactive; ++q)
-      if (groups[gorder[q]].bitem0 <= it) gi = q;
+    int64_t j = i, lo = 0;
+    for (;;) {
+      const GroupDev& G = groups[gorder[gi]];
+      const int64_t n = (int64_t)G.nblk * G.tiles;
+      lo = n * x / 8;
+      const int64_t cnt = n * (x + 1) / 8 - lo;
+      if (j < cnt || gi + 1 == nactive) break;
+      j -= cnt;
+      ++gi;
+    }
     const GroupDev& G = groups[gorder[gi]];
-    const int blk = (int)(it - G.bitem0);
+    const int64_t local = lo + j;
+    const int tb = (int)(local / G.nblk);
+    const int blk = (int)(local % G.nblk);
     const int r0 = G.blk_row[blk], r1 = G.blk_row[blk + 1];
     const int nr = r1 - r0;
     const int e0 = G.rowptr[r0];
     const int ne = G.rowptr[r1] - e0;
     const int nt = G.nt;
     __syncthreads();   // the previous item's LDS contents are no longer read
-    for (int i = tid; i < ne; i += 256) {
-      s_col[i] = G.col[e0 + i];
-      s_val[i] = G.val[e0 + i];
+    for (int i2 = tid; i2 < ne; i2 += 256) {
+      s_col[i2] = G.col[e0 + i2];
+      s_val[i2] = G.val[e0 + i2];
     }
-    for (int i = tid; i <= nr; i += 256) s_rp[i] = G.rowptr[r0 + i] - e0;
-    for (int i = tid; i < nr * nt; i += 256) s_seg[i] = G.segptr[(int64_t)r0 * nt + i] - e0;
+    for (int i2 = tid; i2 <= nr; i2 += 256) s_rp[i2] = G.rowptr[r0 + i2] - e0;
+    for (int i2 = tid; i2 < nr * nt; i2 += 256) s_seg[i2] = G.segptr[(int64_t)r0 * nt + i2] - e0;
     __syncthreads();
     const int T = G.tile;
     const int ngrp = 256 / T, lg = tid / T, bl = tid % T;
@@ -254,7 +277,7 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
     const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
     double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
     const int ld = G.ld;
-    for (int tb = 0; tb < G.tiles; ++tb) {
+    {
       const int b = tb * T + bl;
       double coefb[kMaxBTerms];
 #pragma unroll
@@ -334,15 +357,12 @@ void refresh_items(sun_batch_s& bt) {
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
     G.tiles = (G.B + G.tile - 1) / G.tile;
   }
-  int64_t bitem = 0;
   for (int gi : bt.order) {
     GroupDev& G = bt.ghost[gi];
     G.nblk = bt.nblk[gi];
     G.blk_row = bt.blk_row[gi].get();
     G.item0 = item;
-    G.bitem0 = bitem;
-    if (G.nblk > 0) bitem += G.nblk;
-    else item += (int64_t)G.row_blocks * G.tiles;
+    if (G.nblk == 0) item += (int64_t)G.row_blocks * G.tiles;
   }
 }
 
@@ -588,7 +608,7 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     for (int q = 0; q < bt->ngroups; ++q) {
       const GroupDev& G = bt->ghost[ord[q]];
       items_upto[q + 1] = items_upto[q] + wave_items(G);
-      blocks_upto[q + 1] = blocks_upto[q] + G.nblk;
+      blocks_upto[q + 1] = blocks_upto[q] + (int64_t)G.nblk * G.tiles;
     }
     // the step index of every group lives in a device table: one row per step
     std::vector<int64_t> table((size_t)maxn * bt->ngroups);
@@ -605,7 +625,7 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       const int64_t nitems = items_upto[nactive];
       const int64_t nblocks = blocks_upto[nactive];
       const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((nitems + 3) / 4, (int64_t)ncu * 8));
-      const int64_t bgrid = std::max<int64_t>(1, std::min<int64_t>(nblocks, (int64_t)ncu * 8));
+      const int64_t bgrid = std::max<int64_t>(8, (std::min<int64_t>(nblocks, (int64_t)ncu * 8) + 7) / 8 * 8);
       const int64_t* st = steptab.get() + n * bt->ngroups;
       const GroupDev* gd = bt->gdev.get();
       const int* go = gorder.get();
@@ -613,25 +633,25 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
         hipLaunchKernelGGL(k_batch_stage<0>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<0>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+        hipLaunchKernelGGL(k_batch_stage_lds<0>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
       }
       if (nitems > 0) {
         hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<1>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+        hipLaunchKernelGGL(k_batch_stage_lds<1>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
       }
       if (nitems > 0) {
         hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<2>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+        hipLaunchKernelGGL(k_batch_stage_lds<2>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
       }
       if (nitems > 0) {
         hipLaunchKernelGGL(k_batch_stage<3>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<3>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, nblocks, st);
+        hipLaunchKernelGGL(k_batch_stage_lds<3>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
       }
     }
     HIP_LAUNCH_OK();
