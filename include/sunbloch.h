@@ -261,7 +261,7 @@ typedef struct sun_batch_s* sun_batch;
  * wave[g]: device double[2*steps[g]+1]; dt, steps: host arrays.  The library
  * keeps pointers to w, u and wave (they must outlive the object).  Each group
  * gets a fused row layout with one segment per term and a state of
- * (M_g+1) x ld_g doubles per buffer (4 buffers, ld_g = B[g] rounded up to 64).
+ * (M_g+1) x ld_g doubles per buffer (4 buffers, ld_g = B[g] rounded up to 128).
  * States start at zero; set them with sun_batch_set_state.  Synchronises. */
 int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int32_t* B,
                      const double* const* w, const double* const* u,
@@ -279,7 +279,8 @@ int sun_batch_get_state(sun_batch b, int32_t g, double* V, void* stream);
  * Synchronises at the end. */
 int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream);
 /* Per-group tiling.  tile = instances per lane group (8, 16, 32 or 64; a
- * lane group of `tile` lanes sums one row for `tile` instances).  path 0
+ * lane group of `tile` lanes sums one row for `tile` instances; 128: 64
+ * lanes with two consecutive instances each, on the LDS path, else 64).  path 0
  * (default): one workgroup per (instance tile, block of at most
  * min(rows_per_item, 128) rows and 1024 stored entries), the block's
  * columns, values and row/segment pointers staged in LDS; each XCD sweeps

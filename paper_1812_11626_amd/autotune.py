@@ -1,7 +1,9 @@
 """Autotuner for the batched propagator's per-group tiling.
 
 For every group it times a few RK4 steps of that group alone for each
-(tile, rows_per_item) candidate and keeps the fastest.  Results are cached in
+(tile, rows_per_item) candidate and keeps the fastest; then it times the
+whole batch with those choices against a few uniform tilings and keeps the
+fastest of these.  Results are cached in
 a JSON file keyed by device name, N, number of instances and number of terms
 (path from $SUN_AUTOTUNE_CACHE, default ~/.cache/sunbloch/autotune.json).
 The tiling never changes the numbers, only the speed.
@@ -15,8 +17,9 @@ import time
 
 import torch
 
-TILES = (16, 32, 64)
+TILES = (16, 32, 64, 128)
 ROWS = (32, 64, 128)
+UNIFORM = ((128, 64), (128, 32), (64, 64))
 
 
 def cache_path() -> str:
@@ -45,7 +48,7 @@ def _save(path, data):
 
 def _key(G) -> str:
     name = torch.cuda.get_device_name(0).replace(" ", "_")
-    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds"
+    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds2"
 
 
 def autotune_batched(bp, tiles=TILES, rows=ROWS, probe_steps: int = 6, use_cache: bool = True,
@@ -82,6 +85,38 @@ def autotune_batched(bp, tiles=TILES, rows=ROWS, probe_steps: int = 6, use_cache
         cache[key] = {"tile": t, "rows_per_item": r}
         if log:
             log(f"autotune group {g} (N={G['N']}, B={G['B']}): tile={t} rows={r}")
+    # Whole-batch check: the per-group choices against a few uniform tilings,
+    # timed on all groups together (one launch per stage covers every group,
+    # and mixing 128-instance tiles with narrower ones costs a second launch).
+    bkey = "batch|" + ";".join(_key(G) for G in bp.groups)
+    if use_cache and bkey in cache:
+        pick = cache[bkey]
+    else:
+        saved = [bp.get_state(g) for g in range(len(bp.groups))]
+        steps = min(probe_steps, max(1, min(G["steps"] for G in bp.groups)))
+        cands = [[(chosen[g]["tile"], chosen[g]["rows_per_item"]) for g in range(len(bp.groups))]]
+        cands += [[(t, r)] * len(bp.groups) for (t, r) in UNIFORM if t in tiles]
+        best = None
+        for cand in cands:
+            for g, (t, r) in enumerate(cand):
+                bp.tune(g, t, r)
+                bp.set_state(g, saved[g])
+            bp.run(1)                                  # warm
+            t0 = time.perf_counter()
+            bp.run(steps)
+            el = time.perf_counter() - t0
+            if best is None or el < best[0]:
+                best = (el, cand)
+        pick = [list(x) for x in best[1]]
+        for g in range(len(bp.groups)):
+            bp.set_state(g, saved[g])
+        cache[bkey] = pick
+    for g, (t, r) in enumerate(pick):
+        bp.tune(g, t, r)
+        if (t, r) != (chosen[g]["tile"], chosen[g]["rows_per_item"]):
+            chosen[g] = {"tile": t, "rows_per_item": r, "cached": chosen[g]["cached"], "whole_batch": True}
+            if log:
+                log(f"autotune group {g}: whole-batch choice tile={t} rows={r}")
     if use_cache:
         _save(path, cache)
     return chosen

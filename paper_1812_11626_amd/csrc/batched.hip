@@ -50,6 +50,7 @@ struct GroupDev {
   int64_t item0;         // first work item of this group (per-wavefront path)
   const int* blk_row;    // LDS path: row blocks [blk_row[i], blk_row[i+1])
   int nblk;              // LDS path: number of row blocks (0: per-wavefront path)
+  int vec;               // LDS path: instances per lane (2 for 128-instance tiles)
 };
 
 }  // namespace
@@ -217,7 +218,148 @@ __global__ __launch_bounds__(256) void k_batch_stage(const GroupDev* __restrict_
 constexpr int kLdsCap = 1024;
 constexpr int kLdsRows = 128;
 
+// Row stride of the LDS table of tile coefficients c_a(t) (a tile has at most
+// 128 instances: T, one per lane, or 128, two per lane).
+constexpr int kCfStride = 128;
+
+// Stage arithmetic of one state element: returns the new xout, and the new
+// accumulator through acc_out (stages 0-2).
 template <int STAGE>
+__device__ inline double lds_stage(double vr, double ar, double ysum, double dt, double& acc_out) {
+  if (STAGE == 0) {
+    acc_out = ysum;
+    return vr + (0.5 * dt) * ysum;
+  } else if (STAGE == 1) {
+    acc_out = ar + 2.0 * ysum;
+    return vr + (0.5 * dt) * ysum;
+  } else if (STAGE == 2) {
+    acc_out = ar + 2.0 * ysum;
+    return vr + dt * ysum;
+  } else {
+    return vr + (dt / 6.0) * (ar + ysum);
+  }
+}
+
+// One instance tile (T lanes per row, one instance per lane) over the rows
+// of the block staged in LDS.
+template <int STAGE>
+__device__ inline void lds_rows(const GroupDev& G, int64_t k0, int tb, int r0, int nr, const int* s_col,
+                                const double* s_val, const int* s_rp, const int* s_seg, const double* s_cf) {
+  const int tid = threadIdx.x;
+  const int T = G.tile;
+  const int ngrp = 256 / T, lg = tid / T, bl = tid % T;
+  const int nt = G.nt;
+  const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+  const double ph = G.wave[k0 + krow];
+  const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
+  double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
+  const int ld = G.ld;
+  const int b = tb * T + bl;
+  const double* xb = xin + b;
+  (void)ph;
+  for (int lr = lg; lr < nr; lr += ngrp) {
+    const int ee = s_rp[lr + 1];
+    // the row's own state entries are loaded before its gathers
+    const int64_t ix = (int64_t)(r0 + lr) * ld + b;
+    const bool own = b < G.B;
+    const double vr = own ? G.v[ix] : 0.0;
+    const double ar = (own && STAGE != 0) ? G.acc[ix] : 0.0;
+    double ysum = 0.0;
+    for (int a = 0; a < nt; ++a) {
+      const int s0 = s_seg[lr * nt + a];
+      const int s1 = (a + 1 < nt) ? s_seg[lr * nt + a + 1] : ee;
+      double sacc = 0.0;
+      int e = s0;
+      for (; e + 4 <= s1; e += 4) {
+        const int c0 = s_col[e], c1 = s_col[e + 1], c2 = s_col[e + 2], c3 = s_col[e + 3];
+        const double v0 = s_val[e], v1 = s_val[e + 1], v2 = s_val[e + 2], v3 = s_val[e + 3];
+        const double x0 = xb[(int64_t)c0 * ld], x1 = xb[(int64_t)c1 * ld];
+        const double x2 = xb[(int64_t)c2 * ld], x3 = xb[(int64_t)c3 * ld];
+        sacc += v0 * x0;
+        sacc += v1 * x1;
+        sacc += v2 * x2;
+        sacc += v3 * x3;
+      }
+      for (; e < s1; ++e) sacc += s_val[e] * xb[(int64_t)s_col[e] * ld];
+      ysum += s_cf[a * kCfStride + bl] * sacc;
+    }
+    if (own) {
+      double an = 0.0;
+      xout[ix] = lds_stage<STAGE>(vr, ar, ysum, G.dt, an);
+      if (STAGE != 3) G.acc[ix] = an;
+    }
+  }
+}
+
+// Tile of 128 instances: 64 lanes per row, two consecutive instances per
+// lane (16-byte gathers, half the memory instructions per byte).  Each
+// instance's sums are formed in the same order as in lds_rows.
+template <int STAGE>
+__device__ inline void lds_rows_vec2(const GroupDev& G, int64_t k0, int tb, int r0, int nr, const int* s_col,
+                                     const double* s_val, const int* s_rp, const int* s_seg, const double* s_cf) {
+  const int tid = threadIdx.x;
+  const int lg = tid >> 6, lane = tid & 63;
+  const int nt = G.nt;
+  const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+  const double ph = G.wave[k0 + krow];
+  const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
+  double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
+  const int ld = G.ld;                 // a multiple of 128
+  const int b = tb * 128 + 2 * lane;   // instances b and b + 1
+  (void)ph;
+  const double2* xb = reinterpret_cast<const double2*>(xin + b);
+  const int ld2 = ld / 2;
+  for (int lr = lg; lr < nr; lr += 4) {
+    const int ee = s_rp[lr + 1];
+    const int64_t ix = (int64_t)(r0 + lr) * ld + b;
+    const bool own0 = b < G.B, own1 = b + 1 < G.B;
+    const double2 vr = (own0 || own1) ? *reinterpret_cast<const double2*>(G.v + ix) : make_double2(0.0, 0.0);
+    const double2 ar = ((own0 || own1) && STAGE != 0) ? *reinterpret_cast<const double2*>(G.acc + ix)
+                                                        : make_double2(0.0, 0.0);
+    double y0 = 0.0, y1 = 0.0;
+    for (int a = 0; a < nt; ++a) {
+      const int s0 = s_seg[lr * nt + a];
+      const int s1 = (a + 1 < nt) ? s_seg[lr * nt + a + 1] : ee;
+      double p0 = 0.0, p1 = 0.0;
+      int e = s0;
+      for (; e + 4 <= s1; e += 4) {
+        const int c0 = s_col[e], c1 = s_col[e + 1], c2 = s_col[e + 2], c3 = s_col[e + 3];
+        const double v0 = s_val[e], v1 = s_val[e + 1], v2 = s_val[e + 2], v3 = s_val[e + 3];
+        const double2 x0 = xb[(int64_t)c0 * ld2], x1 = xb[(int64_t)c1 * ld2];
+        const double2 x2 = xb[(int64_t)c2 * ld2], x3 = xb[(int64_t)c3 * ld2];
+        p0 += v0 * x0.x;
+        p1 += v0 * x0.y;
+        p0 += v1 * x1.x;
+        p1 += v1 * x1.y;
+        p0 += v2 * x2.x;
+        p1 += v2 * x2.y;
+        p0 += v3 * x3.x;
+        p1 += v3 * x3.y;
+      }
+      for (; e < s1; ++e) {
+        const double v = s_val[e];
+        const double2 xx = xb[(int64_t)s_col[e] * ld2];
+        p0 += v * xx.x;
+        p1 += v * xx.y;
+      }
+      const double2 cf = *reinterpret_cast<const double2*>(s_cf + a * kCfStride + 2 * lane);
+      y0 += cf.x * p0;
+      y1 += cf.y * p1;
+    }
+    double a0 = 0.0, a1 = 0.0;
+    const double o0 = lds_stage<STAGE>(vr.x, ar.x, y0, G.dt, a0);
+    const double o1 = lds_stage<STAGE>(vr.y, ar.y, y1, G.dt, a1);
+    if (own0 && own1) {
+      *reinterpret_cast<double2*>(xout + ix) = make_double2(o0, o1);
+      if (STAGE != 3) *reinterpret_cast<double2*>(G.acc + ix) = make_double2(a0, a1);
+    } else if (own0) {
+      xout[ix] = o0;
+      if (STAGE != 3) G.acc[ix] = a0;
+    }
+  }
+}
+
+template <int STAGE, int VEC>
 __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restrict__ groups,
                                                          const int* __restrict__ gorder, int nactive,
                                                          const int64_t* __restrict__ step) {
@@ -225,27 +367,27 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
   __shared__ double s_val[kLdsCap];
   __shared__ int s_rp[kLdsRows + 1];
   __shared__ int s_seg[kLdsRows * kMaxBTerms];
+  extern __shared__ double s_cf[];                   // c_a(t) of the tile's instances, [nt][kCfStride]
   const int tid = threadIdx.x;
   // Work item = (instance tile, row block) of one group, numbered tile-major.
   // Workgroups are dispatched round-robin over the 8 XCDs (blockIdx % 8); XCD
   // x takes the x-th eighth of every active group's items and walks it in
   // order, so it sweeps the rows of one instance tile: the state rows that
   // neighbouring rows gather (T doubles each) stay in its L2.  The grid is a
-  // multiple of 8.
+  // multiple of 8.  This kernel takes the groups with VEC instances per lane.
   const int x = blockIdx.x & 7;
   const int64_t K = gridDim.x >> 3;
+  auto items = [&](const GroupDev& G) -> int64_t { return G.vec == VEC ? (int64_t)G.nblk * G.tiles : 0; };
   int64_t total = 0;
   for (int q = 0; q < nactive; ++q) {
-    const GroupDev& G = groups[gorder[q]];
-    const int64_t n = (int64_t)G.nblk * G.tiles;
+    const int64_t n = items(groups[gorder[q]]);
     total += n * (x + 1) / 8 - n * x / 8;
   }
   for (int64_t i = blockIdx.x >> 3; i < total; i += K) {
     int gi = 0;
     int64_t j = i, lo = 0;
     for (;;) {
-      const GroupDev& G = groups[gorder[gi]];
-      const int64_t n = (int64_t)G.nblk * G.tiles;
+      const int64_t n = items(groups[gorder[gi]]);
       lo = n * x / 8;
       const int64_t cnt = n * (x + 1) / 8 - lo;
       if (j < cnt || gi + 1 == nactive) break;
@@ -261,6 +403,10 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
     const int e0 = G.rowptr[r0];
     const int ne = G.rowptr[r1] - e0;
     const int nt = G.nt;
+    const int64_t k0 = 2 * step[gorder[gi]];
+    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+    const double ph = G.wave[k0 + krow];
+    const int tw = VEC == 2 ? 128 : G.tile;           // instances of this tile
     __syncthreads();   // the previous item's LDS contents are no longer read
     for (int i2 = tid; i2 < ne; i2 += 256) {
       s_col[i2] = G.col[e0 + i2];
@@ -268,65 +414,14 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
     }
     for (int i2 = tid; i2 <= nr; i2 += 256) s_rp[i2] = G.rowptr[r0 + i2] - e0;
     for (int i2 = tid; i2 < nr * nt; i2 += 256) s_seg[i2] = G.segptr[(int64_t)r0 * nt + i2] - e0;
-    __syncthreads();
-    const int T = G.tile;
-    const int ngrp = 256 / T, lg = tid / T, bl = tid % T;
-    const int64_t k0 = 2 * step[gorder[gi]];
-    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
-    const double ph = G.wave[k0 + krow];
-    const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
-    double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
-    const int ld = G.ld;
-    {
-      const int b = tb * T + bl;
-      double coefb[kMaxBTerms];
-#pragma unroll
-      for (int a = 0; a < kMaxBTerms; ++a)
-        coefb[a] = (a < nt && b < G.B) ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
-      const double* xb = xin + b;
-      for (int lr = lg; lr < nr; lr += ngrp) {
-        const int ee = s_rp[lr + 1];
-        // the row's own state entries are loaded before its gathers
-        const int64_t ix = (int64_t)(r0 + lr) * ld + b;
-        const bool own = b < G.B;
-        const double vr = own ? G.v[ix] : 0.0;
-        const double ar = (own && STAGE != 0) ? G.acc[ix] : 0.0;
-        double ysum = 0.0;
-        for (int a = 0; a < nt; ++a) {
-          const int s0 = s_seg[lr * nt + a];
-          const int s1 = (a + 1 < nt) ? s_seg[lr * nt + a + 1] : ee;
-          double sacc = 0.0;
-          int e = s0;
-          for (; e + 4 <= s1; e += 4) {
-            const int c0 = s_col[e], c1 = s_col[e + 1], c2 = s_col[e + 2], c3 = s_col[e + 3];
-            const double v0 = s_val[e], v1 = s_val[e + 1], v2 = s_val[e + 2], v3 = s_val[e + 3];
-            const double x0 = xb[(int64_t)c0 * ld], x1 = xb[(int64_t)c1 * ld];
-            const double x2 = xb[(int64_t)c2 * ld], x3 = xb[(int64_t)c3 * ld];
-            sacc += v0 * x0;
-            sacc += v1 * x1;
-            sacc += v2 * x2;
-            sacc += v3 * x3;
-          }
-          for (; e < s1; ++e) sacc += s_val[e] * xb[(int64_t)s_col[e] * ld];
-          ysum += coefb[a] * sacc;
-        }
-        if (own) {
-          const double dt = G.dt;
-          if (STAGE == 0) {
-            xout[ix] = vr + (0.5 * dt) * ysum;
-            G.acc[ix] = ysum;
-          } else if (STAGE == 1) {
-            xout[ix] = vr + (0.5 * dt) * ysum;
-            G.acc[ix] = ar + 2.0 * ysum;
-          } else if (STAGE == 2) {
-            xout[ix] = vr + dt * ysum;
-            G.acc[ix] = ar + 2.0 * ysum;
-          } else {
-            xout[ix] = vr + (dt / 6.0) * (ar + ysum);
-          }
-        }
-      }
+    for (int i2 = tid; i2 < nt * tw; i2 += 256) {
+      const int a = i2 / tw, bl = i2 % tw;
+      const int b = tb * tw + bl;
+      s_cf[a * kCfStride + bl] = b < G.B ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
     }
+    __syncthreads();
+    if constexpr (VEC == 2) lds_rows_vec2<STAGE>(G, k0, tb, r0, nr, s_col, s_val, s_rp, s_seg, s_cf);
+    else lds_rows<STAGE>(G, k0, tb, r0, nr, s_col, s_val, s_rp, s_seg, s_cf);
   }
 }
 
@@ -351,11 +446,13 @@ void refresh_items(sun_batch_s& bt) {
   int64_t item = 0;
   for (int g = 0; g < bt.ngroups; ++g) {
     GroupDev& G = bt.ghost[g];
-    G.tile = bt.tile[g];
+    // a tile of 128 is 64 lanes with two instances each (LDS path only)
+    G.vec = (bt.tile[g] == 128 && bt.nblk[g] > 0) ? 2 : 1;
+    G.tile = std::min(bt.tile[g], 64);
     G.rows_per_item = bt.rows_per_item[g];
     G.ld = bt.ld[g];
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
-    G.tiles = (G.B + G.tile - 1) / G.tile;
+    G.tiles = (G.B + G.tile * G.vec - 1) / (G.tile * G.vec);
   }
   for (int gi : bt.order) {
     GroupDev& G = bt.ghost[gi];
@@ -496,7 +593,7 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
         bt->h_rowptr[g].resize(M + 1);
         HIP_OK(hipMemcpy(bt->h_rowptr[g].data(), bt->rowptr[g].get(), (M + 1) * sizeof(int), hipMemcpyDeviceToHost));
         repartition(*bt, g);
-        bt->ld[g] = round_up(B[g], 64);
+        bt->ld[g] = round_up(B[g], 128);
         GroupDev& G = bt->ghost[g];
         G = GroupDev{};
         G.rowptr = bt->rowptr[g].get();
@@ -555,7 +652,8 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
   return guarded([&] {
     SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
-    SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64, SUN_EINVAL, "tile must be 8, 16, 32 or 64");
+    SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
+                "tile must be 8, 16, 32, 64 or 128");
     SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= 65536, SUN_EINVAL, "rows_per_item out of range");
     SUN_REQUIRE(path == 0 || path == 1, SUN_EINVAL, "path must be 0 or 1");
     hipStream_t s = as_stream(stream);
@@ -626,6 +724,16 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       const int64_t nblocks = blocks_upto[nactive];
       const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((nitems + 3) / 4, (int64_t)ncu * 8));
       const int64_t bgrid = std::max<int64_t>(8, (std::min<int64_t>(nblocks, (int64_t)ncu * 8) + 7) / 8 * 8);
+      bool any_vec1 = false, any_vec2 = false;
+      int max_nt = 1;
+      for (int q = 0; q < nactive; ++q) {
+        const GroupDev& G = bt->ghost[ord[q]];
+        if (G.nblk > 0) {
+          (G.vec == 2 ? any_vec2 : any_vec1) = true;
+          max_nt = std::max(max_nt, G.nt);
+        }
+      }
+      const size_t cf_bytes = (size_t)max_nt * kCfStride * sizeof(double);
       const int64_t* st = steptab.get() + n * bt->ngroups;
       const GroupDev* gd = bt->gdev.get();
       const int* go = gorder.get();
@@ -633,25 +741,45 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
         hipLaunchKernelGGL(k_batch_stage<0>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<0>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
+        if (any_vec1)
+          hipLaunchKernelGGL((k_batch_stage_lds<0, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
+        if (any_vec2)
+          hipLaunchKernelGGL((k_batch_stage_lds<0, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
       }
       if (nitems > 0) {
         hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<1>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
+        if (any_vec1)
+          hipLaunchKernelGGL((k_batch_stage_lds<1, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
+        if (any_vec2)
+          hipLaunchKernelGGL((k_batch_stage_lds<1, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
       }
       if (nitems > 0) {
         hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<2>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
+        if (any_vec1)
+          hipLaunchKernelGGL((k_batch_stage_lds<2, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
+        if (any_vec2)
+          hipLaunchKernelGGL((k_batch_stage_lds<2, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
       }
       if (nitems > 0) {
         hipLaunchKernelGGL(k_batch_stage<3>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
       }
       if (nblocks > 0) {
-        hipLaunchKernelGGL(k_batch_stage_lds<3>, dim3((unsigned)bgrid), dim3(256), 0, s, gd, go, nactive, st);
+        if (any_vec1)
+          hipLaunchKernelGGL((k_batch_stage_lds<3, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
+        if (any_vec2)
+          hipLaunchKernelGGL((k_batch_stage_lds<3, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
+                             st);
       }
     }
     HIP_LAUNCH_OK();
