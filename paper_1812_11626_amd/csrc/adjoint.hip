@@ -202,6 +202,16 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ par
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// out[th] = sum over y < ny and k < n of part[(y * ntheta + th) * n + k], in a
+// fixed order; one workgroup per th.
+__global__ __launch_bounds__(256) void k_sum_slots(const double* __restrict__ part, int ny, int ntheta, int n,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[256];
+  double t = 0.0;
+  for (int y = 0; y < ny; ++y) t += block_sum_fixed(part + ((int64_t)y * ntheta + blockIdx.x) * n, n, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 int dot_blocks(int64_t n) { return (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 255) / 256)); }
 
 void dot_accumulate(const double* a, const double* b, int64_t n, double scale, double* part, double* out,
@@ -278,7 +288,7 @@ struct Work {
   DevBuf<double> ck;        // checkpoints [(nck) * (M+1)]
   DevBuf<double> per;       // states of one interval [(C+1) * (M+1)]
   DevBuf<double> stg;       // stage inputs of one interval [C][3][M+1] (optional)
-  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb, kb2, gpart, jpart, dev_grad, dev_J, dstat;
+  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb4, kb3, kb2, kb1, gpart, jpart, dev_grad, dev_J, dstat;
 };
 
 }  // namespace
@@ -313,7 +323,8 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
                          w.stg.get());
       HIP_LAUNCH_OK();
     }
-    for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.acc, &w.lam, &w.lacc, &w.kb, &w.kb2}) b->alloc(M1);
+    for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.acc, &w.lam, &w.lacc, &w.kb4, &w.kb3, &w.kb2, &w.kb1})
+      b->alloc(M1);
     // per-block accumulator of the objective's dot products
     const int nbj = dot_blocks(M);
     w.jpart.alloc(nbj);
@@ -325,7 +336,7 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     HIP_OK(hipMemsetAsync(w.dev_J.get(), 0, sizeof(double), s));
     if (ntheta > 0)
       HIP_OK(hipMemcpyAsync(w.dstat.get(), dstatic, a->nt * ntheta * sizeof(double), hipMemcpyHostToDevice, s));
-    for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.lam, &w.lacc, &w.kb, &w.kb2}) {
+    for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.lam, &w.lacc, &w.kb4, &w.kb3, &w.kb2, &w.kb1}) {
       hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(M1, 256)), dim3(256), 0, s, M1, 0.0, b->get());
       hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, b->get() + M);
     }
@@ -374,10 +385,11 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
         nslot += prop_dot_slots(*a->termp[t]);
       }
     }
-    w.gpart.alloc(std::max<int64_t>(1, ntheta * nslot));
+    const int ny = kDotStages / kDotStagesPerWave;
+    w.gpart.alloc(std::max<int64_t>(1, ny * ntheta * nslot));
     if (ntheta * nslot > 0)
-      hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(ntheta * nslot, 256)), dim3(256), 0, s, ntheta * nslot, 0.0,
-                         w.gpart.get());
+      hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(ny * ntheta * nslot, 256)), dim3(256), 0, s, ny * ntheta * nslot,
+                         0.0, w.gpart.get());
     std::vector<const sun_prop_s*> gp;
     std::vector<int> gterm, gslot;
     std::vector<int64_t> goff;
@@ -387,10 +399,11 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
       gslot.push_back(g.slot);
       goff.push_back(g.off);
     }
-    auto grad_stage = [&](const double* kbv, const double* x, int64_t krow) {
+    // dot products of the four stages of step n, one launch per step
+    auto grad_step = [&](const double* const* xs, const double* const* kbs, const int64_t* krows) {
       if (gp.empty()) return;
-      prop_dot(gp.data(), gterm.data(), gslot.data(), goff.data(), (int)gp.size(), x, kbv, w.dstat.get(), dcoef,
-               krow, a->ndyn, ntheta, w.gpart.get(), nslot, s);
+      prop_dot(gp.data(), gterm.data(), gslot.data(), goff.data(), (int)gp.size(), xs, kbs, krows, w.dstat.get(),
+               dcoef, a->ndyn, ntheta, w.gpart.get(), nslot, s);
     };
     // ---- backward sweep -----------------------------------------------------
     const int64_t first_avg = steps - S_avg + 1;      // J averages v_n for n >= first_avg
@@ -415,7 +428,7 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
           hipLaunchKernelGGL(k_dot_acc, dim3(nbj), dim3(256), 0, s, M, cobs, vn1, 1.0 / (double)S_avg, w.jpart.get());
         // lambda += c/S (direct dependence of J on v_{n+1}); kb4 = dt/6 lambda
         hipLaunchKernelGGL(k_adj_prep, dim3(grid_for(M, 256)), dim3(256), 0, s, M, lam, cobs,
-                           in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb.get());
+                           in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb4.get());
         // forward stage inputs of step n (kept from the interval recompute,
         // or recomputed here)
         const double *x2 = w.x2.get(), *x3 = w.x3.get(), *x4 = w.x4.get();
@@ -429,20 +442,22 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
           prop_stage(F, 2, w.x3.get(), vn, w.acc.get(), w.x4.get(), coef, 2 * n + 1, dt, s);
         }
         // stage 4: kb4 with x4 at t_{n+1}
-        grad_stage(w.kb.get(), x4, 2 * n + 2);
-        prop_stage(B, 4, w.kb.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 2, dt, s);   // kb2 <- kb3
-        grad_stage(w.kb2.get(), x3, 2 * n + 1);
-        prop_stage(B, 5, w.kb2.get(), lam, lacc, w.kb.get(), coef, 2 * n + 1, dt, s);   // kb <- kb2
-        grad_stage(w.kb.get(), x2, 2 * n + 1);
-        prop_stage(B, 6, w.kb.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 1, dt, s);   // kb2 <- kb1
-        grad_stage(w.kb2.get(), vn, 2 * n);
-        prop_stage(B, 7, w.kb2.get(), lam, lacc, nullptr, coef, 2 * n, dt, s);
+        prop_stage(B, 4, w.kb4.get(), lam, lacc, w.kb3.get(), coef, 2 * n + 2, dt, s);
+        prop_stage(B, 5, w.kb3.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 1, dt, s);
+        prop_stage(B, 6, w.kb2.get(), lam, lacc, w.kb1.get(), coef, 2 * n + 1, dt, s);
+        prop_stage(B, 7, w.kb1.get(), lam, lacc, nullptr, coef, 2 * n, dt, s);
+        // parameter terms: kb_i . (dT/dtheta x_i) for the stage inputs x4, x3, x2, v_n
+        const double* xs[4] = {x4, x3, x2, vn};
+        const double* kbs[4] = {w.kb4.get(), w.kb3.get(), w.kb2.get(), w.kb1.get()};
+        const int64_t krows[4] = {2 * n + 2, 2 * n + 1, 2 * n + 1, 2 * n};
+        grad_step(xs, kbs, krows);
         std::swap(lam, lacc);
       }
     }
     // fixed-order reductions of the accumulated partials
     if (ntheta > 0 && nslot > 0)
-      hipLaunchKernelGGL(k_sum_rows, dim3(ntheta), dim3(256), 0, s, w.gpart.get(), (int)nslot, w.dev_grad.get());
+      hipLaunchKernelGGL(k_sum_slots, dim3(ntheta), dim3(256), 0, s, w.gpart.get(), ny, ntheta, (int)nslot,
+                         w.dev_grad.get());
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, w.jpart.get(), nbj, w.dev_J.get());
     HIP_LAUNCH_OK();
     double hg[kMaxTheta];

@@ -49,16 +49,21 @@ void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double*
                 const double* coef, int64_t coef_row, double dt, hipStream_t s);
 
 // Adjoint parameter dot products on static generators T_j (j < n <= 8) in
-// sliced layout (no time-dependent term), all in one launch: adds, for
-// th < ntheta,  dc_jth * (kb . (T_j x))  (x[M] = 1 brings in T_j's free
-// vector), split over prop_dot_slots(*ps[j]) per-wavefront slots
-// gpart[th * ld + slot0[j] + w], with dc_jth = dstat[term[j] * ntheta + th]
-// (+ dcoef[(krow * ndyn + slot[j]) * ntheta + th] when slot[j] >= 0).  The
+// sliced layout (no time-dependent term), for the kDotStages RK4 stages of
+// one step, all in one launch: adds, for th < ntheta,
+//   sum_i dc_jth(t_i) * (kbs[i] . (T_j xs[i]))   (xs[i][M] = 1 brings in T_j's free vector)
+// split over prop_dot_slots(*ps[j]) per-wavefront slots
+// gpart[(y * ntheta + th) * ld + slot0[j] + w] (y < kDotStages / kDotStagesPerWave
+// selects the stages), with dc_jth(t_i) = dstat[term[j] * ntheta + th]
+// (+ dcoef[(krows[i] * ndyn + slot[j]) * ntheta + th] when slot[j] >= 0).  The
 // slot sums are to be reduced in a fixed order.
 constexpr int kMaxDotTerms = 8;
+constexpr int kDotStages = 4;
+constexpr int kDotStagesPerWave = 2;   // stages one wavefront takes (1, 2 or 4)
+// slots per launch: kDotStages / kDotStagesPerWave groups of ntheta * ld
 int64_t prop_dot_slots(const sun_prop_s& p);
 void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, const int64_t* slot0, int n,
-              const double* x, const double* kb, const double* dstat, const double* dcoef, int64_t krow, int ndyn,
-              int ntheta, double* gpart, int64_t ld, hipStream_t s);
+              const double* const* xs, const double* const* kbs, const int64_t* krows, const double* dstat,
+              const double* dcoef, int ndyn, int ntheta, double* gpart, int64_t ld, hipStream_t s);
 
 }  // namespace sun

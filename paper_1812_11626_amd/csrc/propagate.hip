@@ -588,11 +588,13 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
 
 // Adjoint parameter dot products on the sliced layouts of static generators
 // T_j (each with its free vector folded in as column M, x[M] = 1), all terms
-// in one launch: the wavefronts are numbered term after term (wave0), and
-// each forms q = sum over its rows of kb[r] (T_j x)[r] (one slice, or one long
-// row), reduced over the wavefront in a fixed tree, and adds dc_th * q to its
-// own slot gpart[th * ld + slot0_j + w] for th < ntheta, with
-// dc_th = dstat[term_j * ntheta + th] (+ dcoef[(krow * ndyn + slot_j) * ntheta + th]
+// and the four RK4 stages of one step in one launch, so each matrix is read
+// once per step.  The wavefronts are numbered term after term (wave0); each
+// forms, for every stage i, q_i = sum over its rows of kb_i[r] (T_j x_i)[r]
+// (one slice, or one long row; every sum in row order), reduced over the
+// wavefront in a fixed tree, and adds sum_i dc_jth(t_i) q_i to its own slot
+// gpart[th * ld + slot0_j + w] for th < ntheta, with
+// dc_jth(t_i) = dstat[term_j * ntheta + th] (+ dcoef[(krow_i * ndyn + slot_j) * ntheta + th]
 // for a time-dependent term, slot_j >= 0).  Each slot is updated by one
 // wavefront per launch, in stream order.
 struct DotView {
@@ -612,11 +614,63 @@ struct DotViews {
   DotView v[kMaxDotTerms];
 };
 
-template <int U, bool NTL>
-__global__ __launch_bounds__(256) void k_dot_sell(DotViews dv, int64_t nwaves, const double* __restrict__ xin,
-                                                  const double* __restrict__ kb, const double* __restrict__ dstat,
-                                                  const double* __restrict__ dcoef, int64_t krow, int ndyn,
-                                                  int ntheta, double* __restrict__ gpart, int64_t ld, int xcd_remap) {
+struct DotStages {
+  const double* x[kDotStages];
+  const double* kb[kDotStages];
+  int64_t krow[kDotStages];
+};
+
+// s[i] = sum over one lane's row of a slice (all entries: static generator)
+// of val * x_i[col], for the kDotStages stage vectors; U entries per round.
+template <class T, int U, bool NTL, int NS>
+__device__ inline void slice_row_dots(const unsigned char* cb, const int* __restrict__ gbase,
+                                      const double* __restrict__ vp, int wd, int lane, int len,
+                                      const double* const* xs, double* s) {
+  for (int i = 0; i < NS; ++i) s[i] = 0.0;
+  // full rounds without predicates (all loads of a round issued together),
+  // then the last wd % U entries
+  int k = 0;
+  for (; k + U <= wd; k += U) {
+    int ci[U];
+    double cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ci[u] = gbase[k + u] + load_delta<T, NTL>(cb, (int64_t)(k + u) * kSlice + lane);
+      cv[u] = stream_load<NTL>(vp + (int64_t)(k + u) * kSlice);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      double xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = xs[i][ci[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s[i] += (k + u < len) ? cv[u] * xv[u] : 0.0;
+    }
+  }
+  for (; k < wd; ++k) {
+    const int c = gbase[k] + load_delta<T, NTL>(cb, (int64_t)k * kSlice + lane);
+    const double v = stream_load<NTL>(vp + (int64_t)k * kSlice);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) s[i] += (k < len) ? v * xs[i][c] : 0.0;
+  }
+}
+
+template <int U, bool NTL, int NS>
+__global__ __launch_bounds__(256) void k_dot_sell(DotViews dv, int64_t nwaves, DotStages st,
+                                                  const double* __restrict__ dstat,
+                                                  const double* __restrict__ dcoef, int ndyn, int ntheta,
+                                                  double* __restrict__ gpart, int64_t ld, int xcd_remap) {
+  // blockIdx.y selects stages [NS * blockIdx.y, NS * blockIdx.y + NS); its
+  // slots follow those of the previous y at offset ntheta * ld
+  const int sb = NS * blockIdx.y;
+  gpart += (int64_t)blockIdx.y * ntheta * ld;
+  const double* xs[NS];
+  const double* kbs[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    xs[i] = st.x[sb + i];
+    kbs[i] = st.kb[sb + i];
+  }
   const int lane = threadIdx.x & 63;
   int64_t blk = blockIdx.x;
   if (xcd_remap) {
@@ -630,7 +684,7 @@ __global__ __launch_bounds__(256) void k_dot_sell(DotViews dv, int64_t nwaves, c
     if (dv.v[q].wave0 <= gw) j = q;
   const DotView& D = dv.v[j];
   const int64_t wid = gw - D.wave0;
-  double qv = 0.0;
+  double qv[NS];
   if (wid < D.nslices) {
     const int64_t i = wid * kSlice + lane;
     const int off = __builtin_amdgcn_readfirstlane(D.off[wid]);
@@ -638,31 +692,48 @@ __global__ __launch_bounds__(256) void k_dot_sell(DotViews dv, int64_t nwaves, c
     const int coff = __builtin_amdgcn_readfirstlane(D.coff[wid]);
     const bool own = i < D.nshort;
     const int r = own ? D.row[i] : 0;
-    const int lens = D.len[i];
-    const int slen = lens & 0xFFFF, len = lens >> 16;
-    const double kr = own ? kb[r] : 0.0;
+    const int len = D.len[i] >> 16;
     const unsigned char* cb = D.cb + (coff & ~63);
     const int* gbase = D.gbase + off / kSlice;
     const double* vp = D.sval + off + lane;
-    double a0 = 0.0, a1 = 0.0;
+    double sv[NS];
     switch (coff & 3) {
-      case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 0: slice_row_dots<uint8_t, U, NTL, NS>(cb, gbase, vp, wd, lane, len, xs, sv); break;
+      case 1: slice_row_dots<uint16_t, U, NTL, NS>(cb, gbase, vp, wd, lane, len, xs, sv); break;
+      default: slice_row_dots<uint32_t, U, NTL, NS>(cb, gbase, vp, wd, lane, len, xs, sv); break;
     }
-    qv = own ? kr * (a0 + a1) : 0.0;
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) qv[s2] = own ? kbs[s2][r] * sv[s2] : 0.0;
   } else {
     const int r = D.long_rows[wid - D.nslices];
-    double a0 = 0.0;
-    for (int e = D.rowptr[r] + lane; e < D.rowptr[r + 1]; e += 64) a0 += D.val[e] * xin[D.col[e]];
-    for (int o = 32; o > 0; o >>= 1) a0 += __shfl_xor(a0, o, 64);
-    qv = lane == 0 ? kb[r] * a0 : 0.0;
+    double a[NS];
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) a[s2] = 0.0;
+    for (int e = D.rowptr[r] + lane; e < D.rowptr[r + 1]; e += 64) {
+      const double v = D.val[e];
+      const int c = D.col[e];
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) a[s2] += v * xs[s2][c];
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      for (int o = 32; o > 0; o >>= 1) a[s2] += __shfl_xor(a[s2], o, 64);
+      qv[s2] = lane == 0 ? kbs[s2][r] * a[s2] : 0.0;
+    }
   }
-  for (int o = 32; o > 0; o >>= 1) qv += __shfl_xor(qv, o, 64);
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2)
+    for (int o = 32; o > 0; o >>= 1) qv[s2] += __shfl_xor(qv[s2], o, 64);
   if (lane < ntheta) {
-    double dc = dstat[D.term * ntheta + lane];
-    if (D.slot >= 0 && dcoef) dc += dcoef[(krow * ndyn + D.slot) * ntheta + lane];
-    gpart[lane * ld + D.slot0 + wid] += dc * qv;
+    const double d0 = dstat[D.term * ntheta + lane];
+    double add = 0.0;
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      double dc = d0;
+      if (D.slot >= 0 && dcoef) dc += dcoef[(st.krow[sb + s2] * ndyn + D.slot) * ntheta + lane];
+      add += dc * qv[s2];
+    }
+    gpart[lane * ld + D.slot0 + wid] += add;
   }
 }
 
@@ -832,8 +903,8 @@ void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double*
 int64_t prop_dot_slots(const sun_prop_s& p) { return p.nslices + p.nlong; }
 
 void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, const int64_t* slot0, int n,
-              const double* x, const double* kb, const double* dstat, const double* dcoef, int64_t krow, int ndyn,
-              int ntheta, double* gpart, int64_t ld, hipStream_t s) {
+              const double* const* xs, const double* const* kbs, const int64_t* krows, const double* dstat,
+              const double* dcoef, int ndyn, int ntheta, double* gpart, int64_t ld, hipStream_t s) {
   SUN_REQUIRE(n >= 1 && n <= kMaxDotTerms, SUN_EINVAL, "1 to 8 terms per dot launch");
   DotViews dv{};
   dv.n = n;
@@ -866,9 +937,15 @@ void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, con
   unsigned grid = (unsigned)((nw + 3) / 4);
   const int remap = ps[0]->sell_remap;
   if (remap) grid = (grid + 7) / 8 * 8;
-  auto kern = ps[0]->sell_nt ? k_dot_sell<8, true> : k_dot_sell<8, false>;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, dv, nw, x, kb, dstat, dcoef, krow, ndyn, ntheta, gpart, ld,
-                     remap);
+  DotStages st{};
+  for (int i = 0; i < kDotStages; ++i) {
+    st.x[i] = xs[i];
+    st.kb[i] = kbs[i];
+    st.krow[i] = krows[i];
+  }
+  auto kern = ps[0]->sell_nt ? k_dot_sell<4, true, kDotStagesPerWave> : k_dot_sell<4, false, kDotStagesPerWave>;
+  hipLaunchKernelGGL(kern, dim3(grid, kDotStages / kDotStagesPerWave), dim3(256), 0, s, dv, nw, st, dstat, dcoef, ndyn,
+                     ntheta, gpart, ld, remap);
   HIP_LAUNCH_OK();
 }
 
