@@ -265,8 +265,8 @@ def pmc_mode(sb, torch, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path has no multi-GPU form "
-              "in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU "
+              "form (the design notes describe how it would shard)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1812_11626_amd as sb

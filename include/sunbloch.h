@@ -49,7 +49,7 @@ enum {
   SUN_EINVAL = -1,   /* invalid argument (sizes, null pointers, non-Hermitian H, gamma < 0, ...) */
   SUN_ENOMEM = -2,   /* device allocation failed */
   SUN_EDEVICE = -3,  /* a HIP runtime call failed */
-  SUN_ENOTSUP = -4,  /* valid input outside what this build supports (limits stated per call) */
+  SUN_ENOTSUP = -4,  /* valid input outside what the library supports (limits stated per call) */
   SUN_ERANGE = -5    /* caller buffer too small; the needed size is returned */
 };
 

@@ -246,7 +246,7 @@ RowAssemblyResult assemble_rows(const G& g, int64_t rows, double rel_drop, bool 
   if (res.max_row_raw > cap) {
     SUN_THROW(SUN_ENOTSUP, "a row has " + std::to_string(res.max_row_raw) +
                                " raw contributions, more than the LDS sort holds (" + std::to_string(cap) +
-                               "); operator too dense for this build");
+                               "); operator too dense for the LDS row sort");
   }
   res.raw = exclusive_scan_i64(cnt.get(), off.get(), rows, s);
   DevBuf<uint64_t> key(res.raw > 0 ? res.raw : 1), mkey(res.raw > 0 ? res.raw : 1);
@@ -270,7 +270,7 @@ RowAssemblyResult assemble_rows(const G& g, int64_t rows, double rel_drop, bool 
   if (hf[0]) SUN_THROW(SUN_EDEVICE, "row generator produced different counts in its two passes");
   if (hf[1]) {
     SUN_THROW(SUN_ENOTSUP, "a row has more raw contributions than the LDS sort holds (" +
-                               std::to_string(cap) + "); operator too dense for this build");
+                               std::to_string(cap) + "); operator too dense for the LDS row sort");
   }
   double thr = 0.0;
   if (rel_drop > 0) thr = rel_drop * device_max(rowmax.get(), rows, s);
