@@ -200,6 +200,16 @@ int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
 int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt,
                          int64_t steps, int64_t every, double* states, int64_t ld,
                          const double* x, double x0, double* obs, void* stream);
+/* Spectral radius |lambda|max of the linear part of the generator, G with
+ * the time-dependent coefficients frozen at coef (host double[ndyn]), by
+ * power iteration: `iters` applications of G to a normalised pseudo-random
+ * start vector, returning the mean growth factor per application over the
+ * second half (host double *rho).  For choosing RK4 steps: the method is
+ * stable for |lambda| dt up to about 2.8 on the imaginary axis.  Allocates
+ * its own work vectors; synchronises `stream`.  SUN_ERANGE if the iteration
+ * collapses (G x = 0) or overflows. */
+int sun_prop_spectral_radius(sun_prop p, const double* coef, int32_t iters, double* rho,
+                             void* stream);
 /* Same as sun_propagate, and additionally records a HIP event pair around
  * every stage launch on `stream`; on return (synchronised) stage_ms[i]
  * (host double[4]) holds the summed GPU time of stage i over all steps and

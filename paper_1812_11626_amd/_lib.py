@@ -59,6 +59,7 @@ PROTOS = {
     "sun_propagate_profile": (C.c_int, [vp, vp, vp, f64, i64, vp, P(f64), P(i64)]),
     "sun_propagate_record": (C.c_int, [vp, vp, vp, f64, i64, i64, vp, i64, vp, f64, vp, vp]),
     "sun_prop_info": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
+    "sun_prop_spectral_radius": (C.c_int, [vp, P(f64), i32, P(f64), vp]),
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),
     "sun_prop_layout": (C.c_int, [vp, P(i32), P(i64), P(i64), P(i64)]),

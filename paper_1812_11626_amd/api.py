@@ -265,6 +265,16 @@ class Propagator:
         check(self._lib.sun_propagate(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), _stream()))
         return v
 
+    def spectral_radius(self, coef=(), iters: int = 200) -> float:
+        """|lambda|max of the generator's linear part with the time-dependent
+        coefficients frozen at `coef` (power iteration on the GPU)."""
+        c = list(coef)
+        assert len(c) == self.ndyn
+        buf = (C.c_double * max(1, len(c)))(*[float(x) for x in c])
+        rho = C.c_double()
+        check(self._lib.sun_prop_spectral_radius(self.handle, buf, int(iters), C.byref(rho), _stream()))
+        return rho.value
+
     def record(self, v: torch.Tensor, coef: torch.Tensor | None, dt: float, steps: int, every: int,
                states: bool = True, observable=None):
         """RK4 like ``propagate`` (in place on v), recording after every

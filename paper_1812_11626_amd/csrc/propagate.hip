@@ -26,6 +26,7 @@
 //   s=3: x4 = v + dt   k3,  acc = acc + 2 k3
 //   s=4: v  = v + dt/6 (acc + k4)
 #include <algorithm>
+#include <cmath>
 
 #include "internal.hpp"
 
@@ -1166,6 +1167,69 @@ extern "C" int sun_propagate_record(sun_prop p, double* v, const double* coef, d
     }
     HIP_LAUNCH_OK();
     HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  });
+}
+
+namespace {
+
+// x[i] = a deterministic pseudo-random value in [-1, 1) (splitmix64 of i), x[M] = 0
+__global__ void k_spec_init(int64_t M, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= M; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = (uint64_t)i + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = i < M ? (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0 : 0.0;
+  }
+}
+
+// x = y / sqrt(*n2) on rows < M, x[M] = 0
+__global__ void k_spec_scale(int64_t M, const double* __restrict__ y, const double* __restrict__ n2,
+                             double* __restrict__ x) {
+  const double inv = 1.0 / sqrt(*n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= M; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = i < M ? y[i] * inv : 0.0;
+}
+
+}  // namespace
+
+extern "C" int sun_prop_spectral_radius(sun_prop p, const double* coef, int32_t iters, double* rho, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr && rho != nullptr, SUN_EINVAL, "NULL argument");
+    SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    SUN_REQUIRE(iters >= 2 && iters <= 100000, SUN_EINVAL, "iters must be in [2, 100000]");
+    hipStream_t s = as_stream(stream);
+    const int64_t M = p->M;
+    DevBuf<double> x(M + 1), y(M + 1), zero(M + 1), acc(M + 1), n2(iters), cdev(p->ndyn > 0 ? p->ndyn : 1);
+    const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M + 4095) / 4096));
+    DevBuf<double> part(2 * nb);
+    if (p->ndyn > 0) HIP_OK(hipMemcpyAsync(cdev.get(), coef, p->ndyn * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M + 1, 0.0, zero.get());
+    hipLaunchKernelGGL(k_spec_init, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get());
+    HIP_LAUNCH_OK();
+    // start from the normalised pseudo-random vector
+    expect_launch(M, y.get(), 1, M, y.get(), nullptr, 0.0, 0.0, n2.get(), nullptr, part.get(), nb, s);
+    hipLaunchKernelGGL(k_spec_scale, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get(), n2.get(), x.get());
+    HIP_LAUNCH_OK();
+    for (int i = 0; i < iters; ++i) {
+      // stage 0 with a zero base vector and dt = 2: y = G x (x[M] = 0 leaves K out)
+      prop_stage(*p, 0, x.get(), zero.get(), acc.get(), y.get(), cdev.get(), 0, 2.0, s);
+      expect_launch(M, y.get(), 1, M, y.get(), nullptr, 0.0, 0.0, n2.get() + i, nullptr, part.get(), nb, s);
+      hipLaunchKernelGGL(k_spec_scale, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get(), n2.get() + i,
+                         x.get());
+      HIP_LAUNCH_OK();
+    }
+    std::vector<double> h(iters);
+    HIP_OK(hipMemcpyAsync(h.data(), n2.get(), iters * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    // mean log growth per application over the second half of the iterations
+    double acc_log = 0.0;
+    const int first = iters / 2;
+    for (int i = first; i < iters; ++i) {
+      SUN_REQUIRE(h[i] > 0.0 && std::isfinite(h[i]), SUN_ERANGE, "power iteration lost its vector (G x = 0 or overflow)");
+      acc_log += 0.5 * std::log(h[i]);
+    }
+    *rho = std::exp(acc_log / (double)(iters - first));
   });
 }
 

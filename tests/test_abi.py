@@ -54,6 +54,8 @@ def test_host_side_argument_checks():
     assert lib.sun_prop_tune(None, 2048, 256, 1, None) == _lib.SUN_EINVAL
     assert lib.sun_propagate_record(None, None, None, 0.1, 1, 1, None, 0, None, 0.0, None, None) == _lib.SUN_EINVAL
     assert lib.sun_bloch_density(None, None, None, None, None) == _lib.SUN_EINVAL
+    r = ctypes.c_double()
+    assert lib.sun_prop_spectral_radius(None, None, 100, ctypes.byref(r), None) == _lib.SUN_EINVAL
     assert lib.sun_bloch_expect(None, None, 1, 0, None, None, None, None, None, None) == _lib.SUN_EINVAL
     n = ctypes.c_int64()
     assert lib.sun_lind_nnz(None, 0, 0, ctypes.byref(n)) == _lib.SUN_EINVAL

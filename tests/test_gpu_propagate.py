@@ -232,3 +232,44 @@ def test_sliced_kernel_variants_are_bitwise_identical(lib):
         prop.propagate(v, eps, p.dt, steps)
         assert torch.equal(v, ref), kw
 
+
+
+@pytest.mark.parametrize("N", [11, 31])
+def test_spectral_radius_matches_dense_eigenvalues(lib, N):
+    """Power iteration on the GPU against the largest |eigenvalue| of the
+    oracle's dense generator, at both ends of the drive range."""
+    flush(f"[propagate] spectral radius N={N}")
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    _, _, prop = _gpu_system(lib, p, ops)
+    G0 = (lb.q_full("H", ops["H0"]) + p.gamma_eff * lb.q_full("L", ops["L"])).toarray()
+    G1 = lb.q_full("H", ops["H1"]).toarray()
+    for eps in (p.E - p.A, p.E + p.A):
+        want = np.abs(np.linalg.eigvals(G0 + eps * G1)).max()
+        got = prop.spectral_radius([eps], iters=300)
+        assert abs(got - want) <= 1e-3 * want, (eps, got, want)
+
+
+def test_configured_step_counts_are_rk4_stable(lib):
+    """The step counts per period of the workloads keep |lambda|max dt <= 2.5
+    (inside RK4's stability interval on the imaginary axis, 2*sqrt(2)) over the
+    whole drive range: plain N = 51, 101, 301, 1001 and every batched group."""
+    for N in (51, 101, 301, 1001):
+        flush(f"[propagate] stability N={N}")
+        p = dimer.plain_config(N)
+        ops = dimer.dimer_operators(p)
+        _, _, prop = _gpu_system(lib, p, ops)
+        for eps in (p.E - p.A, p.E + p.A):
+            lam = prop.spectral_radius([eps], iters=200)
+            assert lam * p.dt <= 2.5 * (1 + 1e-3), (N, eps, lam * p.dt)
+    inst = dimer.batched_instances()
+    for N in sorted({q.N for q in inst}):
+        group = [q for q in inst if q.N == N]
+        q = max(group, key=lambda x: x.A)
+        ops = dimer.dimer_operators(q)
+        b = lib.build_basis(N)
+        lind = lib.Lindbladian(b, [ops["H0"], ops["H1"]], [ops["L"]])
+        gmax = max(x.gamma_eff for x in group)
+        prop = lind.propagator([1.0, 0.0, gmax], [1])
+        lam = prop.spectral_radius([q.E + q.A], iters=200)
+        assert lam * q.dt <= 2.5 * (1 + 1e-3), (N, lam * q.dt)

@@ -221,11 +221,13 @@ BATCH_SIZES = (51, 101, 151, 201, 301)
 
 def stable_steps_per_period(N: int, eps_max: float, J: float = 1.0,
                             omega: float = 1.0, nominal: int = 1000,
-                            quantum: int = 256) -> int:
+                            quantum: int = 256, margin: float = 1.02) -> int:
     """Smallest step count per period (a multiple of ``quantum``, at least
     ``nominal``) with |lambda_max| dt <= 2.5, using the dimer estimate
-    |lambda_max| ~= 2 sqrt(eps_max^2 + J^2) (N - 1)."""
-    lam = 2.0 * math.sqrt(eps_max * eps_max + J * J) * (N - 1)
+    |lambda_max| ~= 2 sqrt(eps_max^2 + J^2) (N - 1) times ``margin`` (the
+    interaction and dissipation terms raise the true spectral radius by up to
+    ~1% at the workloads' parameters)."""
+    lam = 2.0 * math.sqrt(eps_max * eps_max + J * J) * (N - 1) * margin
     T = 2.0 * math.pi / omega
     need = math.ceil(T * lam / 2.5)
     need = quantum * math.ceil(need / quantum)
