@@ -3,8 +3,10 @@
 
 Checks: against the oracle's dense discrete adjoint at N = 6 (J to 1e-12,
 gradient to 1e-7 relative), against central finite differences (h = 1e-6)
-of the GPU objective at N = 6 and N = 51, invariance under the checkpoint
-interval, and the torch.autograd.Function wrapper.
+of the GPU objective at N = 6 and N = 51, at the benchmark's size N = 301
+(J against the oracle's sparse objective, the gradient against central
+differences), invariance under the checkpoint interval, and the
+torch.autograd.Function wrapper.
 """
 
 import numpy as np
@@ -12,7 +14,7 @@ import pytest
 import torch
 
 from helpers import dimer_adjoint_problem, flush
-from oracle import adjoint as oadj, basis as ob, lindblad as lb
+from oracle import adjoint as oadj, basis as ob, lindblad as lb, propagate as opr
 from workloads import dimer
 
 pytestmark = pytest.mark.gpu
@@ -66,6 +68,39 @@ def test_central_differences(lib, N):
     h = 1e-6
     for i in range(3):
         tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (prob.value(tp) - prob.value(tm)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * abs(g[i]) + 1e-11, (i, fd, g[i])
+
+
+def test_N301_benchmark_configuration(lib):
+    """N = 301 (M = 90,600) with a checkpoint every S steps as the benchmark
+    runs it, over 256 steps: J against the oracle (1e-12), dJ/d(A, gamma, U)
+    against central differences of the GPU objective (1e-7)."""
+    N = 301
+    flush(f"[adjoint] N={N} benchmark configuration")
+    p = dimer.adjoint_config(N)
+    steps, S = 256, 128
+    prob, _, _ = dimer_adjoint_problem(lib, p, steps, S, ckpt_every=S)
+    J, g = prob.value_and_grad(THETA.copy())
+    # oracle: RK4 on the density matrix itself (eq. 1; the same trajectory as
+    # RK4 on eq. 9 in exact arithmetic), J = mean of Tr(rho_n (n1 - n2)) over
+    # the last S grid states (n1 - n2 is traceless)
+    ops = dimer.dimer_operators(p)
+    eps = dimer.drive_table(p, steps=steps)[:, None]
+    rho0 = np.zeros((N, N), complex)
+    rho0[0, 0] = 1
+    rho = opr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho0, eps[: 2 * (steps - S) + 1],
+                      p.dt, steps - S)
+    _, rec = opr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho, eps[2 * (steps - S):], p.dt, S,
+                         record_every=1)
+    n12 = np.real(ops["H1"].to_dense().diagonal())
+    J_o = float(np.mean([np.real(np.diagonal(r)) @ n12 for r in rec]))
+    assert abs(J - J_o) <= 1e-12 * abs(J_o), (J, J_o)
+    h = 1e-6
+    for i in range(3):
+        tp, tm = THETA.copy(), THETA.copy()
         tp[i] += h
         tm[i] -= h
         fd = (prob.value(tp) - prob.value(tm)) / (2 * h)
