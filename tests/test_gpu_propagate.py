@@ -273,3 +273,48 @@ def test_configured_step_counts_are_rk4_stable(lib):
         prop = lind.propagator([1.0, 0.0, gmax], [1])
         lam = prop.spectral_radius([q.E + q.A], iters=200)
         assert lam * q.dt <= 2.5 * (1 + 1e-3), (N, lam * q.dt)
+
+
+def test_plain_N51_full_horizon(lib):
+    """The N = 51 workload over its full horizon, 100 periods (100,000 RK4
+    steps), against the oracle's Bloch RK4 at every period end."""
+    flush("[propagate] N=51 100 periods")
+    p = dimer.plain_config(51)
+    ops = dimer.dimer_operators(p)
+    G0 = lb.q_full("H", ops["H0"]) + p.gamma_eff * lb.q_full("L", ops["L"])
+    G1 = lb.q_full("H", ops["H1"])
+    K = p.gamma_eff * lb.k_vector(ops["L"])
+    eps = dimer.drive_table(p)
+    v0 = _fock_v0(51)
+    _, rec = pr.rk4_bloch(G0, [G1], K, v0, eps[:, None], p.dt, p.steps, record_every=p.steps_per_period)
+    _, _, prop = _gpu_system(lib, p, ops)
+    v = torch.as_tensor(v0).cuda().clone()
+    states, _ = prop.record(v, torch.as_tensor(eps).cuda().contiguous(), p.dt, p.steps, p.steps_per_period)
+    got = states.cpu().numpy()
+    worst = max(rel_vec_err(a, b) for a, b in zip(got, rec))
+    flush(f"[propagate] N=51 100 periods: worst relative error {worst:.2e}")
+    assert worst <= TOL
+
+
+def test_plain_N1001_first_period_properties(lib):
+    """The N = 1001 workload over its first period (16,384 steps): the oracle
+    cannot follow that far, so check what holds for any exact solution and
+    RK4 keeps to rounding: purity Tr(rho^2) = 1/N + |v|^2 <= 1, rho positive
+    semidefinite (eigenvalues >= -1e-9), <n1 - n2> inside its spectrum."""
+    N = 1001
+    flush(f"[propagate] N={N} first period")
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    b, _, prop = _gpu_system(lib, p, ops)
+    steps = p.steps_per_period
+    eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+    v = torch.as_tensor(_fock_v0(N)).cuda().clone()
+    x, x0 = b.observable(ops["H1"])
+    _, obs = prop.record(v, eps, p.dt, steps, 1024, states=False, observable=(x, x0))
+    assert torch.isfinite(v).all()
+    vv = v.cpu().numpy()
+    assert vv @ vv <= 1.0 - 1.0 / N + 1e-12
+    rho = b.density(v).cpu().numpy()
+    assert np.linalg.eigvalsh(rho).min() >= -1e-9
+    o = obs.cpu().numpy()
+    assert np.all(np.abs(o) <= (N - 1) * (1 + 1e-12))
