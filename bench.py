@@ -131,6 +131,40 @@ def _fock_v0(sb, basis, N, i=0):
     return basis.expand(dimer.ZCSR.from_diagonals(N, {0: e}))[0].real.contiguous()
 
 
+def small_configs_report(sb, torch, steps=2000):
+    """The plain workloads at N = 4 and N = 51 (parity configurations; both
+    are latency bound, four stage launches per step): nnz per term, assembly
+    time and RK4 steps/s."""
+    from workloads import dimer
+    res = {}
+    for N in (4, 51):
+        p = dimer.plain_config(N)
+        ops = dimer.dimer_operators(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        basis = sb.build_basis(N)
+        lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+        torch.cuda.synchronize()
+        t_asm = time.perf_counter() - t0
+        v = _fock_v0(sb, basis, N)
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps + 50)).cuda().contiguous()
+        prop.propagate(v, eps, p.dt, 50)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        prop.propagate(v, eps[100:], p.dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[str(N)] = {"M": N * N - 1, "nnz_QH0": lind.nnz("H", 0), "nnz_QH1": lind.nnz("H", 1),
+                       "nnz_R": lind.nnz("L", 0), "nnz_union": union_nnz(lind, torch),
+                       "assembly_ms": 1e3 * t_asm, "steps_per_s": steps / (ms / 1e3),
+                       "steps_per_period": p.steps_per_period}
+        log(f"plain N={N}: {res[str(N)]['steps_per_s']:.0f} steps/s, assembly {1e3 * t_asm:.1f} ms")
+    return res
+
+
 def batched_report(sb, torch, steps=200):
     """Batched form: the 512-instance dimer workload (N in {51,...,301},
     A ~ U[0.5,3], gamma ~ logU[0.01,0.5]), one launch per RK4 stage for all
@@ -382,6 +416,7 @@ def main():
     }
 
     # ---- batched and adjoint forms, reported against plain -----------------
+    out["plain_other_configs"] = small_configs_report(sb, torch)
     out["batched"] = None if args.no_batched else batched_report(sb, torch)
     out["adjoint"] = None if args.no_adjoint else adjoint_report(sb, torch)
 
