@@ -185,7 +185,8 @@ int sun_prop_create(sun_lind l, const double* static_w, const int32_t* dyn,
 /* Advance v (device double[M], in/out) by `steps` RK4 steps of size dt.
  * coef: device double[(2*steps+1) * ndyn]; row k holds c_d(t0 + k dt/2), so
  * the stages of step n read rows 2n, 2n+1, 2n+1, 2n+2.  Asynchronous on
- * `stream`.  Four kernel launches per step (one per stage). */
+ * `stream`.  Four kernel launches per step (one per stage), or one launch
+ * for all steps on the resident path (see sun_prop_tune_resident). */
 int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
                   int64_t steps, void* stream);
 /* Same as sun_propagate, recording along the way (Sec. IV step 3.2): after
@@ -250,6 +251,16 @@ int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_re
                   void* stream);
 int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,
                          int32_t flags, void* stream);
+/* Resident path (on by default for small generators -- at most 6000 fused
+ * nonzeros, 4(M+1) doubles within one workgroup's LDS, at most one
+ * time-dependent term -- and selectable up to the LDS limit): sun_propagate and
+ * sun_propagate_record keep v, the stage vectors and the accumulator in the
+ * LDS of a single workgroup and run all steps of a call (of a recording
+ * interval) in one launch, instead of four launches per step; rows are summed
+ * in the same order and rounding as by the sliced kernel.  on = 0 turns it
+ * off (sun_prop_tune and sun_prop_tune_sliced also do); on = 1 where it
+ * does not apply returns SUN_ENOTSUP. */
+int sun_prop_tune_resident(sun_prop p, int32_t on);
 /* Current layout, number of stored matrix entries (with padding), rows on
  * the long-row path, and bytes of matrix data plus per-row metadata one
  * stage launch streams (sliced layout: excluding the long rows' entries). */

@@ -62,6 +62,7 @@ PROTOS = {
     "sun_prop_spectral_radius": (C.c_int, [vp, P(f64), i32, P(f64), vp]),
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),
+    "sun_prop_tune_resident": (C.c_int, [vp, i32]),
     "sun_prop_layout": (C.c_int, [vp, P(i32), P(i64), P(i64), P(i64)]),
     "sun_prop_free": (None, [vp]),
     "sun_batch_create": (C.c_int, [P(vp), i32, P(i32), P(vp), P(vp), P(vp), P(f64), P(i64), vp, P(vp)]),

@@ -249,6 +249,10 @@ class Propagator:
         check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes), flags,
                                              _stream()))
 
+    def tune_resident(self, on: bool = True):
+        """Run all steps of a call in one single-workgroup launch (small systems)."""
+        check(self._lib.sun_prop_tune_resident(self.handle, int(bool(on))))
+
     def layout(self):
         lay, stored, nlong, nb = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
         check(self._lib.sun_prop_layout(self.handle, C.byref(lay), C.byref(stored), C.byref(nlong), C.byref(nb)))

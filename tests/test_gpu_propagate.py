@@ -318,3 +318,36 @@ def test_plain_N1001_first_period_properties(lib):
     assert np.linalg.eigvalsh(rho).min() >= -1e-9
     o = obs.cpu().numpy()
     assert np.all(np.abs(o) <= (N - 1) * (1 + 1e-12))
+
+
+def test_resident_path_matches_sliced_kernel(lib):
+    """The single-workgroup resident path against the sliced stage kernel at
+    N = 51: the same row order and roundings, so the same bits (no row of the
+    N = 51 generator exceeds 64 entries); also through the recorder, with a
+    partial last interval."""
+    flush("[propagate] resident vs sliced N=51")
+    p = dimer.plain_config(51)
+    ops = dimer.dimer_operators(p)
+    _, _, prop = _gpu_system(lib, p, ops)
+    steps = 250
+    eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+    v0 = torch.as_tensor(_fock_v0(51)).cuda()
+    prop.tune_resident(True)
+    a = v0.clone()
+    prop.propagate(a, eps, p.dt, steps)              # one launch for all steps
+    ra, _ = prop.record(v0.clone(), eps, p.dt, steps, 60)
+    prop.tune_sliced()                               # four launches per step
+    b = v0.clone()
+    prop.propagate(b, eps, p.dt, steps)
+    rb, _ = prop.record(v0.clone(), eps, p.dt, steps, 60)
+    assert torch.equal(a, b)
+    assert torch.equal(ra, rb)
+    prop.tune_resident(True)
+    c = v0.clone()
+    prop.propagate(c, eps, p.dt, steps)
+    assert torch.equal(a, c)
+    big = dimer.plain_config(101)
+    _, _, prop101 = _gpu_system(lib, big, dimer.dimer_operators(big))
+    with pytest.raises(lib.SunError):
+        prop101.tune_resident(True)                  # 4 (M + 1) doubles exceed the LDS
+
