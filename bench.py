@@ -215,7 +215,8 @@ def batched_report(sb, torch, steps=200):
         torch.cuda.synchronize()
         tstep = (time.perf_counter() - ta) / nst
         per_N[N] = {"instances": len(idx), "steps_per_period": p0.steps_per_period, "plain_us_per_step": 1e6 * tstep,
-                    "tile": tuned[g]["tile"], "rows_per_item": tuned[g]["rows_per_item"]}
+                    "tile": tuned[g]["tile"], "rows_per_item": tuned[g]["rows_per_item"],
+                    "path": tuned[g]["path"]}
         seq_time += len(idx) * tstep
     seq_rate = sum(len(idx) for (_, idx, _, _, _) in meta) / seq_time
     total_20T = sum(len(idx) * p0.steps for (_, idx, _, _, p0) in meta)

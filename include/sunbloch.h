@@ -308,8 +308,11 @@ int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream)
  * its own eighth of every group's (tile, block) items in tile-major order;
  * taken when every row of the group has at most 1024 entries, else path 1.  path 1: one
  * wavefront per (block of rows_per_item rows, instance tile), reading the
- * matrix from global memory.  Defaults 64, 64, 0.  Both paths add every
- * term's entries in row order: results do not depend on the tiling or path. */
+ * matrix from global memory.  path 2: path 0 with two consecutive instances
+ * per lane for tiles 16, 32 and 64 as well (tile/2 lanes per row; a group
+ * with a row of more than 1024 entries falls back to path 1).  Defaults 64,
+ * 64, 0.  All paths add every term's entries in row order: results do not
+ * depend on the tiling or path. */
 int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, int32_t path,
                    void* stream);
 int sun_batch_info(sun_batch b, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,

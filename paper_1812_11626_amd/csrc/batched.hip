@@ -13,7 +13,14 @@
 //
 // Layout.  Each group keeps one fused CSR whose row r lists the entries of
 // T_0 row r, then T_1 row r, ... (the free vector of a dissipator term as an
-// extra column M), with the segment boundaries per row.  The state of a
+// extra column M), with the segment boundaries per row.  Rows and columns
+// are stored in an interleaved order: generator S_p at 2p, J_p at 2p+1, the
+// diagonal generators D_l after them in their own order.  The diagonal part
+// of any Hamiltonian couples S_p with J_p, so in the grouped order
+// (S_0..S_{P-1}, J_0.., D_1..) every S row gathers from two regions P rows
+// apart; interleaved, neighbouring rows gather neighbouring state rows and
+// the L2 holds them.  Each row keeps its entries in the grouped column
+// order, so the sums are formed exactly as in the plain propagator.  The state of a
 // group is row-major [M+1][ld] with the instance index fastest (ld = number
 // of instances rounded up to the tile width), and X[M][b] = 1.  A wavefront
 // is split into 64/T lane groups of T lanes; each lane group handles one row
@@ -50,7 +57,7 @@ struct GroupDev {
   int64_t item0;         // first work item of this group (per-wavefront path)
   const int* blk_row;    // LDS path: row blocks [blk_row[i], blk_row[i+1])
   int nblk;              // LDS path: number of row blocks (0: per-wavefront path)
-  int vec;               // LDS path: instances per lane (2 for 128-instance tiles)
+  int vec;               // LDS path: instances per lane (tile = tile lanes x vec instances)
 };
 
 }  // namespace
@@ -60,6 +67,7 @@ struct sun_batch_s {
   std::vector<const sun_lind_s*> lind;
   std::vector<int> B, tile, rows_per_item;
   std::vector<int64_t> M, nnz, steps, done;
+  std::vector<int> P;       // pairs of the group's basis (interleaved stored order)
   std::vector<double> dt;
   std::vector<const double*> w, u, wave;
   std::vector<DevBuf<int>> rowptr, segptr, col;
@@ -71,7 +79,7 @@ struct sun_batch_s {
   std::vector<std::vector<int>> h_rowptr;   // host copies, for the LDS row-block partition
   std::vector<DevBuf<int>> blk_row;
   std::vector<int> nblk;    // row blocks of the LDS path (0: the group uses the per-wavefront path)
-  std::vector<int> path;    // 0: LDS path when every row fits, 1: per-wavefront path
+  std::vector<int> path;    // 0: LDS path when every row fits, 1: per-wavefront path, 2: as 0 with two instances per lane
 };
 
 namespace {
@@ -85,15 +93,22 @@ struct TermPtrs {
   const double* K[kMaxBTerms];
 };
 
-__global__ void k_batch_fuse(int64_t M, TermPtrs t, int mode, int64_t* __restrict__ cnt,
+// Grouped generator index -> stored row (S_p -> 2p, J_p -> 2p+1, D unchanged);
+// P = 0 is the identity.
+__device__ __host__ inline int64_t inter(int64_t i, int64_t P) {
+  return i < P ? 2 * i : (i < 2 * P ? 2 * (i - P) + 1 : i);
+}
+
+__global__ void k_batch_fuse(int64_t M, int64_t P, TermPtrs t, int mode, int64_t* __restrict__ cnt,
                              const int64_t* __restrict__ off, int* __restrict__ segptr, int* __restrict__ col,
                              double* __restrict__ val) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
-    int64_t w = mode ? off[r] : 0, n = 0;
+    const int64_t q = inter(r, P);   // stored row of grouped row r
+    int64_t w = mode ? off[q] : 0, n = 0;
     for (int a = 0; a < t.n; ++a) {
-      if (mode) segptr[r * t.n + a] = (int)(w + n);
+      if (mode) segptr[q * t.n + a] = (int)(w + n);
       for (int e = t.rowptr[a][r]; e < t.rowptr[a][r + 1]; ++e) {
-        if (mode) { col[w + n] = t.col[a][e]; val[w + n] = t.val[a][e]; }
+        if (mode) { col[w + n] = (int)inter(t.col[a][e], P); val[w + n] = t.val[a][e]; }
         ++n;
       }
       if (t.K[a] && t.K[a][r] != 0.0) {
@@ -101,7 +116,7 @@ __global__ void k_batch_fuse(int64_t M, TermPtrs t, int mode, int64_t* __restric
         ++n;
       }
     }
-    if (!mode) cnt[r] = n;
+    if (!mode) cnt[q] = n;
   }
 }
 
@@ -111,20 +126,23 @@ __global__ void k_b_i64_to_i32(int64_t n, const int64_t* __restrict__ a, int64_t
   if (blockIdx.x == 0 && threadIdx.x == 0) b[n] = (int)total;
 }
 
-// instance-major [B][M] <-> row-major [M+1][ld] (row M set to 1)
-__global__ void k_to_rowmajor(int M, int B, int ld, const double* __restrict__ src, double* __restrict__ dst) {
-  const int64_t total = (int64_t)(M + 1) * ld;
+// instance-major [B][M] (grouped order) <-> row-major [M+1][ld] (stored
+// order; row M set to 1)
+__global__ void k_to_rowmajor(int M, int P, int B, int ld, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t total = (int64_t)M * ld;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(i / ld), b = (int)(i % ld);
-    dst[i] = (r == M) ? 1.0 : (b < B ? src[(int64_t)b * M + r] : 0.0);
+    dst[inter(r, P) * ld + b] = b < B ? src[(int64_t)b * M + r] : 0.0;
   }
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < ld; b += (int64_t)gridDim.x * blockDim.x)
+    dst[(int64_t)M * ld + b] = 1.0;
 }
 
-__global__ void k_from_rowmajor(int M, int B, int ld, const double* __restrict__ src, double* __restrict__ dst) {
+__global__ void k_from_rowmajor(int M, int P, int B, int ld, const double* __restrict__ src, double* __restrict__ dst) {
   const int64_t total = (int64_t)M * B;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int b = (int)(i / M), r = (int)(i % M);
-    dst[i] = src[(int64_t)r * ld + b];
+    dst[i] = src[inter(r, P) * ld + b];
   }
 }
 
@@ -291,25 +309,28 @@ __device__ inline void lds_rows(const GroupDev& G, int64_t k0, int tb, int r0, i
   }
 }
 
-// Tile of 128 instances: 64 lanes per row, two consecutive instances per
-// lane (16-byte gathers, half the memory instructions per byte).  Each
-// instance's sums are formed in the same order as in lds_rows.
+// Tile of 2*G.tile instances: G.tile lanes (8, 16, 32 or 64) per row, two
+// consecutive instances per lane (16-byte gathers, half the memory
+// instructions per byte of one-instance lanes).  Each instance's sums are
+// formed in the same order as in lds_rows.
 template <int STAGE>
 __device__ inline void lds_rows_vec2(const GroupDev& G, int64_t k0, int tb, int r0, int nr, const int* s_col,
                                      const double* s_val, const int* s_rp, const int* s_seg, const double* s_cf) {
   const int tid = threadIdx.x;
-  const int lg = tid >> 6, lane = tid & 63;
+  const int lpr = G.tile;              // lanes per row, a power of two
+  const int lg = tid / lpr, lane = tid % lpr;
+  const int ngrp = 256 / lpr;
   const int nt = G.nt;
   const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
   const double ph = G.wave[k0 + krow];
   const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
   double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
   const int ld = G.ld;                 // a multiple of 128
-  const int b = tb * 128 + 2 * lane;   // instances b and b + 1
+  const int b = tb * 2 * lpr + 2 * lane;   // instances b and b + 1
   (void)ph;
   const double2* xb = reinterpret_cast<const double2*>(xin + b);
   const int ld2 = ld / 2;
-  for (int lr = lg; lr < nr; lr += 4) {
+  for (int lr = lg; lr < nr; lr += ngrp) {
     const int ee = s_rp[lr + 1];
     const int64_t ix = (int64_t)(r0 + lr) * ld + b;
     const bool own0 = b < G.B, own1 = b + 1 < G.B;
@@ -406,7 +427,7 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
     const int64_t k0 = 2 * step[gorder[gi]];
     const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
     const double ph = G.wave[k0 + krow];
-    const int tw = VEC == 2 ? 128 : G.tile;           // instances of this tile
+    const int tw = G.tile * VEC;                      // instances of this tile
     __syncthreads();   // the previous item's LDS contents are no longer read
     for (int i2 = tid; i2 < ne; i2 += 256) {
       s_col[i2] = G.col[e0 + i2];
@@ -446,9 +467,11 @@ void refresh_items(sun_batch_s& bt) {
   int64_t item = 0;
   for (int g = 0; g < bt.ngroups; ++g) {
     GroupDev& G = bt.ghost[g];
-    // a tile of 128 is 64 lanes with two instances each (LDS path only)
-    G.vec = (bt.tile[g] == 128 && bt.nblk[g] > 0) ? 2 : 1;
-    G.tile = std::min(bt.tile[g], 64);
+    // LDS path: a tile of 128 is 64 lanes with two instances each; path 2
+    // gives narrower tiles (16, 32, 64) two instances per lane as well
+    const bool two = bt.nblk[g] > 0 && (bt.tile[g] == 128 || (bt.path[g] == 2 && bt.tile[g] >= 16));
+    G.vec = two ? 2 : 1;
+    G.tile = two ? bt.tile[g] / 2 : std::min(bt.tile[g], 64);
     G.rows_per_item = bt.rows_per_item[g];
     G.ld = bt.ld[g];
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
@@ -524,6 +547,7 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->tile.assign(ngroups, 64);
       bt->rows_per_item.assign(ngroups, 64);
       bt->M.resize(ngroups);
+      bt->P.resize(ngroups);
       bt->nnz.resize(ngroups);
       bt->steps.resize(ngroups);
       bt->done.assign(ngroups, 0);
@@ -557,6 +581,7 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
         bt->lind[g] = l;
         bt->B[g] = B[g];
         bt->M[g] = l->basis->M;
+        bt->P[g] = l->basis->P;
         bt->steps[g] = steps[g];
         bt->dt[g] = dt[g];
         bt->w[g] = w[g];
@@ -574,7 +599,8 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
         }
         const int64_t M = bt->M[g];
         DevBuf<int64_t> cnt(M), off(M);
-        hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, t, 0, cnt.get(), nullptr,
+        const int64_t P = bt->P[g];
+        hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, P, t, 0, cnt.get(), nullptr,
                            nullptr, nullptr, nullptr);
         HIP_LAUNCH_OK();
         bt->nnz[g] = exclusive_scan_i64(cnt.get(), off.get(), M, s);
@@ -583,7 +609,7 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
         bt->segptr[g].alloc(M * nt);
         bt->col[g].alloc(bt->nnz[g] > 0 ? bt->nnz[g] : 1);
         bt->val[g].alloc(bt->nnz[g] > 0 ? bt->nnz[g] : 1);
-        hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, t, 1, nullptr, off.get(),
+        hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, P, t, 1, nullptr, off.get(),
                            bt->segptr[g].get(), bt->col[g].get(), bt->val[g].get());
         HIP_LAUNCH_OK();
         hipLaunchKernelGGL(k_b_i64_to_i32, dim3(grid_for(M, 256)), dim3(256), 0, s, M, off.get(), bt->nnz[g],
@@ -628,7 +654,8 @@ extern "C" int sun_batch_set_state(sun_batch bt, int32_t g, const double* V, voi
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
     hipStream_t s = as_stream(stream);
     const int64_t total = (bt->M[g] + 1) * bt->ld[g];
-    hipLaunchKernelGGL(k_to_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g], bt->B[g],
+    hipLaunchKernelGGL(k_to_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g],
+                       bt->P[g], bt->B[g],
                        bt->ld[g], V, bt->v[g].get());
     HIP_LAUNCH_OK();
     bt->done[g] = 0;
@@ -641,7 +668,8 @@ extern "C" int sun_batch_get_state(sun_batch bt, int32_t g, double* V, void* str
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
     hipStream_t s = as_stream(stream);
     const int64_t total = bt->M[g] * bt->B[g];
-    hipLaunchKernelGGL(k_from_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g], bt->B[g],
+    hipLaunchKernelGGL(k_from_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g],
+                       bt->P[g], bt->B[g],
                        bt->ld[g], bt->v[g].get(), V);
     HIP_LAUNCH_OK();
   });
@@ -655,7 +683,7 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
     SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
                 "tile must be 8, 16, 32, 64 or 128");
     SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= 65536, SUN_EINVAL, "rows_per_item out of range");
-    SUN_REQUIRE(path == 0 || path == 1, SUN_EINVAL, "path must be 0 or 1");
+    SUN_REQUIRE(path >= 0 && path <= 2, SUN_EINVAL, "path must be 0, 1 or 2");
     hipStream_t s = as_stream(stream);
     HIP_OK(hipStreamSynchronize(s));
     bt->tile[g] = tile;
