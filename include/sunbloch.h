@@ -339,8 +339,10 @@ int sun_adjoint_create(sun_lind l, const double* static_w, const int32_t* dyn, i
  * th] (host) plus, for the time-dependent term, dcoef[(k*ndyn + d)*ntheta +
  * th] (device, may be NULL = 0).  cobs: device double[M].  States are
  * checkpointed every ckpt_every steps and recomputed one interval at a time
- * in the reverse sweep (memory: (steps/ckpt_every + ckpt_every + 10) vectors
- * of M+1 doubles).  J_out: host double; grad_out: host double[ntheta] (may be
+ * in the reverse sweep, except the last interval, which the forward sweep
+ * keeps (memory: (steps/ckpt_every + ckpt_every + 10) vectors of M+1
+ * doubles, plus 3*ckpt_every vectors of stage inputs when they fit in
+ * 24 GiB).  J_out: host double; grad_out: host double[ntheta] (may be
  * NULL).  Synchronises. */
 int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, const double* dstatic,
                     const double* dcoef, int32_t ntheta, const double* cobs, double dt,

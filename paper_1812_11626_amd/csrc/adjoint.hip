@@ -18,7 +18,8 @@
 // generator runs on the same fused stage kernels (a second propagator built
 // from the transposed terms, with the reverse-mode vector updates fused in).
 // States are checkpointed every `ckpt_every` steps in the forward sweep; the
-// backward sweep recomputes one checkpoint interval at a time.
+// backward sweep recomputes one checkpoint interval at a time, except the
+// last, whose states and stage inputs the forward sweep leaves in place.
 #include <algorithm>
 #include <vector>
 
@@ -342,17 +343,32 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     }
     HIP_LAUNCH_OK();
     // ---- forward sweep with checkpoints --------------------------------------
+    // Up to the last interval the state ping-pongs between the first two
+    // interval slots; the last interval's states (and stage inputs) are
+    // written where the backward sweep reads them, so it is not recomputed.
+    const int64_t nlast = (nck - 1) * C;
     double* cur = w.per.get();
     double* nxt = w.per.get() + M1;
     HIP_OK(hipMemcpyAsync(cur, v0, M * sizeof(double), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, cur + M);
     hipLaunchKernelGGL(k_adj_fill, dim3(1), dim3(1), 0, s, (int64_t)1, 1.0, nxt + M);
-    for (int64_t n = 0; n < steps; ++n) {
+    for (int64_t n = 0; n < nlast; ++n) {
       if (n % C == 0) HIP_OK(hipMemcpyAsync(w.ck.get() + (n / C) * M1, cur, M1 * sizeof(double),
                                             hipMemcpyDeviceToDevice, s));
       forward_step(F, cur, nxt, w.x2.get(), w.x3.get(), w.x4.get(), w.acc.get(), coef, n, dt, s);
       std::swap(cur, nxt);
     }
+    if (cur != w.per.get())
+      HIP_OK(hipMemcpyAsync(w.per.get(), cur, M1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    auto interval_states = [&](int64_t n0, int64_t n1) {
+      double* P0 = w.per.get();
+      for (int64_t n = n0; n < n1; ++n) {
+        double* sx = keep_stages ? w.stg.get() + 3 * (n - n0) * M1 : nullptr;
+        forward_step(F, P0 + (n - n0) * M1, P0 + (n + 1 - n0) * M1, sx ? sx : w.x2.get(),
+                     sx ? sx + M1 : w.x3.get(), sx ? sx + 2 * M1 : w.x4.get(), w.acc.get(), coef, n, dt, s);
+      }
+    };
+    interval_states(nlast, steps);
     // ---- parameter-dependent terms ---------------------------------------
     // Each term that depends on a parameter gets its own static propagator
     // (unit weight, the term's free vector folded in); its dot products
@@ -412,13 +428,12 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     double* lacc = w.lacc.get();
     for (int64_t ci = nck - 1; ci >= 0; --ci) {
       const int64_t n0 = ci * C, n1 = std::min(steps, n0 + C);
-      // recompute the states v_{n0} .. v_{n1} of this interval
+      // recompute the states v_{n0} .. v_{n1} of this interval (the last
+      // one is still there from the forward sweep)
       double* P0 = w.per.get();
-      HIP_OK(hipMemcpyAsync(P0, w.ck.get() + ci * M1, M1 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      for (int64_t n = n0; n < n1; ++n) {
-        double* sx = keep_stages ? w.stg.get() + 3 * (n - n0) * M1 : nullptr;
-        forward_step(F, P0 + (n - n0) * M1, P0 + (n + 1 - n0) * M1, sx ? sx : w.x2.get(),
-                     sx ? sx + M1 : w.x3.get(), sx ? sx + 2 * M1 : w.x4.get(), w.acc.get(), coef, n, dt, s);
+      if (ci < nck - 1) {
+        HIP_OK(hipMemcpyAsync(P0, w.ck.get() + ci * M1, M1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        interval_states(n0, n1);
       }
       for (int64_t n = n1 - 1; n >= n0; --n) {
         const double* vn = P0 + (n - n0) * M1;
