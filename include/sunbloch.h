@@ -310,9 +310,12 @@ int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream)
  * wavefront per (block of rows_per_item rows, instance tile), reading the
  * matrix from global memory.  path 2: path 0 with two consecutive instances
  * per lane for tiles 16, 32 and 64 as well (tile/2 lanes per row; a group
- * with a row of more than 1024 entries falls back to path 1).  Defaults 64,
- * 64, 0.  All paths add every term's entries in row order: results do not
- * depend on the tiling or path. */
+ * with a row of more than 1024 entries falls back to path 1).  path 3 (tile
+ * 8, 16 or 32): path 2 with the state rows each block gathers staged in LDS
+ * too (blocks also limited to 4096/tile distinct columns; a group where one
+ * row exceeds that falls back to path 2).  Defaults 64, 64, 0.  All paths
+ * add every term's entries in row order: results do not depend on the
+ * tiling or path. */
 int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, int32_t path,
                    void* stream);
 int sun_batch_info(sun_batch b, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,

@@ -390,7 +390,9 @@ class BatchedPropagator:
     def tune(self, g: int, tile: int, rows_per_item: int, path: int = 0):
         """Tiling of group g; path 0 = LDS-staged row blocks (when every row
         fits), 1 = one wavefront per (rows, tile) reading the matrix from
-        global memory."""
+        global memory, 2 = path 0 with two instances per lane for every tile
+        width, 3 = path 2 with the gathered state rows staged in LDS as well
+        (tiles 8, 16, 32)."""
         check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), int(path), _stream()))
 
     def info(self, g: int):

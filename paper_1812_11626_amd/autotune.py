@@ -20,9 +20,11 @@ import torch
 TILES = (16, 32, 64, 128)
 ROWS = (32, 64, 128)
 # path 0: LDS-staged row blocks, one instance per lane below 128-instance
-# tiles; path 2: the same with two instances per lane for every tile width
-PATHS = (0, 2)
-UNIFORM = ((128, 64, 0), (128, 32, 0), (64, 64, 0), (16, 64, 2), (32, 64, 2))
+# tiles; path 2: the same with two instances per lane for every tile width;
+# path 3: path 2 with the gathered state rows staged in LDS (tiles 8-32)
+PATHS = (0, 2, 3)
+TILES3 = (8, 16, 32)
+UNIFORM = ((128, 64, 0), (128, 32, 0), (64, 64, 0), (16, 64, 2), (32, 64, 2), (16, 128, 3), (8, 128, 3))
 
 
 def cache_path() -> str:
@@ -51,13 +53,13 @@ def _save(path, data):
 
 def _key(G) -> str:
     name = torch.cuda.get_device_name(0).replace(" ", "_")
-    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds3"
+    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4"
 
 
 def _candidates(tiles, rows, paths):
     out = []
     for p in paths:
-        for t in tiles:
+        for t in (TILES3 if p == 3 else tiles):
             if p == 2 and t == 128:
                 continue               # 128-instance tiles are two per lane on path 0 already
             for r in rows:
@@ -108,7 +110,8 @@ def autotune_batched(bp, tiles=TILES, rows=ROWS, paths=PATHS, probe_steps: int =
         saved = [bp.get_state(g) for g in range(len(bp.groups))]
         steps = min(probe_steps, max(1, min(G["steps"] for G in bp.groups)))
         cands = [[(chosen[g]["tile"], chosen[g]["rows_per_item"], chosen[g]["path"]) for g in range(len(bp.groups))]]
-        cands += [[(t, r, p)] * len(bp.groups) for (t, r, p) in UNIFORM if t in tiles and p in paths]
+        cands += [[(t, r, p)] * len(bp.groups) for (t, r, p) in UNIFORM
+                  if (t in TILES3 if p == 3 else t in tiles) and p in paths]
         best = None
         for cand in cands:
             for g, (t, r, p) in enumerate(cand):

@@ -58,6 +58,10 @@ struct GroupDev {
   const int* blk_row;    // LDS path: row blocks [blk_row[i], blk_row[i+1])
   int nblk;              // LDS path: number of row blocks (0: per-wavefront path)
   int vec;               // LDS path: instances per lane (tile = tile lanes x vec instances)
+  int xlds;              // 1: the gathered state rows are staged in LDS as well (path 3)
+  const int* ucol_ptr;   // path 3: distinct columns of block i are ucol[ucol_ptr[i] .. ucol_ptr[i+1])
+  const int* ucol;
+  const unsigned short* lidx;   // path 3: position of every stored entry's column in its block's list
 };
 
 }  // namespace
@@ -79,7 +83,11 @@ struct sun_batch_s {
   std::vector<std::vector<int>> h_rowptr;   // host copies, for the LDS row-block partition
   std::vector<DevBuf<int>> blk_row;
   std::vector<int> nblk;    // row blocks of the LDS path (0: the group uses the per-wavefront path)
-  std::vector<int> path;    // 0: LDS path when every row fits, 1: per-wavefront path, 2: as 0 with two instances per lane
+  std::vector<int> path;    // 0: LDS path when every row fits, 1: per-wavefront path, 2: as 0 with two instances
+                            // per lane, 3: as 2 with the gathered state rows staged in LDS
+  std::vector<int> xl;      // 1 when the group runs path 3
+  std::vector<DevBuf<int>> xu_ptr, xu_col;
+  std::vector<DevBuf<unsigned short>> xu_lidx;
 };
 
 namespace {
@@ -398,7 +406,9 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
   // multiple of 8.  This kernel takes the groups with VEC instances per lane.
   const int x = blockIdx.x & 7;
   const int64_t K = gridDim.x >> 3;
-  auto items = [&](const GroupDev& G) -> int64_t { return G.vec == VEC ? (int64_t)G.nblk * G.tiles : 0; };
+  auto items = [&](const GroupDev& G) -> int64_t {
+    return (G.vec == VEC && !G.xlds) ? (int64_t)G.nblk * G.tiles : 0;
+  };
   int64_t total = 0;
   for (int q = 0; q < nactive; ++q) {
     const int64_t n = items(groups[gorder[q]]);
@@ -446,6 +456,210 @@ __global__ __launch_bounds__(256) void k_batch_stage_lds(const GroupDev* __restr
   }
 }
 
+// Path 3: the state rows a block gathers are staged in LDS too.  Every row
+// block carries the sorted list of its distinct columns (at most
+// kXLdsBytes / (8 T) of them for a tile of T instances) and each stored
+// entry the 16-bit position of its column in that list.  The staged rows are
+// loaded with independent, coalesced 16-byte loads before the row walk, so
+// the walk's gathers wait only on LDS, and a state row that several rows of
+// the block use is read from the memory system once per block.
+constexpr int kXLdsBytes = 32768;
+
+int xlds_cap(int tile) { return kXLdsBytes / (8 * tile); }
+
+template <int STAGE>
+__device__ inline void xlds_rows(const GroupDev& G, int64_t k0, int tb, int r0, int nr, const unsigned short* s_lx,
+                                 const double* s_val, const int* s_rp, const int* s_seg, const double* s_cf,
+                                 const double2* s_x) {
+  const int tid = threadIdx.x;
+  const int lpr = G.tile;              // lanes per row, a power of two
+  const int lg = tid / lpr, lane = tid % lpr;
+  const int ngrp = 256 / lpr;
+  const int nt = G.nt;
+  double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
+  const int ld = G.ld;
+  const int b = tb * 2 * lpr + 2 * lane;   // instances b and b + 1
+  (void)k0;
+  for (int lr = lg; lr < nr; lr += ngrp) {
+    const int ee = s_rp[lr + 1];
+    const int64_t ix = (int64_t)(r0 + lr) * ld + b;
+    const bool own0 = b < G.B, own1 = b + 1 < G.B;
+    const double2 vr = (own0 || own1) ? *reinterpret_cast<const double2*>(G.v + ix) : make_double2(0.0, 0.0);
+    const double2 ar = ((own0 || own1) && STAGE != 0) ? *reinterpret_cast<const double2*>(G.acc + ix)
+                                                        : make_double2(0.0, 0.0);
+    double y0 = 0.0, y1 = 0.0;
+    for (int a = 0; a < nt; ++a) {
+      const int s0 = s_seg[lr * nt + a];
+      const int s1 = (a + 1 < nt) ? s_seg[lr * nt + a + 1] : ee;
+      double p0 = 0.0, p1 = 0.0;
+      int e = s0;
+      for (; e + 4 <= s1; e += 4) {
+        const int c0 = s_lx[e], c1 = s_lx[e + 1], c2 = s_lx[e + 2], c3 = s_lx[e + 3];
+        const double v0 = s_val[e], v1 = s_val[e + 1], v2 = s_val[e + 2], v3 = s_val[e + 3];
+        const double2 x0 = s_x[c0 * lpr + lane], x1 = s_x[c1 * lpr + lane];
+        const double2 x2 = s_x[c2 * lpr + lane], x3 = s_x[c3 * lpr + lane];
+        p0 += v0 * x0.x;
+        p1 += v0 * x0.y;
+        p0 += v1 * x1.x;
+        p1 += v1 * x1.y;
+        p0 += v2 * x2.x;
+        p1 += v2 * x2.y;
+        p0 += v3 * x3.x;
+        p1 += v3 * x3.y;
+      }
+      for (; e < s1; ++e) {
+        const double v = s_val[e];
+        const double2 xx = s_x[s_lx[e] * lpr + lane];
+        p0 += v * xx.x;
+        p1 += v * xx.y;
+      }
+      const double2 cf = *reinterpret_cast<const double2*>(s_cf + a * kCfStride + 2 * lane);
+      y0 += cf.x * p0;
+      y1 += cf.y * p1;
+    }
+    double a0 = 0.0, a1 = 0.0;
+    const double o0 = lds_stage<STAGE>(vr.x, ar.x, y0, G.dt, a0);
+    const double o1 = lds_stage<STAGE>(vr.y, ar.y, y1, G.dt, a1);
+    if (own0 && own1) {
+      *reinterpret_cast<double2*>(xout + ix) = make_double2(o0, o1);
+      if (STAGE != 3) *reinterpret_cast<double2*>(G.acc + ix) = make_double2(a0, a1);
+    } else if (own0) {
+      xout[ix] = o0;
+      if (STAGE != 3) G.acc[ix] = a0;
+    }
+  }
+}
+
+// cf_len: doubles of the coefficient table at the start of the dynamic LDS
+// (the staged state rows follow it).
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_batch_stage_xlds(const GroupDev* __restrict__ groups,
+                                                          const int* __restrict__ gorder, int nactive,
+                                                          const int64_t* __restrict__ step, int cf_len) {
+  __shared__ unsigned short s_lx[kLdsCap];
+  __shared__ double s_val[kLdsCap];
+  __shared__ int s_rp[kLdsRows + 1];
+  __shared__ int s_seg[kLdsRows * kMaxBTerms];
+  extern __shared__ double s_dyn[];
+  double* s_cf = s_dyn;                                        // [nt][kCfStride]
+  double2* s_x = reinterpret_cast<double2*>(s_dyn + cf_len);   // [distinct columns][tile / 2]
+  const int tid = threadIdx.x;
+  // Work items and their walk as in k_batch_stage_lds.
+  const int x = blockIdx.x & 7;
+  const int64_t K = gridDim.x >> 3;
+  auto items = [&](const GroupDev& G) -> int64_t { return G.xlds ? (int64_t)G.nblk * G.tiles : 0; };
+  int64_t total = 0;
+  for (int q = 0; q < nactive; ++q) {
+    const int64_t n = items(groups[gorder[q]]);
+    total += n * (x + 1) / 8 - n * x / 8;
+  }
+  for (int64_t i = blockIdx.x >> 3; i < total; i += K) {
+    int gi = 0;
+    int64_t j = i, lo = 0;
+    for (;;) {
+      const int64_t n = items(groups[gorder[gi]]);
+      lo = n * x / 8;
+      const int64_t cnt = n * (x + 1) / 8 - lo;
+      if (j < cnt || gi + 1 == nactive) break;
+      j -= cnt;
+      ++gi;
+    }
+    const GroupDev& G = groups[gorder[gi]];
+    const int64_t local = lo + j;
+    const int tb = (int)(local / G.nblk);
+    const int blk = (int)(local % G.nblk);
+    const int r0 = G.blk_row[blk], r1 = G.blk_row[blk + 1];
+    const int nr = r1 - r0;
+    const int e0 = G.rowptr[r0];
+    const int ne = G.rowptr[r1] - e0;
+    const int u0 = G.ucol_ptr[blk];
+    const int nu = G.ucol_ptr[blk + 1] - u0;
+    const int nt = G.nt;
+    const int lpr = G.tile;
+    const int tw = 2 * lpr;
+    const int64_t k0 = 2 * step[gorder[gi]];
+    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+    const double ph = G.wave[k0 + krow];
+    const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
+    const double2* xin2 = reinterpret_cast<const double2*>(xin) + tb * lpr;
+    const int ld2 = G.ld / 2;
+    __syncthreads();   // the previous item's LDS contents are no longer read
+    for (int i2 = tid; i2 < nu * lpr; i2 += 256) {
+      const int d = i2 / lpr, q = i2 % lpr;
+      s_x[i2] = xin2[(int64_t)G.ucol[u0 + d] * ld2 + q];
+    }
+    for (int i2 = tid; i2 < ne; i2 += 256) {
+      s_lx[i2] = G.lidx[e0 + i2];
+      s_val[i2] = G.val[e0 + i2];
+    }
+    for (int i2 = tid; i2 <= nr; i2 += 256) s_rp[i2] = G.rowptr[r0 + i2] - e0;
+    for (int i2 = tid; i2 < nr * nt; i2 += 256) s_seg[i2] = G.segptr[(int64_t)r0 * nt + i2] - e0;
+    for (int i2 = tid; i2 < nt * tw; i2 += 256) {
+      const int a = i2 / tw, bl = i2 % tw;
+      const int b = tb * tw + bl;
+      s_cf[a * kCfStride + bl] = b < G.B ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
+    }
+    __syncthreads();
+    xlds_rows<STAGE>(G, k0, tb, r0, nr, s_lx, s_val, s_rp, s_seg, s_cf, s_x);
+  }
+}
+
+// Row blocks for path 3: at most max_rows rows, kLdsCap entries and ucap
+// distinct columns; with each block's sorted distinct columns and every
+// entry's position in them.  False if a single row does not fit.
+struct XPart {
+  std::vector<int> blk, uptr, ucol;
+  std::vector<unsigned short> lidx;
+};
+
+bool xlds_partition(const std::vector<int>& rp, const std::vector<int>& col, int max_rows, int ucap, XPart& out) {
+  const int M = (int)rp.size() - 1;
+  const int ncol = M + 1;                  // the free-vector column M included
+  // mark[c]: last block that holds column c; seen[c]: last candidate row
+  // examination that counted c (a row examined and left for the next block
+  // is examined again, under a new stamp)
+  std::vector<int> mark(ncol, -1), seen(ncol, -1);
+  out.blk.assign(1, 0);
+  int r0 = 0, nb = 0, stamp = 0;
+  while (r0 < M) {
+    int r1 = r0, used = 0;
+    while (r1 < M && r1 - r0 < max_rows && rp[r1 + 1] - rp[r0] <= kLdsCap) {
+      int fresh = 0;
+      ++stamp;
+      for (int e = rp[r1]; e < rp[r1 + 1]; ++e) {
+        const int c = col[e];
+        if (mark[c] != nb && seen[c] != stamp) { seen[c] = stamp; ++fresh; }
+      }
+      if (used + fresh > ucap) break;
+      for (int e = rp[r1]; e < rp[r1 + 1]; ++e) mark[col[e]] = nb;
+      used += fresh;
+      ++r1;
+    }
+    if (r1 == r0) return false;              // the row alone exceeds a limit
+    out.blk.push_back(r1);
+    r0 = r1;
+    ++nb;
+  }
+  out.uptr.assign(1, 0);
+  out.ucol.clear();
+  out.lidx.assign(rp[M], 0);
+  std::vector<int> u;
+  for (int b = 0; b < nb; ++b) {
+    const int e0 = rp[out.blk[b]], e1 = rp[out.blk[b + 1]];
+    u.assign(col.begin() + e0, col.begin() + e1);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    // the kernel's LDS tables hold exactly these limits
+    SUN_REQUIRE(e1 - e0 <= kLdsCap && (int)u.size() <= ucap && out.blk[b + 1] - out.blk[b] <= kLdsRows,
+                SUN_ENOTSUP, "internal: row block exceeds its LDS limits");
+    for (int e = e0; e < e1; ++e)
+      out.lidx[e] = (unsigned short)(std::lower_bound(u.begin(), u.end(), col[e]) - u.begin());
+    out.ucol.insert(out.ucol.end(), u.begin(), u.end());
+    out.uptr.push_back((int)out.ucol.size());
+  }
+  return true;
+}
+
 // Row blocks of at most max_rows rows and kLdsCap entries; empty if a single
 // row has more than kLdsCap entries (the group then takes the per-wavefront
 // path).
@@ -469,9 +683,13 @@ void refresh_items(sun_batch_s& bt) {
     GroupDev& G = bt.ghost[g];
     // LDS path: a tile of 128 is 64 lanes with two instances each; path 2
     // gives narrower tiles (16, 32, 64) two instances per lane as well
-    const bool two = bt.nblk[g] > 0 && (bt.tile[g] == 128 || (bt.path[g] == 2 && bt.tile[g] >= 16));
+    const bool two = bt.nblk[g] > 0 && (bt.tile[g] == 128 || (bt.path[g] >= 2 && bt.tile[g] >= 16) || bt.xl[g]);
     G.vec = two ? 2 : 1;
     G.tile = two ? bt.tile[g] / 2 : std::min(bt.tile[g], 64);
+    G.xlds = bt.xl[g];
+    G.ucol_ptr = bt.xl[g] ? bt.xu_ptr[g].get() : nullptr;
+    G.ucol = bt.xl[g] ? bt.xu_col[g].get() : nullptr;
+    G.lidx = bt.xl[g] ? bt.xu_lidx[g].get() : nullptr;
     G.rows_per_item = bt.rows_per_item[g];
     G.ld = bt.ld[g];
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
@@ -490,8 +708,34 @@ void refresh_items(sun_batch_s& bt) {
 int64_t wave_items(const GroupDev& G) { return G.nblk > 0 ? 0 : (int64_t)G.row_blocks * G.tiles; }
 
 void repartition(sun_batch_s& bt, int g) {
-  const std::vector<int> blk = bt.path[g] == 1 ? std::vector<int>{}
-                                               : lds_partition(bt.h_rowptr[g], std::min(bt.rows_per_item[g], kLdsRows));
+  const int max_rows = std::min(bt.rows_per_item[g], kLdsRows);
+  std::vector<int> blk;
+  bt.xl[g] = 0;
+  if (bt.path[g] == 3) {
+    std::vector<int> hcol(bt.nnz[g]);
+    if (bt.nnz[g] > 0)
+      HIP_OK(hipMemcpy(hcol.data(), bt.col[g].get(), bt.nnz[g] * sizeof(int), hipMemcpyDeviceToHost));
+    XPart xp;
+    if (xlds_partition(bt.h_rowptr[g], hcol, max_rows, xlds_cap(bt.tile[g]), xp)) {
+      blk = xp.blk;
+      bt.xu_ptr[g].alloc(xp.uptr.size());
+      bt.xu_col[g].alloc(std::max<size_t>(1, xp.ucol.size()));
+      bt.xu_lidx[g].alloc(std::max<size_t>(1, xp.lidx.size()));
+      HIP_OK(hipMemcpy(bt.xu_ptr[g].get(), xp.uptr.data(), xp.uptr.size() * sizeof(int), hipMemcpyHostToDevice));
+      if (!xp.ucol.empty())
+        HIP_OK(hipMemcpy(bt.xu_col[g].get(), xp.ucol.data(), xp.ucol.size() * sizeof(int), hipMemcpyHostToDevice));
+      if (!xp.lidx.empty())
+        HIP_OK(hipMemcpy(bt.xu_lidx[g].get(), xp.lidx.data(), xp.lidx.size() * sizeof(unsigned short),
+                         hipMemcpyHostToDevice));
+      bt.xl[g] = 1;
+    }
+  }
+  if (!bt.xl[g]) {
+    bt.xu_ptr[g].release();
+    bt.xu_col[g].release();
+    bt.xu_lidx[g].release();
+    if (bt.path[g] != 1) blk = lds_partition(bt.h_rowptr[g], max_rows);
+  }
   bt.nblk[g] = blk.empty() ? 0 : (int)blk.size() - 1;
   if (bt.nblk[g] > 0) {
     bt.blk_row[g].alloc(blk.size());
@@ -528,6 +772,36 @@ void alloc_state(sun_batch_s& bt, int g, hipStream_t s) {
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// One RK4 stage over all active groups: the per-wavefront kernel, the LDS
+// kernels (one or two instances per lane) and the path-3 kernel, each
+// launched only when some group takes it.
+struct StageLaunch {
+  const GroupDev* gd = nullptr;
+  const int* go = nullptr;
+  const int64_t* st = nullptr;
+  hipStream_t s = nullptr;
+  int nactive = 0, cf_len = 0;
+  int64_t nitems = 0, grid = 1, bgrid = 8, xgrid = 8;
+  bool v1 = false, v2 = false, xl = false;
+};
+
+template <int STAGE>
+void launch_stage(const StageLaunch& L) {
+  const size_t cf_bytes = (size_t)L.cf_len * sizeof(double);
+  if (L.nitems > 0)
+    hipLaunchKernelGGL(k_batch_stage<STAGE>, dim3((unsigned)L.grid), dim3(256), 0, L.s, L.gd, L.go, L.nactive,
+                       L.nitems, L.st);
+  if (L.v1)
+    hipLaunchKernelGGL((k_batch_stage_lds<STAGE, 1>), dim3((unsigned)L.bgrid), dim3(256), cf_bytes, L.s, L.gd, L.go,
+                       L.nactive, L.st);
+  if (L.v2)
+    hipLaunchKernelGGL((k_batch_stage_lds<STAGE, 2>), dim3((unsigned)L.bgrid), dim3(256), cf_bytes, L.s, L.gd, L.go,
+                       L.nactive, L.st);
+  if (L.xl)
+    hipLaunchKernelGGL(k_batch_stage_xlds<STAGE>, dim3((unsigned)L.xgrid), dim3(256), cf_bytes + kXLdsBytes, L.s,
+                       L.gd, L.go, L.nactive, L.st, L.cf_len);
+}
 
 }  // namespace
 
@@ -570,6 +844,10 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->blk_row.resize(ngroups);
       bt->nblk.assign(ngroups, 0);
       bt->path.assign(ngroups, 0);
+      bt->xl.assign(ngroups, 0);
+      bt->xu_ptr.resize(ngroups);
+      bt->xu_col.resize(ngroups);
+      bt->xu_lidx.resize(ngroups);
       for (int g = 0; g < ngroups; ++g) {
         const sun_lind_s* l = lind[g];
         SUN_REQUIRE(l != nullptr, SUN_EINVAL, "group system is NULL");
@@ -683,7 +961,8 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
     SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
                 "tile must be 8, 16, 32, 64 or 128");
     SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= 65536, SUN_EINVAL, "rows_per_item out of range");
-    SUN_REQUIRE(path >= 0 && path <= 2, SUN_EINVAL, "path must be 0, 1 or 2");
+    SUN_REQUIRE(path >= 0 && path <= 3, SUN_EINVAL, "path must be 0, 1, 2 or 3");
+    SUN_REQUIRE(path != 3 || tile == 8 || tile == 16 || tile == 32, SUN_EINVAL, "path 3 takes tiles 8, 16 or 32");
     hipStream_t s = as_stream(stream);
     HIP_OK(hipStreamSynchronize(s));
     bt->tile[g] = tile;
@@ -730,11 +1009,10 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     DevBuf<int64_t> stepidx(bt->ngroups);
     HIP_OK(hipMemcpyAsync(gorder.get(), ord.data(), bt->ngroups * sizeof(int), hipMemcpyHostToDevice, s));
     // prefix sums of work items in launch order (per-wavefront and LDS paths)
-    std::vector<int64_t> items_upto(bt->ngroups + 1, 0), blocks_upto(bt->ngroups + 1, 0);
+    std::vector<int64_t> items_upto(bt->ngroups + 1, 0);
     for (int q = 0; q < bt->ngroups; ++q) {
       const GroupDev& G = bt->ghost[ord[q]];
       items_upto[q + 1] = items_upto[q] + wave_items(G);
-      blocks_upto[q + 1] = blocks_upto[q] + (int64_t)G.nblk * G.tiles;
     }
     // the step index of every group lives in a device table: one row per step
     std::vector<int64_t> table((size_t)maxn * bt->ngroups);
@@ -748,67 +1026,37 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     for (int64_t n = 0; n < maxn; ++n) {
       int nactive = 0;
       while (nactive < bt->ngroups && todo[ord[nactive]] > n) ++nactive;
-      const int64_t nitems = items_upto[nactive];
-      const int64_t nblocks = blocks_upto[nactive];
-      const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((nitems + 3) / 4, (int64_t)ncu * 8));
-      const int64_t bgrid = std::max<int64_t>(8, (std::min<int64_t>(nblocks, (int64_t)ncu * 8) + 7) / 8 * 8);
-      bool any_vec1 = false, any_vec2 = false;
+      StageLaunch L;
+      L.nactive = nactive;
+      L.nitems = items_upto[nactive];
+      L.grid = std::max<int64_t>(1, std::min<int64_t>((L.nitems + 3) / 4, (int64_t)ncu * 8));
+      int64_t nlds = 0, nx = 0;
       int max_nt = 1;
       for (int q = 0; q < nactive; ++q) {
         const GroupDev& G = bt->ghost[ord[q]];
-        if (G.nblk > 0) {
-          (G.vec == 2 ? any_vec2 : any_vec1) = true;
-          max_nt = std::max(max_nt, G.nt);
+        if (G.nblk == 0) continue;
+        max_nt = std::max(max_nt, G.nt);
+        if (G.xlds) {
+          L.xl = true;
+          nx += (int64_t)G.nblk * G.tiles;
+        } else {
+          (G.vec == 2 ? L.v2 : L.v1) = true;
+          nlds += (int64_t)G.nblk * G.tiles;
         }
       }
-      const size_t cf_bytes = (size_t)max_nt * kCfStride * sizeof(double);
-      const int64_t* st = steptab.get() + n * bt->ngroups;
-      const GroupDev* gd = bt->gdev.get();
-      const int* go = gorder.get();
-      if (nitems > 0) {
-        hipLaunchKernelGGL(k_batch_stage<0>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
-      }
-      if (nblocks > 0) {
-        if (any_vec1)
-          hipLaunchKernelGGL((k_batch_stage_lds<0, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-        if (any_vec2)
-          hipLaunchKernelGGL((k_batch_stage_lds<0, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-      }
-      if (nitems > 0) {
-        hipLaunchKernelGGL(k_batch_stage<1>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
-      }
-      if (nblocks > 0) {
-        if (any_vec1)
-          hipLaunchKernelGGL((k_batch_stage_lds<1, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-        if (any_vec2)
-          hipLaunchKernelGGL((k_batch_stage_lds<1, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-      }
-      if (nitems > 0) {
-        hipLaunchKernelGGL(k_batch_stage<2>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
-      }
-      if (nblocks > 0) {
-        if (any_vec1)
-          hipLaunchKernelGGL((k_batch_stage_lds<2, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-        if (any_vec2)
-          hipLaunchKernelGGL((k_batch_stage_lds<2, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-      }
-      if (nitems > 0) {
-        hipLaunchKernelGGL(k_batch_stage<3>, dim3((unsigned)grid), dim3(256), 0, s, gd, go, nactive, nitems, st);
-      }
-      if (nblocks > 0) {
-        if (any_vec1)
-          hipLaunchKernelGGL((k_batch_stage_lds<3, 1>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-        if (any_vec2)
-          hipLaunchKernelGGL((k_batch_stage_lds<3, 2>), dim3((unsigned)bgrid), dim3(256), cf_bytes, s, gd, go, nactive,
-                             st);
-      }
+      // grids are multiples of 8 (one share per XCD); path 3 holds ~50 KB of
+      // LDS per workgroup, so three per CU are resident
+      L.bgrid = std::max<int64_t>(8, (std::min<int64_t>(nlds, (int64_t)ncu * 8) + 7) / 8 * 8);
+      L.xgrid = std::max<int64_t>(8, (std::min<int64_t>(nx, (int64_t)ncu * 3) + 7) / 8 * 8);
+      L.cf_len = max_nt * kCfStride;
+      L.st = steptab.get() + n * bt->ngroups;
+      L.gd = bt->gdev.get();
+      L.go = gorder.get();
+      L.s = s;
+      launch_stage<0>(L);
+      launch_stage<1>(L);
+      launch_stage<2>(L);
+      launch_stage<3>(L);
     }
     HIP_LAUNCH_OK();
     for (int g = 0; g < bt->ngroups; ++g) bt->done[g] += todo[g];

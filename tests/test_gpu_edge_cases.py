@@ -160,3 +160,18 @@ def test_propagate_argument_checks(lib):
         prop.tune_sliced(unroll=5)                                              # unsupported unroll
     with pytest.raises(lib.SunError):
         lind.propagator([1.0, 0.0, 0.1], [0, 1, 2, 0, 1])                       # > 4 dynamic terms
+
+
+def test_batch_tune_argument_checks(lib):
+    from helpers import dimer_batch
+    inst = [dimer.plain_config(4) for _ in range(3)]
+    bp, _ = dimer_batch(lib, inst, 4)
+    for tile, rows, path in ((12, 64, 0),        # tile not a power of two in range
+                             (64, 0, 0),         # no rows per item
+                             (16, 64, 4),        # unknown path
+                             (64, 64, 3),        # path 3 takes tiles 8, 16, 32
+                             (128, 64, 3)):
+        with pytest.raises(lib.SunError):
+            bp.tune(0, tile, rows, path)
+    bp.tune(0, 16, 64, 3)                        # valid after the rejected calls
+    bp.run(4)
