@@ -223,11 +223,12 @@ int sun_propagate_profile(sun_prop p, double* v, const double* coef, double dt,
  * (row blocks, or slices + long rows), rows M. */
 int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
 /* Two device layouts exist for the stage kernel:
- *  1 (default when ndyn <= 1) sliced ELL: rows of at most long_len nonzeros
+ *  1 (default when ndyn <= 1 and the fused generator has more than 100,000
+ *    stored nonzeros) sliced ELL: rows of at most long_len nonzeros
  *    are sorted by length inside windows of sigma rows and packed 64 per
  *    slice, one wavefront lane per row; longer rows are reduced by one
  *    wavefront each.
- *  0 (default when ndyn > 1) CSR stream: row blocks of about block_nnz
+ *  0 (default otherwise: faster for small generators) CSR stream: row blocks of about block_nnz
  *    nonzeros are streamed into LDS by a workgroup of `threads` lanes, then
  *    reduced one lane per row.
  * Rows summed by one lane (all of layout 0, the short rows of layout 1) add
@@ -245,7 +246,7 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  * let the matrix stay in the memory-side cache between launches when it
  * fits); bits 16-23 the entries a lane loads per round (0 = 8, or 4, 6,
  * 12, 16).  Other bits must be 0 (else SUN_EINVAL).  Defaults: block_nnz 1024,
- * threads 256, xcd_remap 0; sigma 4096, long_len 64, min_col_bytes 1,
+ * threads 256, xcd_remap 1; sigma 4096, long_len 64, min_col_bytes 1,
  * flags 1. */
 int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
                   void* stream);

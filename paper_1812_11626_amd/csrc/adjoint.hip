@@ -390,8 +390,16 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
           std::vector<double> unit(a->nt, 0.0);
           unit[t] = 1.0;
           sun_prop q = nullptr;
-          const int st = sun_prop_create(const_cast<sun_lind_s*>(a->lind), unit.data(), nullptr, 0, stream, &q);
+          int st = sun_prop_create(const_cast<sun_lind_s*>(a->lind), unit.data(), nullptr, 0, stream, &q);
           if (st != SUN_OK) SUN_THROW(st, std::string("term propagator: ") + sun_last_error());
+          // the dot-product kernel reads the sliced layout (small terms start in the stream layout)
+          if (q->layout != 1) {
+            st = sun_prop_tune_sliced(q, 4096, 64, 1, 1, stream);
+            if (st != SUN_OK) {
+              sun_prop_free(q);
+              SUN_THROW(st, std::string("term propagator layout: ") + sun_last_error());
+            }
+          }
           a->termp[t] = q;
         }
         int slot = -1;

@@ -16,7 +16,7 @@ struct sun_prop_s {
   int64_t nblocks = 0;
   int block_nnz = 1024;
   int threads = 256;
-  int xcd_remap = 0;
+  int xcd_remap = 1;
   DevBuf<double> vaug, xa, xb, acc;
   // sliced-ELL layout (used when ndyn <= 1)
   int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows
@@ -35,6 +35,10 @@ struct sun_prop_s {
 };
 
 namespace sun {
+
+// Largest fused generator (stored nonzeros) that sun_prop_create puts in the
+// CSR stream layout rather than the sliced one.
+constexpr int64_t kStreamMaxNnz = 100000;
 
 // One launch of stage `stage` of the fused generator on the given vectors.
 // Forward RK4 stages 0..3 (see propagate.hip):

@@ -1094,7 +1094,12 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
                          p->rowptr.get());
       HIP_LAUNCH_OK();
       build_partition(*p, s);
-      p->layout = ndyn <= 1 ? 1 : 0;
+      // sliced ELL for large generators; the CSR stream layout for small ones,
+      // where its one load round per block beats the sliced kernel's per-lane
+      // chains (measured on the dimer: 5.3 against 7.4 us per stage at
+      // 45,773 nonzeros, 6.0 against 6.6 at 93,000; from ~190,000 on the
+      // sliced kernel is ahead)
+      p->layout = (ndyn <= 1 && p->nnz > kStreamMaxNnz) ? 1 : 0;
       if (p->layout == 1) build_sell(*p, s);
       // one workgroup wins while the whole generator is small (measured on
       // the dimer: 2.9x faster at 140 nonzeros, 1.1x at 4,200, slower from

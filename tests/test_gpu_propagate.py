@@ -6,6 +6,8 @@ tier at N = 4, column tier at N = 51) and RK4 on the density matrix itself
 (N = 51, 1001), which shares nothing with the Bloch form but the drive table.
 """
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -182,14 +184,14 @@ def test_deterministic_and_block_size_invariant(lib):
 
 
 def test_sliced_layout_matches_stream_layout(lib):
-    """The sliced-ELL layout (default for <= 1 dynamic term) and the CSR
-    stream layout agree to rounding, and the sliced layout is deterministic,
-    for several window sizes and long-row thresholds (N = 51 has rows from 5
-    to 62 nonzeros)."""
+    """The sliced-ELL layout and the CSR stream layout (the default for a
+    generator this small) agree to rounding, and the sliced layout is
+    deterministic, for several window sizes and long-row thresholds (N = 51
+    has rows from 5 to 62 nonzeros)."""
     p = dimer.plain_config(51)
     ops = dimer.dimer_operators(p)
     _, _, prop = _gpu_system(lib, p, ops)
-    assert prop.layout()["layout"] == "sliced"
+    assert prop.layout()["layout"] == "stream"
     eps = torch.as_tensor(dimer.drive_table(p, steps=300)).cuda().contiguous()
     v0 = torch.as_tensor(_fock_v0(51)).cuda()
     prop.tune(1024, 256, False)
@@ -296,11 +298,31 @@ def test_plain_N51_full_horizon(lib):
     assert worst <= TOL
 
 
-def test_plain_N1001_first_period_properties(lib):
-    """The N = 1001 workload over its first period (16,384 steps): the oracle
-    cannot follow that far, so check what holds for any exact solution and
-    RK4 keeps to rounding: purity Tr(rho^2) = 1/N + |v|^2 <= 1, rho positive
-    semidefinite (eigenvalues >= -1e-9), <n1 - n2> inside its spectrum."""
+def _golden_n1001():
+    """Oracle values of tests/golden/dimer_n1001_period.txt (written by
+    make_dimer_n1001_period.py from the density-matrix RK4 oracle)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dimer_n1001_period.txt")
+    obs, idx, val = {}, [], []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            kind, k, x = line.split()
+            if kind == "obs":
+                obs[int(k)] = float(x)
+            else:
+                idx.append(int(k))
+                val.append(float(x))
+    return obs, np.asarray(idx), np.asarray(val)
+
+
+def test_plain_N1001_first_period(lib):
+    """The N = 1001 workload over its first period (16,384 steps), in the
+    launch configuration the benchmark times: <n1 - n2> every 1024 steps and
+    sampled entries of v at the end against the oracle's density-matrix RK4
+    (stored values), and what holds for any exact solution and RK4 keeps to
+    rounding: purity Tr(rho^2) = 1/N + |v|^2 <= 1, rho positive semidefinite
+    (eigenvalues >= -1e-9), <n1 - n2> inside its spectrum."""
     N = 1001
     flush(f"[propagate] N={N} first period")
     p = dimer.plain_config(N)
@@ -318,6 +340,10 @@ def test_plain_N1001_first_period_properties(lib):
     assert np.linalg.eigvalsh(rho).min() >= -1e-9
     o = obs.cpu().numpy()
     assert np.all(np.abs(o) <= (N - 1) * (1 + 1e-12))
+    g_obs, g_idx, g_val = _golden_n1001()
+    want_obs = np.asarray([g_obs[k] for k in range(1, len(o) + 1)])
+    assert rel_vec_err(o, want_obs) <= TOL
+    assert rel_vec_err(vv[g_idx], g_val) <= TOL
 
 
 def test_resident_path_matches_sliced_kernel(lib):
