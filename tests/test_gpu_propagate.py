@@ -302,6 +302,8 @@ def _golden_n1001():
     """Oracle values of tests/golden/dimer_n1001_period.txt (written by
     make_dimer_n1001_period.py from the density-matrix RK4 oracle)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dimer_n1001_period.txt")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/dimer_n1001_period.txt not written (make_dimer_n1001_period.py)")
     obs, idx, val = {}, [], []
     with open(path) as fh:
         for line in fh:
