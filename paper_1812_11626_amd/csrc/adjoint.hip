@@ -139,21 +139,28 @@ constexpr int kDotBlocks = 512;
 constexpr int kMaxTheta = 8;
 constexpr int kMaxGTerms = 8;
 
-// part[blk] += scale * (this block's share of a . b), accumulated over calls
-// in stream order (fixed order per slot).
-__global__ __launch_bounds__(256) void k_dot_acc(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
-                                                 double scale, double* __restrict__ part) {
-  __shared__ double sh[256];
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    s += a[i] * b[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
+// Running per-thread sums for a time average: each thread of the fixed grid
+// (nbj blocks of 256) adds c[i] a_s[i] over its rows i, for the count vectors
+// a_s = a0 + s * stride taken from the last to the first, to its own slot of
+// run.  The additions into a slot follow the global order of the states
+// however the calls split them, so the result does not depend on how the
+// states are grouped into calls.
+__global__ __launch_bounds__(256) void k_dot_acc_states(int64_t n, const double* __restrict__ c,
+                                                        const double* __restrict__ a0, int64_t stride, int64_t count,
+                                                        double* __restrict__ run) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = run[gid];
+  for (int64_t k = count - 1; k >= 0; --k) {
+    const double* a = a0 + k * stride;
+    for (int64_t i = gid; i < n; i += (int64_t)gridDim.x * blockDim.x) s += c[i] * a[i];
   }
-  if (threadIdx.x == 0) part[blockIdx.x] += scale * sh[0];
+  run[gid] = s;
+}
+
+// out[i] = a[i] * w for i < n, out[n] = 0
+__global__ void k_adj_scaled(int64_t n, const double* __restrict__ a, double w, double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = i < n ? a[i] * w : 0.0;
 }
 
 // Sum of n partials by one workgroup in a fixed order (strided per lane,
@@ -193,14 +200,6 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double* __restrict__ p
   __shared__ double sh[256];
   const double s = block_sum_fixed(part, nblk, sh);
   if (threadIdx.x == 0) out[0] += scale * s;
-}
-
-// out[i] = sum over the n partials part[i * n + k], k = 0..n-1, in a fixed
-// order; one workgroup per output.
-__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ part, int n, double* __restrict__ out) {
-  __shared__ double sh[256];
-  const double s = block_sum_fixed(part + (int64_t)blockIdx.x * n, n, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // out[th] = sum over y < ny and k < n of part[(y * ntheta + th) * n + k], in a
@@ -289,7 +288,8 @@ struct Work {
   DevBuf<double> ck;        // checkpoints [(nck) * (M+1)]
   DevBuf<double> per;       // states of one interval [(C+1) * (M+1)]
   DevBuf<double> stg;       // stage inputs of one interval [C][3][M+1] (optional)
-  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb4, kb3, kb2, kb1, gpart, jpart, dev_grad, dev_J, dstat;
+  DevBuf<double> x2, x3, x4, acc, lam, lacc, kb4, kb3, kb2, kb1, gpart, jrun, dev_grad, dev_J, dstat;
+  DevBuf<double> cw, zero;  // objective weights c/S_avg, and zeros (M+1 each)
 };
 
 }  // namespace
@@ -326,10 +326,16 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     }
     for (DevBuf<double>* b : {&w.x2, &w.x3, &w.x4, &w.acc, &w.lam, &w.lacc, &w.kb4, &w.kb3, &w.kb2, &w.kb1})
       b->alloc(M1);
-    // per-block accumulator of the objective's dot products
+    // per-thread running sums of the objective's dot products (nbj blocks of 256)
     const int nbj = dot_blocks(M);
-    w.jpart.alloc(nbj);
-    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(nbj, 256)), dim3(256), 0, s, (int64_t)nbj, 0.0, w.jpart.get());
+    w.jrun.alloc((size_t)nbj * 256);
+    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for((int64_t)nbj * 256, 256)), dim3(256), 0, s, (int64_t)nbj * 256, 0.0,
+                       w.jrun.get());
+    w.cw.alloc(M1);
+    w.zero.alloc(M1);
+    hipLaunchKernelGGL(k_adj_scaled, dim3(grid_for(M1, 256)), dim3(256), 0, s, M, cobs, 1.0 / (double)S_avg,
+                       w.cw.get());
+    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(M1, 256)), dim3(256), 0, s, M1, 0.0, w.zero.get());
     w.dev_grad.alloc(kMaxTheta);
     w.dev_J.alloc(1);
     w.dstat.alloc(a->nt * (ntheta > 0 ? ntheta : 1));
@@ -443,15 +449,20 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
         HIP_OK(hipMemcpyAsync(P0, w.ck.get() + ci * M1, M1 * sizeof(double), hipMemcpyDeviceToDevice, s));
         interval_states(n0, n1);
       }
+      // J: the states v_{n+1} of this interval inside the averaging window, in one launch
+      const int64_t j0 = std::max(n0 + 1, first_avg);
+      if (j0 <= n1)
+        hipLaunchKernelGGL(k_dot_acc_states, dim3(nbj), dim3(256), 0, s, M, cobs, P0 + (j0 - n0) * M1, M1,
+                           n1 - j0 + 1, w.jrun.get());
       for (int64_t n = n1 - 1; n >= n0; --n) {
         const double* vn = P0 + (n - n0) * M1;
-        const double* vn1 = P0 + (n + 1 - n0) * M1;
         const bool in_avg = (n + 1) >= first_avg;
-        if (in_avg)
-          hipLaunchKernelGGL(k_dot_acc, dim3(nbj), dim3(256), 0, s, M, cobs, vn1, 1.0 / (double)S_avg, w.jpart.get());
-        // lambda += c/S (direct dependence of J on v_{n+1}); kb4 = dt/6 lambda
-        hipLaunchKernelGGL(k_adj_prep, dim3(grid_for(M, 256)), dim3(256), 0, s, M, lam, cobs,
-                           in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb4.get());
+        // lambda += c/S (direct dependence of J on v_{n+1}); kb4 = dt/6 lambda.
+        // After the first backward step the previous step's last stage
+        // (stage 8) has done this already.
+        if (n == steps - 1)
+          hipLaunchKernelGGL(k_adj_prep, dim3(grid_for(M, 256)), dim3(256), 0, s, M, lam, cobs,
+                             in_avg ? 1.0 / (double)S_avg : 0.0, dt6, w.kb4.get());
         // forward stage inputs of step n (kept from the interval recompute,
         // or recomputed here)
         const double *x2 = w.x2.get(), *x3 = w.x3.get(), *x4 = w.x4.get();
@@ -468,12 +479,20 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
         prop_stage(B, 4, w.kb4.get(), lam, lacc, w.kb3.get(), coef, 2 * n + 2, dt, s);
         prop_stage(B, 5, w.kb3.get(), lam, lacc, w.kb2.get(), coef, 2 * n + 1, dt, s);
         prop_stage(B, 6, w.kb2.get(), lam, lacc, w.kb1.get(), coef, 2 * n + 1, dt, s);
-        prop_stage(B, 7, w.kb1.get(), lam, lacc, nullptr, coef, 2 * n, dt, s);
         // parameter terms: kb_i . (dT/dtheta x_i) for the stage inputs x4, x3, x2, v_n
+        // (before the last stage, which overwrites kb4 with the next step's)
         const double* xs[4] = {x4, x3, x2, vn};
         const double* kbs[4] = {w.kb4.get(), w.kb3.get(), w.kb2.get(), w.kb1.get()};
         const int64_t krows[4] = {2 * n + 2, 2 * n + 1, 2 * n + 1, 2 * n};
         grad_step(xs, kbs, krows);
+        if (n > 0) {
+          // stage 7 and the next step's start: lambda_n += c/S if v_n is averaged
+          const bool next_avg = n >= first_avg;
+          prop_stage(B, 8, w.kb1.get(), next_avg ? w.cw.get() : w.zero.get(), lacc, w.kb4.get(), coef, 2 * n, dt,
+                     s);
+        } else {
+          prop_stage(B, 7, w.kb1.get(), lam, lacc, nullptr, coef, 2 * n, dt, s);
+        }
         std::swap(lam, lacc);
       }
     }
@@ -481,7 +500,8 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     if (ntheta > 0 && nslot > 0)
       hipLaunchKernelGGL(k_sum_slots, dim3(ntheta), dim3(256), 0, s, w.gpart.get(), ny, ntheta, (int)nslot,
                          w.dev_grad.get());
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, w.jpart.get(), nbj, w.dev_J.get());
+    hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(256), 0, s, w.jrun.get(), nbj * 256, 1.0 / (double)S_avg,
+                       w.dev_J.get());
     HIP_LAUNCH_OK();
     double hg[kMaxTheta];
     HIP_OK(hipMemcpyAsync(hg, w.dev_grad.get(), sizeof(hg), hipMemcpyDeviceToHost, s));

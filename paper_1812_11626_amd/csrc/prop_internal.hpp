@@ -48,7 +48,8 @@ constexpr int64_t kStreamMaxNnz = 100000;
 // generator; vin = lambda, acc = lambda accumulator, xout = next cotangent):
 //   k = G(t)^T xin;  4: acc = vin + k, xout = dt/3 vin + dt k;
 //   5: acc += k, xout = dt/3 vin + dt/2 k;  6: acc += k, xout = dt/6 vin + dt/2 k;
-//   7: acc += k.
+//   7: acc += k;  8: acc = (acc + k) + vin, xout = dt/6 acc (stage 7 fused with
+//   the start of the next backward step).
 // Vectors have M+1 entries with entry M equal to 1.
 void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
                 const double* coef, int64_t coef_row, double dt, hipStream_t s);

@@ -161,8 +161,15 @@ __device__ inline void stage_store(int r, double k, double vr, double ar, double
   } else if (STAGE == 6) {
     acc[r] = ar + k;
     xout[r] = (dt / 6.0) * vr + (0.5 * dt) * k;
-  } else {
+  } else if (STAGE == 7) {
     acc[r] = ar + k;
+  } else {
+    // stage 7 followed by the start of the next backward step: the new
+    // lambda gets vin (the objective's weight on the state, or 0) added and
+    // xout receives dt/6 lambda
+    const double l = (ar + k) + vr;
+    acc[r] = l;
+    xout[r] = (dt / 6.0) * l;
   }
 }
 
@@ -972,7 +979,8 @@ void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double*
     case 4: launch_stage_v<4>(p, xin, vin, acc, xout, coef, row, dt, s); break;
     case 5: launch_stage_v<5>(p, xin, vin, acc, xout, coef, row, dt, s); break;
     case 6: launch_stage_v<6>(p, xin, vin, acc, xout, coef, row, dt, s); break;
-    default: launch_stage_v<7>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    case 7: launch_stage_v<7>(p, xin, vin, acc, xout, coef, row, dt, s); break;
+    default: launch_stage_v<8>(p, xin, vin, acc, xout, coef, row, dt, s); break;
   }
   HIP_LAUNCH_OK();
 }
