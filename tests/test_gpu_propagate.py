@@ -379,3 +379,27 @@ def test_resident_path_matches_sliced_kernel(lib):
     with pytest.raises(lib.SunError):
         prop101.tune_resident(True)                  # 4 (M + 1) doubles exceed the LDS
 
+
+
+def test_periodic_steady_state_N4(lib):
+    """300 drive periods (60,000 steps) of the N = 4 workload on the GPU from
+    the Fock state land on the fixed point of the oracle's one-period RK4
+    map, v* = (1 - Phi)^-1 phi (computed by linear algebra, not by stepping)."""
+    flush("[propagate] periodic steady state N=4")
+    p = dimer.plain_config(4)
+    ops = dimer.dimer_operators(p)
+    F = ob.generators(4)
+    G0 = lb.q_hamiltonian(F, ops["H0"].to_dense()) + p.gamma_eff * lb.q_dissipator(F, ops["L"].to_dense())
+    G1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    K = p.gamma_eff * lb.k_dissipator(F, ops["L"].to_dense())
+    S = p.steps_per_period
+    eps1 = dimer.drive_table(p, steps=S)[:, None]
+    Phi = np.stack([pr.rk4_bloch(G0, [G1], None, np.eye(15)[j], eps1, p.dt, S) for j in range(15)], axis=1)
+    phi = pr.rk4_bloch(G0, [G1], K, np.zeros(15), eps1, p.dt, S)
+    vstar = np.linalg.solve(np.eye(15) - Phi, phi)
+    _, _, prop = _gpu_system(lib, p, ops)
+    periods = 300
+    eps = torch.as_tensor(dimer.drive_table(p, steps=periods * S)).cuda().contiguous()
+    v = torch.as_tensor(_fock_v0(4)).cuda().clone()
+    prop.propagate(v, eps, p.dt, periods * S)
+    assert rel_vec_err(v.cpu().numpy(), vstar) <= TOL

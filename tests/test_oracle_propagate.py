@@ -81,3 +81,51 @@ def test_bloch_rk4_sparse_equals_dense():
     a = pr.rk4_bloch(G0, [G1], K, v0, coef, p.dt, steps)
     b = pr.rk4_bloch(sp.csr_matrix(G0), [sp.csr_matrix(G1)], K, v0, coef, p.dt, steps)
     np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+def _one_period_map(p):
+    """The one-period RK4 map of the driven N = 4 dimer as v -> Phi v + phi
+    (RK4 on an affine ODE is affine in the state), from the dense generators."""
+    ops = dimer.dimer_operators(p)
+    F = basis.generators(p.N)
+    G0 = lb.q_hamiltonian(F, ops["H0"].to_dense()) + p.gamma_eff * lb.q_dissipator(F, ops["L"].to_dense())
+    G1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    K = p.gamma_eff * lb.k_dissipator(F, ops["L"].to_dense())
+    S = p.steps_per_period
+    eps = dimer.drive_table(p, steps=S)[:, None]
+    M = p.N * p.N - 1
+    Phi = np.stack([pr.rk4_bloch(G0, [G1], None, np.eye(M)[j], eps, p.dt, S) for j in range(M)], axis=1)
+    phi = pr.rk4_bloch(G0, [G1], K, np.zeros(M), eps, p.dt, S)
+    return F, G0, G1, K, eps, Phi, phi
+
+
+def test_driven_dimer_periodic_steady_state():
+    """With A != 0 the one-period RK4 map has one attracting fixed point v*
+    (spectral radius of Phi below 1): it is a valid state (rho* >= 0, trace
+    1), the trajectory from the Fock state reaches it after many periods, and
+    over one period from v* the population imbalance oscillates with the
+    drive and comes back (the asymptotic state is T-periodic, Sec. III)."""
+    p = dimer.plain_config(4)
+    F, G0, G1, K, eps, Phi, phi = _one_period_map(p)
+    M = Phi.shape[0]
+    assert np.abs(np.linalg.eigvals(Phi)).max() < 0.99
+    vstar = np.linalg.solve(np.eye(M) - Phi, phi)
+    rho = lb.density_from_bloch(F, vstar)
+    np.testing.assert_allclose(np.trace(rho), 1.0, atol=1e-13)
+    assert np.linalg.eigvalsh(0.5 * (rho + rho.conj().T)).min() > -1e-12
+    v0 = lb.bloch_vector(F, np.diag([1.0, 0.0, 0.0, 0.0]).astype(complex))
+    v = v0
+    for _ in range(300):
+        v = Phi @ v + phi
+    assert np.max(np.abs(v - vstar)) < 1e-12
+    # the same through the time stepper itself, from the Fock state
+    S = p.steps_per_period
+    eps_long = dimer.drive_table(p, steps=150 * S)[:, None]
+    vt = pr.rk4_bloch(G0, [G1], K, v0, eps_long, p.dt, 150 * S)
+    assert np.max(np.abs(vt - vstar)) < 1e-10
+    _, rec = pr.rk4_bloch(G0, [G1], K, vstar, eps, p.dt, S, record_every=S // 8)
+    # <n1 - n2> = Tr(X)/N + v . x with X = diag(-3, -1, 1, 3), Tr X = 0
+    n12 = np.real(lb.trace_against(F, np.diag([-3.0, -1.0, 1.0, 3.0]).astype(complex)))
+    obs = np.array([x @ n12 for x in rec])
+    assert np.max(np.abs(rec[-1] - vstar)) < 1e-12
+    assert obs.max() - obs.min() > 1e-3
