@@ -32,6 +32,11 @@ struct sun_adj_s {
   sun_lind_s lindT;             // transposed terms, K = 0
   sun_prop fwd = nullptr, bwd = nullptr;
   std::vector<sun_prop> termp;  // per term: the term alone (unit weight), for the parameter dot products
+  // transposed generator with each parameter-dependent term as its own
+  // segment (segmented sliced layout), for reverse stages with the dot
+  // products fused in; built for the term list revg_terms
+  sun_prop revg = nullptr;
+  std::vector<int> revg_terms;
   std::vector<double> static_w;
   std::vector<int> dyn;
   int nt = 0, ndyn = 0;
@@ -39,6 +44,7 @@ struct sun_adj_s {
   ~sun_adj_s() {
     if (fwd) sun_prop_free(fwd);
     if (bwd) sun_prop_free(bwd);
+    if (revg) sun_prop_free(revg);
     for (sun_prop q : termp)
       if (q) sun_prop_free(q);
   }
@@ -376,22 +382,70 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
     };
     interval_states(nlast, steps);
     // ---- parameter-dependent terms ---------------------------------------
-    // Each term that depends on a parameter gets its own static propagator
-    // (unit weight, the term's free vector folded in); its dot products
-    // kb . (T_j x + K_j) accumulate, weighted by dc_j/dtheta, in per-wavefront
-    // slots gpart[th * nslot + off_j + w].
-    struct GTerm { int term, slot; const sun_prop_s* p; int64_t off; };
-    std::vector<GTerm> gterms;
-    int64_t nslot = 0;
+    // The terms whose coefficient depends on a parameter.  Up to
+    // kMaxRevSeg of them: the reverse stages run on a transposed generator
+    // that keeps each of them as its own segment and form the dot products
+    // kb . (T_j x + K_j) = (T_jᵀ kb) . x + kb . K_j in the same pass,
+    // weighted by dc_j/dtheta, into per-wavefront slots gpart[th * ld + w].
+    // More of them: each gets its own static propagator (unit weight, free
+    // vector folded in) and one launch per step forms the products, into
+    // slots gpart[(y * ntheta + th) * nslot + off_j + w].
+    std::vector<int> used_terms;
     if (ntheta > 0) {
       std::vector<bool> used(a->nt, false);
       for (int d = 0; d < a->ndyn; ++d) used[a->dyn[d]] = true;
       for (int t = 0; t < a->nt; ++t)
         for (int th = 0; th < ntheta; ++th)
           if (dstatic[t * ntheta + th] != 0.0) used[t] = true;
+      for (int t = 0; t < a->nt; ++t)
+        if (used[t]) used_terms.push_back(t);
+    }
+    auto dyn_slot = [&](int t) {
+      for (int d = 0; d < a->ndyn; ++d)
+        if (a->dyn[d] == t) return d;
+      return -1;
+    };
+    const bool fused = !used_terms.empty() && (int)used_terms.size() <= kMaxRevSeg;
+    RevDot rd;
+    struct GTerm { int term, slot; const sun_prop_s* p; int64_t off; };
+    std::vector<GTerm> gterms;
+    int64_t nslot = 0;
+    if (fused) {
+      if (!a->revg || a->revg_terms != used_terms) {
+        if (a->revg) sun_prop_free(a->revg);
+        a->revg = nullptr;
+        std::vector<double> w0(a->static_w);
+        for (int t : used_terms) w0[t] = 0.0;    // their weights enter as segment coefficients
+        sun_prop q = nullptr;
+        const int st = sun_prop_create(&a->lindT, w0.data(), used_terms.data(), (int)used_terms.size(), stream, &q);
+        if (st != SUN_OK) SUN_THROW(st, std::string("segmented transposed propagator: ") + sun_last_error());
+        try {
+          prop_build_segments(*q, s);
+        } catch (...) {
+          sun_prop_free(q);
+          throw;
+        }
+        a->revg = q;
+        a->revg_terms = used_terms;
+      }
+      rd.nseg = (int)used_terms.size();
+      for (int d = 0; d < rd.nseg; ++d) {
+        const int t = used_terms[d];
+        rd.wseg[d] = a->static_w[t];
+        rd.slot[d] = dyn_slot(t);
+        rd.term[d] = t;
+        rd.K[d] = t >= a->lind->nH ? a->lind->K[t - a->lind->nH].get() : nullptr;
+      }
+      rd.coef = coef;
+      rd.ncoef = a->ndyn;
+      rd.dstat = w.dstat.get();
+      rd.dcoef = dcoef;
+      rd.ntheta = ntheta;
+      rd.ld = prop_rev_slots(*a->revg);
+      nslot = rd.ld;
+    } else {
       if (a->termp.size() != (size_t)a->nt) a->termp.assign(a->nt, nullptr);
-      for (int t = 0; t < a->nt; ++t) {
-        if (!used[t]) continue;
+      for (int t : used_terms) {
         if (!a->termp[t]) {
           std::vector<double> unit(a->nt, 0.0);
           unit[t] = 1.0;
@@ -408,18 +462,16 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
           }
           a->termp[t] = q;
         }
-        int slot = -1;
-        for (int d = 0; d < a->ndyn; ++d)
-          if (a->dyn[d] == t) slot = d;
-        gterms.push_back({t, slot, a->termp[t], nslot});
+        gterms.push_back({t, dyn_slot(t), a->termp[t], nslot});
         nslot += prop_dot_slots(*a->termp[t]);
       }
     }
-    const int ny = kDotStages / kDotStagesPerWave;
+    const int ny = fused ? 1 : kDotStages / kDotStagesPerWave;
     w.gpart.alloc(std::max<int64_t>(1, ny * ntheta * nslot));
     if (ntheta * nslot > 0)
       hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(ny * ntheta * nslot, 256)), dim3(256), 0, s, ny * ntheta * nslot,
                          0.0, w.gpart.get());
+    rd.gpart = w.gpart.get();
     std::vector<const sun_prop_s*> gp;
     std::vector<int> gterm, gslot;
     std::vector<int64_t> goff;
@@ -474,6 +526,20 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
           prop_stage(F, 0, vn, vn, w.acc.get(), w.x2.get(), coef, 2 * n, dt, s);
           prop_stage(F, 1, w.x2.get(), vn, w.acc.get(), w.x3.get(), coef, 2 * n + 1, dt, s);
           prop_stage(F, 2, w.x3.get(), vn, w.acc.get(), w.x4.get(), coef, 2 * n + 1, dt, s);
+        }
+        if (fused) {
+          // reverse stages with the dot products kb_i . (T_j x_i + K_j) fused in
+          const sun_prop_s& G = *a->revg;
+          prop_stage_dot(G, 4, w.kb4.get(), lam, lacc, w.kb3.get(), x4, rd, 2 * n + 2, dt, s);
+          prop_stage_dot(G, 5, w.kb3.get(), lam, lacc, w.kb2.get(), x3, rd, 2 * n + 1, dt, s);
+          prop_stage_dot(G, 6, w.kb2.get(), lam, lacc, w.kb1.get(), x2, rd, 2 * n + 1, dt, s);
+          if (n > 0)
+            prop_stage_dot(G, 8, w.kb1.get(), n >= first_avg ? w.cw.get() : w.zero.get(), lacc, w.kb4.get(), vn, rd,
+                           2 * n, dt, s);
+          else
+            prop_stage_dot(G, 7, w.kb1.get(), lam, lacc, nullptr, vn, rd, 2 * n, dt, s);
+          std::swap(lam, lacc);
+          continue;
         }
         // stage 4: kb4 with x4 at t_{n+1}
         prop_stage(B, 4, w.kb4.get(), lam, lacc, w.kb3.get(), coef, 2 * n + 2, dt, s);

@@ -32,6 +32,10 @@ struct sun_prop_s {
   DevBuf<unsigned char> sell_cb;
   DevBuf<double> sell_val;
   DevBuf<double> rec_part;   // partial sums of the recorded observable
+  // segmented sliced layout (adjoint reverse stages with dot products): the
+  // starts of up to kMaxRevSeg time-dependent segments per lane, 8 bits each
+  int sell_segs = 0;
+  DevBuf<int> sell_seg;
 };
 
 namespace sun {
@@ -64,6 +68,7 @@ void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double*
 // (+ dcoef[(krows[i] * ndyn + slot[j]) * ntheta + th] when slot[j] >= 0).  The
 // slot sums are to be reduced in a fixed order.
 constexpr int kMaxDotTerms = 8;
+constexpr int kMaxRevSeg = 3;
 constexpr int kDotStages = 4;
 constexpr int kDotStagesPerWave = 2;   // stages one wavefront takes (1, 2 or 4)
 // slots per launch: kDotStages / kDotStagesPerWave groups of ntheta * ld
@@ -71,5 +76,37 @@ int64_t prop_dot_slots(const sun_prop_s& p);
 void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, const int64_t* slot0, int n,
               const double* const* xs, const double* const* kbs, const int64_t* krows, const double* dstat,
               const double* dcoef, int ndyn, int ntheta, double* gpart, int64_t ld, hipStream_t s);
+
+// Reverse stage with the parameter dot products fused in.  The propagator
+// holds the transposed generator with every parameter-dependent term as its
+// own time-dependent segment (ndyn = nseg <= kMaxRevSeg, in the segmented
+// sliced layout of prop_build_segments).  Segment d has the coefficient
+// wseg[d] (+ coef[krow * ncoef + slot[d]] when slot[d] >= 0) at this stage's
+// time.  Besides the stage update of prop_stage (stages 4..8), every
+// wavefront adds, for th < ntheta,
+//   sum_d dc_d,th * (sum over its rows r of s_d[r] xdot[r] + xin[r] K_d[r])
+// to gpart[th * ld + w] (w = its slice, or nslices + its long row), where
+// s_d = T_dᵀ xin is the row's segment sum, K_d the term's free vector (or
+// NULL) and dc_d,th = dstat[term[d] * ntheta + th] (+ dcoef[(krow * ncoef +
+// slot[d]) * ntheta + th] when slot[d] >= 0): kb . (T_d x + K_d) of the
+// forward stage input x = xdot through kb . T_d x = (T_dᵀ kb) . x.
+struct RevDot {
+  int nseg = 0;
+  double wseg[kMaxRevSeg] = {};
+  int slot[kMaxRevSeg] = {-1, -1, -1};
+  int term[kMaxRevSeg] = {};
+  const double* K[kMaxRevSeg] = {};
+  const double* coef = nullptr;
+  int ncoef = 0;
+  const double* dstat = nullptr;
+  const double* dcoef = nullptr;
+  int ntheta = 0;
+  double* gpart = nullptr;
+  int64_t ld = 0;
+};
+void prop_build_segments(sun_prop_s& p, hipStream_t s);
+int64_t prop_rev_slots(const sun_prop_s& p);
+void prop_stage_dot(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
+                    const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s);
 
 }  // namespace sun

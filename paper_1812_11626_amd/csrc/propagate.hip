@@ -380,7 +380,7 @@ __global__ void k_sell_fill(int64_t nslices, int64_t nshort, const int* __restri
                             const double* __restrict__ val, const int* __restrict__ sell_row,
                             const int64_t* __restrict__ off64, const int64_t* __restrict__ width_x64,
                             int* __restrict__ sell_off, int* __restrict__ sell_len, int* __restrict__ scol,
-                            double* __restrict__ sval) {
+                            double* __restrict__ sval, int64_t M, int* __restrict__ sell_seg) {
   const int64_t total = nslices * kSlice;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t sl = i / kSlice;
@@ -396,6 +396,13 @@ __global__ void k_sell_fill(int64_t nslices, int64_t nshort, const int* __restri
       slen = ndyn ? seg[r] - a : len;
     }
     sell_len[i] = (len << 16) | slen;
+    if (sell_seg) {
+      // row-relative starts of the time-dependent segments, 8 bits each
+      // (rows on the sliced path have at most 255 entries here)
+      int packed = 0;
+      for (int d = 0; d < ndyn; ++d) packed |= (i < nshort ? seg[(int64_t)d * M + sell_row[i]] - a : 0) << (8 * d);
+      sell_seg[i] = packed;
+    }
     for (int k = 0; k < w; ++k) {
       const int64_t dst = base + (int64_t)k * kSlice;
       if (k < len) { scol[dst] = col[a + k]; sval[dst] = val[a + k]; }
@@ -745,6 +752,149 @@ __global__ __launch_bounds__(256) void k_dot_sell(DotViews dv, int64_t nwaves, D
   }
 }
 
+// Segmented row sums for the reverse stages with fused dot products: ND
+// time-dependent segments after the static one, their row-relative starts in
+// b[1..ND] (b[0] = 0, b[ND + 1] = len); every segment summed in row order.
+template <class T, int U, int ND>
+__device__ inline void slice_row_segs(const unsigned char* cb, const int* __restrict__ gbase,
+                                      const double* __restrict__ vp, int wd, int lane, const int* b,
+                                      const double* __restrict__ xin, double* a) {
+#pragma unroll
+  for (int q = 0; q <= ND; ++q) a[q] = 0.0;
+  int k = 0;
+  for (; k + U <= wd; k += U) {
+    int ci[U];
+    double cv[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ci[u] = gbase[k + u] + load_delta<T, false>(cb, (int64_t)(k + u) * kSlice + lane);
+      cv[u] = vp[(int64_t)(k + u) * kSlice];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = xin[ci[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double pr = cv[u] * xv[u];
+#pragma unroll
+      for (int q = 0; q <= ND; ++q) a[q] += (k + u >= b[q] && k + u < b[q + 1]) ? pr : 0.0;
+    }
+  }
+  for (; k < wd; ++k) {
+    const int c = gbase[k] + load_delta<T, false>(cb, (int64_t)k * kSlice + lane);
+    const double pr = vp[(int64_t)k * kSlice] * xin[c];
+#pragma unroll
+    for (int q = 0; q <= ND; ++q) a[q] += (k >= b[q] && k < b[q + 1]) ? pr : 0.0;
+  }
+}
+
+template <int STAGE, int ND>
+__global__ __launch_bounds__(256) void k_rev_dot(
+    const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
+    const unsigned char* __restrict__ cb_all, const int* __restrict__ sell_row, const int* __restrict__ sell_len,
+    const int* __restrict__ sell_seg, const double* __restrict__ sval, int64_t nslices, int64_t nshort,
+    const int* __restrict__ long_rows, int64_t nlong, const int* __restrict__ rowptr, const int* __restrict__ seg,
+    const int* __restrict__ col, const double* __restrict__ val, int64_t M, const double* __restrict__ xin,
+    const double* v, double* acc, double* xout, const double* __restrict__ xdot, RevDot rd, int64_t krow,
+    double dt, int xcd_remap) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (xcd_remap) {
+    const int64_t q = ((int64_t)gridDim.x + 7) >> 3;
+    blk = (blk & 7) * q + (blk >> 3);
+  }
+  const int64_t wid = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wid >= nslices + nlong) return;
+  double cseg[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+    cseg[d] = rd.wseg[d] + (rd.slot[d] >= 0 ? rd.coef[krow * rd.ncoef + rd.slot[d]] : 0.0);
+  double qd[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) qd[d] = 0.0;
+  if (wid < nslices) {
+    const int64_t i = wid * kSlice + lane;
+    const int off = __builtin_amdgcn_readfirstlane(sell_off[wid]);
+    const int wd = (__builtin_amdgcn_readfirstlane(sell_off[wid + 1]) - off) / kSlice;
+    const int coff = __builtin_amdgcn_readfirstlane(sell_coff[wid]);
+    const bool own = i < nshort;
+    const int r = own ? sell_row[i] : 0;
+    const int lens = sell_len[i];
+    const int packed = sell_seg[i];
+    int b[ND + 2];
+    b[0] = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) b[d + 1] = (packed >> (8 * d)) & 255;
+    b[ND + 1] = lens >> 16;
+    double vr = 0.0, ar = 0.0, xr = 0.0, kr = 0.0;
+    if (own) {
+      vr = v[r];
+      if (reads_acc<STAGE>()) ar = acc[r];
+      xr = xdot[r];
+      kr = xin[r];
+    }
+    const unsigned char* cb = cb_all + (coff & ~63);
+    const int* gbase = gbase_all + off / kSlice;
+    const double* vp = sval + off + lane;
+    double a[ND + 1];
+    switch (coff & 3) {
+      case 0: slice_row_segs<uint8_t, 8, ND>(cb, gbase, vp, wd, lane, b, xin, a); break;
+      case 1: slice_row_segs<uint16_t, 8, ND>(cb, gbase, vp, wd, lane, b, xin, a); break;
+      default: slice_row_segs<uint32_t, 8, ND>(cb, gbase, vp, wd, lane, b, xin, a); break;
+    }
+    if (own) {
+      double k = a[0];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) k += cseg[d] * a[d + 1];
+      stage_store<STAGE>(r, k, vr, ar, acc, xout, dt);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) qd[d] = a[d + 1] * xr + (rd.K[d] ? kr * rd.K[d][r] : 0.0);
+    }
+  } else {
+    const int r = long_rows[wid - nslices];
+    const int e0 = rowptr[r], e1 = rowptr[r + 1];
+    int b[ND + 2];
+    b[0] = e0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) b[d + 1] = seg[(int64_t)d * M + r];
+    b[ND + 1] = e1;
+    double a[ND + 1];
+#pragma unroll
+    for (int q = 0; q <= ND; ++q) a[q] = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const double pr = val[e] * xin[col[e]];
+#pragma unroll
+      for (int q = 0; q <= ND; ++q) a[q] += (e >= b[q] && e < b[q + 1]) ? pr : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q <= ND; ++q)
+      for (int o = 32; o > 0; o >>= 1) a[q] += __shfl_down(a[q], o, 64);
+    if (lane == 0) {
+      const double vr = v[r];
+      const double ar = reads_acc<STAGE>() ? acc[r] : 0.0;
+      double k = a[0];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) k += cseg[d] * a[d + 1];
+      stage_store<STAGE>(r, k, vr, ar, acc, xout, dt);
+      const double xr = xdot[r], kr = xin[r];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) qd[d] = a[d + 1] * xr + (rd.K[d] ? kr * rd.K[d][r] : 0.0);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+    for (int o = 32; o > 0; o >>= 1) qd[d] += __shfl_xor(qd[d], o, 64);
+  if (lane < rd.ntheta) {
+    double add = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      double dc = rd.dstat[rd.term[d] * rd.ntheta + lane];
+      if (rd.slot[d] >= 0 && rd.dcoef) dc += rd.dcoef[(krow * rd.ncoef + rd.slot[d]) * rd.ntheta + lane];
+      add += dc * qd[d];
+    }
+    rd.gpart[lane * rd.ld + wid] += add;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Resident path for small systems: one workgroup keeps v, two stage vectors
 // and the accumulator ((M+1) doubles each, entry M = 1) in LDS and runs every
@@ -839,6 +989,8 @@ void build_sell(sun_prop_s& p, hipStream_t s) {
   const int64_t padded_rows = p.nslices * kSlice;
   p.sell_row.alloc(padded_rows > 0 ? padded_rows : 1);
   p.sell_len.alloc(padded_rows > 0 ? padded_rows : 1);
+  if (p.sell_segs > 0) p.sell_seg.alloc(padded_rows > 0 ? padded_rows : 1);
+  else p.sell_seg.release();
   p.sell_off.alloc(p.nslices + 1);
   p.sell_coff.alloc(p.nslices + 1);
   p.sell_nnz = 0;
@@ -860,7 +1012,8 @@ void build_sell(sun_prop_s& p, hipStream_t s) {
     p.sell_val.alloc(p.sell_nnz);
     hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(padded_rows, 256)), dim3(256), 0, s, p.nslices, p.nshort,
                        p.rowptr.get(), p.seg.get(), p.ndyn, p.col.get(), p.val.get(), p.sell_row.get(),
-                       off64.get(), wx.get(), p.sell_off.get(), p.sell_len.get(), scol.get(), p.sell_val.get());
+                       off64.get(), wx.get(), p.sell_off.get(), p.sell_len.get(), scol.get(), p.sell_val.get(), M,
+                       p.sell_segs > 0 ? p.sell_seg.get() : nullptr);
     HIP_LAUNCH_OK();
     int tot = (int)p.sell_nnz;
     HIP_OK(hipMemcpyAsync(p.sell_off.get() + p.nslices, &tot, sizeof(int), hipMemcpyHostToDevice, s));
@@ -1031,6 +1184,47 @@ void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, con
   auto kern = ps[0]->sell_nt ? k_dot_sell<4, true, kDotStagesPerWave> : k_dot_sell<4, false, kDotStagesPerWave>;
   hipLaunchKernelGGL(kern, dim3(grid, kDotStages / kDotStagesPerWave), dim3(256), 0, s, dv, nw, st, dstat, dcoef, ndyn,
                      ntheta, gpart, ld, remap);
+  HIP_LAUNCH_OK();
+}
+
+void prop_build_segments(sun_prop_s& p, hipStream_t s) {
+  SUN_REQUIRE(p.ndyn >= 1 && p.ndyn <= kMaxRevSeg, SUN_ENOTSUP, "1 to 3 segments for the fused reverse stages");
+  p.long_len = std::min(p.long_len, 255);   // segment starts are stored in 8 bits
+  p.sell_segs = p.ndyn;
+  build_sell(p, s);
+}
+
+int64_t prop_rev_slots(const sun_prop_s& p) { return p.nslices + p.nlong; }
+
+template <int STAGE>
+void launch_rev_dot(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                    const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s) {
+  const int64_t waves = p.nslices + p.nlong;
+  if (waves == 0) return;
+  unsigned grid = (unsigned)((waves + 3) / 4);
+  if (p.sell_remap) grid = (grid + 7) / 8 * 8;
+  auto kern = k_rev_dot<STAGE, 1>;
+  if (rd.nseg == 2) kern = k_rev_dot<STAGE, 2>;
+  else if (rd.nseg == 3) kern = k_rev_dot<STAGE, 3>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(), p.sell_base.get(),
+                     p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_seg.get(), p.sell_val.get(),
+                     p.nslices, p.nshort, p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(),
+                     p.val.get(), p.M, xin, vin, acc, xout, xdot, rd, krow, dt, p.sell_remap);
+}
+
+void prop_stage_dot(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
+                    const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s) {
+  SUN_REQUIRE(p.sell_segs == rd.nseg && rd.nseg >= 1 && rd.nseg <= kMaxRevSeg && p.ndyn == rd.nseg, SUN_EINVAL,
+              "fused reverse stage needs the segmented sliced layout of its terms");
+  SUN_REQUIRE(rd.ntheta >= 0 && rd.ntheta <= 64, SUN_EINVAL, "at most 64 parameters per wavefront");
+  switch (stage) {
+    case 4: launch_rev_dot<4>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 5: launch_rev_dot<5>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 6: launch_rev_dot<6>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 7: launch_rev_dot<7>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 8: launch_rev_dot<8>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    default: SUN_THROW(SUN_EINVAL, "fused reverse stages are 4..8");
+  }
   HIP_LAUNCH_OK();
 }
 

@@ -129,3 +129,58 @@ def test_autograd_function(lib):
     J2, g = prob.value_and_grad(THETA)
     assert float(J.detach()) == J2
     np.testing.assert_array_equal(theta.grad.numpy(), 2.0 * g)
+
+
+def test_four_dependent_terms_against_dense_adjoint(lib):
+    """theta = (A, gamma, U, J): all four terms depend on a parameter, more
+    than the fused reverse stages take, so the per-term dot-product path
+    runs.  Against the oracle's dense adjoint at N = 6, and its (A, gamma, U)
+    components against the fused path of the three-parameter problem."""
+    import copy
+    flush("[adjoint] N=6 four parameter-dependent terms")
+    p = dimer.adjoint_config(6)
+    steps, S = 2 * p.steps_per_period, p.steps_per_period
+    prob3, lind, basis = dimer_adjoint_problem(lib, p, steps, S, ckpt_every=p.steps_per_period)
+
+    def pmap4(theta):
+        A, g, U, Jh = (float(x) for x in theta)
+        q = copy.copy(p)
+        q.A = A
+        coef = dimer.drive_table(q, steps=steps)[:, None]
+        dcoef = np.zeros((2 * steps + 1, 1, 4))
+        dcoef[:, 0, 0] = dimer.drive_table_dA(q, steps=steps)
+        static_w = [-Jh, U * p.U_scale, 0.0, g * p.gamma_scale]
+        dstatic = np.zeros((4, 4))
+        dstatic[0, 3] = -1.0
+        dstatic[1, 2] = p.U_scale
+        dstatic[3, 1] = p.gamma_scale
+        return dict(static_w=static_w, dyn=[2], coef=coef, dstatic=dstatic, dcoef=dcoef)
+
+    prob4 = lib.AdjointProblem(lind, pmap4, prob3.v0, prob3.cobs, p.dt, steps, S, p.steps_per_period)
+    theta4 = np.array([1.5, 0.1, 0.5, p.J])
+    J4, g4 = prob4.value_and_grad(theta4)
+    J3, g3 = prob3.value_and_grad(THETA)
+    # oracle: the dense adjoint with the J derivative added
+    ops = dimer.dimer_operators(p)
+    F = ob.generators(p.N)
+    Gs = [lb.q_hamiltonian(F, ops[k].to_dense()) for k in ("HJ", "HU", "H1")]
+    Gs.append(lb.q_dissipator(F, ops["L"].to_dense()))
+    Ks = [None, None, None, lb.k_dissipator(F, ops["L"].to_dense())]
+    coef = np.zeros((2 * steps + 1, 4))
+    coef[:, 0] = -p.J
+    coef[:, 1] = p.U_eff
+    coef[:, 2] = dimer.drive_table(p, steps=steps)
+    coef[:, 3] = p.gamma_eff
+    dcoef = np.zeros((2 * steps + 1, 4, 4))
+    dcoef[:, 2, 0] = dimer.drive_table_dA(p, steps=steps)
+    dcoef[:, 3, 1] = p.gamma_scale
+    dcoef[:, 1, 2] = p.U_scale
+    dcoef[:, 0, 3] = -1.0
+    rho0 = np.zeros((p.N, p.N), complex)
+    rho0[0, 0] = 1
+    J_o, g_o = oadj.adjoint_gradient(Gs, Ks, coef, dcoef, lb.bloch_vector(F, rho0),
+                                     lb.bloch_vector(F, ops["H1"].to_dense()), p.dt, steps, S)
+    assert abs(J4 - J_o) <= 1e-12 * abs(J_o)
+    np.testing.assert_allclose(g4, g_o, rtol=1e-7)
+    assert J4 == J3
+    np.testing.assert_allclose(g4[:3], g3, rtol=1e-11)
