@@ -346,8 +346,12 @@ int sun_adjoint_create(sun_lind l, const double* static_w, const int32_t* dyn, i
  * in the reverse sweep, except the last interval, which the forward sweep
  * keeps (memory: (steps/ckpt_every + ckpt_every + 10) vectors of M+1
  * doubles, plus 3*ckpt_every vectors of stage inputs when they fit in
- * 24 GiB).  J_out: host double; grad_out: host double[ntheta] (may be
- * NULL).  Synchronises. */
+ * 24 GiB).  When at most three terms depend on a parameter, the reverse
+ * stages form the parameter dot products in the same pass, on a transposed
+ * generator that keeps those terms as separate segments (built on the first
+ * call, kept with the object); with more, one extra launch per step forms
+ * them from per-term propagators.  J_out: host double; grad_out: host
+ * double[ntheta] (may be NULL).  Synchronises. */
 int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, const double* dstatic,
                     const double* dcoef, int32_t ntheta, const double* cobs, double dt,
                     int64_t steps, int64_t S_avg, int64_t ckpt_every, double* J_out,
