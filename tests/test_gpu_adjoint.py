@@ -184,3 +184,52 @@ def test_four_dependent_terms_against_dense_adjoint(lib):
     np.testing.assert_allclose(g4, g_o, rtol=1e-7)
     assert J4 == J3
     np.testing.assert_allclose(g4[:3], g3, rtol=1e-11)
+
+
+@pytest.mark.parametrize("params", ["gamma,U", "gamma"])
+def test_static_generator_adjoint_against_dense(lib, params):
+    """No time-dependent term (the drive frozen at eps = E + A, folded into a
+    static weight): theta = (gamma, U) or (gamma) alone, i.e. two or one
+    segments on the fused reverse stages, against the oracle's dense adjoint
+    at N = 5 over three checkpoint intervals."""
+    flush(f"[adjoint] N=5 static generator, theta = ({params})")
+    p = dimer.adjoint_config(5)
+    steps, S = 120, 40
+    ops = dimer.dimer_operators(p)
+    basis = lib.build_basis(p.N)
+    lind = lib.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
+    e0 = np.zeros(p.N)
+    e0[0] = 1.0
+    v0 = basis.expand(dimer.ZCSR.from_diagonals(p.N, {0: e0}))[0].real.contiguous()
+    cobs = basis.expand(ops["H1"])[0].real.contiguous()
+    eps0 = p.E + p.A
+    with_u = params == "gamma,U"
+    nth = 2 if with_u else 1
+
+    def pmap(theta):
+        g = float(theta[0])
+        U = float(theta[1]) if with_u else p.U
+        dstatic = np.zeros((4, nth))
+        dstatic[3, 0] = p.gamma_scale
+        if with_u:
+            dstatic[1, 1] = p.U_scale
+        return dict(static_w=[-p.J, U * p.U_scale, eps0, g * p.gamma_scale], dyn=[], coef=None,
+                    dstatic=dstatic, dcoef=None)
+
+    prob = lib.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S, 50)
+    J, g = prob.value_and_grad(np.array([p.gamma, p.U][:nth]))
+    F = ob.generators(p.N)
+    Gs = [lb.q_hamiltonian(F, ops[k].to_dense()) for k in ("HJ", "HU", "H1")]
+    Gs.append(lb.q_dissipator(F, ops["L"].to_dense()))
+    Ks = [None, None, None, lb.k_dissipator(F, ops["L"].to_dense())]
+    coef = np.tile(np.array([-p.J, p.U_eff, eps0, p.gamma_eff]), (2 * steps + 1, 1))
+    dcoef = np.zeros((2 * steps + 1, 4, nth))
+    dcoef[:, 3, 0] = p.gamma_scale
+    if with_u:
+        dcoef[:, 1, 1] = p.U_scale
+    rho0 = np.zeros((p.N, p.N), complex)
+    rho0[0, 0] = 1
+    J_o, g_o = oadj.adjoint_gradient(Gs, Ks, coef, dcoef, lb.bloch_vector(F, rho0),
+                                     lb.bloch_vector(F, ops["H1"].to_dense()), p.dt, steps, S)
+    assert abs(J - J_o) <= 1e-12 * abs(J_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-7)
