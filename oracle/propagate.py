@@ -39,23 +39,29 @@ def _coef_rows(coef: np.ndarray, n: int):
 
 
 def rk4_bloch(G0, Gs, K, v0, coef, dt: float, steps: int,
-              record_every: int = 0):
-    """Classical RK4 for dv/dt = (G0 + sum_a c_a(t) G_a) v + K.
+              record_every: int = 0, Ks=None):
+    """Classical RK4 for dv/dt = (G0 + sum_a c_a(t) G_a) v + K(t), with
+    K(t) = K + sum_a c_a(t) Ks[a].
 
     G0, Gs[a]: dense arrays or scipy sparse matrices (M, M); K (M,) or None;
-    coef: (2*steps+1, len(Gs)).  Returns v at the end, and if record_every > 0
-    also the list of states after every record_every steps.
+    coef: (2*steps+1, len(Gs)); Ks: None, or one free vector (M,) or None per
+    time-dependent term (a dissipation channel whose rate varies carries its
+    eq. 11 vector with its eq. 10 matrix).  Returns v at the end, and if
+    record_every > 0 also the list of states after every record_every steps.
     """
     coef = np.asarray(coef, dtype=np.float64).reshape(2 * steps + 1, -1) \
         if len(Gs) else np.zeros((2 * steps + 1, 0))
     v = np.array(v0, dtype=np.float64, copy=True)
     Kv = np.zeros_like(v) if K is None else np.asarray(K, dtype=np.float64)
+    Ka = [None] * len(Gs) if Ks is None else [None if k is None else np.asarray(k, dtype=np.float64) for k in Ks]
     rec = []
 
     def rhs(x, c):
         y = G0 @ x + Kv
         for a, Ga in enumerate(Gs):
             y = y + c[a] * (Ga @ x)
+            if Ka[a] is not None:
+                y = y + c[a] * Ka[a]
         return y
 
     for n in range(steps):
@@ -82,11 +88,13 @@ def _sp(op):
 
 
 def rk4_rho(H0, Hs, Ls, gammas, rho0, coef, dt: float, steps: int,
-            record_every: int = 0):
+            record_every: int = 0, rates=None):
     """Classical RK4 on drho/dt = -i[H(t), rho] + sum_p g_p D_p(rho) (eq. 1).
 
     H(t) = H0 + sum_a c_a(t) Hs[a].  Operators may be dense, scipy sparse or
-    workloads.ZCSR; rho is a dense complex N x N array.
+    workloads.ZCSR; rho is a dense complex N x N array.  rates: None (the
+    constant g_p = gammas[p]) or a (2*steps+1, P) table of g_p on the same
+    half-step grid as coef.
     """
     H0 = _sp(H0)
     Hs = [_sp(h) for h in Hs]
@@ -96,24 +104,27 @@ def rk4_rho(H0, Hs, Ls, gammas, rho0, coef, dt: float, steps: int,
     coef = np.asarray(coef, dtype=np.float64).reshape(2 * steps + 1, -1) \
         if len(Hs) else np.zeros((2 * steps + 1, 0))
     rho = np.array(rho0, dtype=np.complex128, copy=True)
+    rtab = np.tile(np.asarray(gammas, dtype=np.float64), (2 * steps + 1, 1)) if rates is None \
+        else np.asarray(rates, dtype=np.float64).reshape(2 * steps + 1, len(Ls))
     rec = []
 
-    def rhs(r, c):
+    def rhs(r, c, gs):
         H = H0
         for a, Ha in enumerate(Hs):
             H = H + c[a] * Ha
         out = -1j * (H @ r - (H.T @ r.T).T)          # r @ H
-        for g, L, Ld, LdL in zip(gammas, Ls, Lds, LdLs):
+        for g, L, Ld, LdL in zip(gs, Ls, Lds, LdLs):
             rLd = (Ld.T @ r.T).T                       # r @ Ld
             out = out + g * (L @ rLd - 0.5 * (LdL @ r + (LdL.T @ r.T).T))
         return out
 
     for n in range(steps):
         c0, ch, c1 = _coef_rows(coef, n)
-        k1 = rhs(rho, c0)
-        k2 = rhs(rho + 0.5 * dt * k1, ch)
-        k3 = rhs(rho + 0.5 * dt * k2, ch)
-        k4 = rhs(rho + dt * k3, c1)
+        g0, gh, g1 = _coef_rows(rtab, n)
+        k1 = rhs(rho, c0, g0)
+        k2 = rhs(rho + 0.5 * dt * k1, ch, gh)
+        k3 = rhs(rho + 0.5 * dt * k2, ch, gh)
+        k4 = rhs(rho + dt * k3, c1, g1)
         rho = rho + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
         if record_every and (n + 1) % record_every == 0:
             rec.append(rho.copy())

@@ -256,7 +256,8 @@ class Propagator:
     def layout(self):
         lay, stored, nlong, nb = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
         check(self._lib.sun_prop_layout(self.handle, C.byref(lay), C.byref(stored), C.byref(nlong), C.byref(nb)))
-        return {"layout": "sliced" if lay.value == 1 else "stream", "stored_entries": stored.value,
+        name = {0: "stream", 1: "sliced", 2: "sliced-segmented"}.get(lay.value, "stream")
+        return {"layout": name, "stored_entries": stored.value,
                 "long_rows": nlong.value, "matrix_bytes_per_launch": nb.value}
 
     def propagate(self, v: torch.Tensor, coef: torch.Tensor | None, dt: float, steps: int) -> torch.Tensor:

@@ -19,7 +19,7 @@ struct sun_prop_s {
   int xcd_remap = 1;
   DevBuf<double> vaug, xa, xb, acc;
   // sliced-ELL layout (used when ndyn <= 1)
-  int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows
+  int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows, 2 = segmented sliced ELL (2-3 dyn terms)
   int sigma = 4096;          // rows sorted by length inside windows of sigma rows
   int long_len = 64;         // rows longer than this use the wave-per-row path
   int min_col_bytes = 1;     // narrowest column-delta width allowed (1, 2 or 4)
@@ -108,5 +108,9 @@ void prop_build_segments(sun_prop_s& p, hipStream_t s);
 int64_t prop_rev_slots(const sun_prop_s& p);
 void prop_stage_dot(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
                     const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s);
+// Forward stage 0..3 on the segmented sliced layout (layout 2: 2-3
+// time-dependent terms, segment d with coefficient coef[row * ndyn + d]).
+void prop_seg_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
+                    const double* coef, int64_t row, double dt, hipStream_t s);
 
 }  // namespace sun

@@ -787,8 +787,13 @@ __device__ inline void slice_row_segs(const unsigned char* cb, const int* __rest
   }
 }
 
-template <int STAGE, int ND>
-__global__ __launch_bounds__(256) void k_rev_dot(
+// One RK4 stage (forward 0..3 or reverse 4..8) on the segmented sliced
+// layout: the static segment plus ND time-dependent segments per row, each
+// summed in row order, k = a_0 + sum_d c_d a_{d+1} with c_d from rd (the
+// forward layout 2 of 2-3 time-dependent terms).  With DOTS, the reverse
+// stages also form the parameter dot products described at RevDot.
+template <int STAGE, int ND, bool DOTS>
+__global__ __launch_bounds__(256) void k_sell_seg(
     const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
     const unsigned char* __restrict__ cb_all, const int* __restrict__ sell_row, const int* __restrict__ sell_len,
     const int* __restrict__ sell_seg, const double* __restrict__ sval, int64_t nslices, int64_t nshort,
@@ -829,8 +834,10 @@ __global__ __launch_bounds__(256) void k_rev_dot(
     if (own) {
       vr = v[r];
       if (reads_acc<STAGE>()) ar = acc[r];
-      xr = xdot[r];
-      kr = xin[r];
+      if (DOTS) {
+        xr = xdot[r];
+        kr = xin[r];
+      }
     }
     const unsigned char* cb = cb_all + (coff & ~63);
     const int* gbase = gbase_all + off / kSlice;
@@ -846,8 +853,10 @@ __global__ __launch_bounds__(256) void k_rev_dot(
 #pragma unroll
       for (int d = 0; d < ND; ++d) k += cseg[d] * a[d + 1];
       stage_store<STAGE>(r, k, vr, ar, acc, xout, dt);
+      if (DOTS) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d) qd[d] = a[d + 1] * xr + (rd.K[d] ? kr * rd.K[d][r] : 0.0);
+        for (int d = 0; d < ND; ++d) qd[d] = a[d + 1] * xr + (rd.K[d] ? kr * rd.K[d][r] : 0.0);
+      }
     }
   } else {
     const int r = long_rows[wid - nslices];
@@ -875,11 +884,14 @@ __global__ __launch_bounds__(256) void k_rev_dot(
 #pragma unroll
       for (int d = 0; d < ND; ++d) k += cseg[d] * a[d + 1];
       stage_store<STAGE>(r, k, vr, ar, acc, xout, dt);
-      const double xr = xdot[r], kr = xin[r];
+      if (DOTS) {
+        const double xr = xdot[r], kr = xin[r];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) qd[d] = a[d + 1] * xr + (rd.K[d] ? kr * rd.K[d][r] : 0.0);
+        for (int d = 0; d < ND; ++d) qd[d] = a[d + 1] * xr + (rd.K[d] ? kr * rd.K[d][r] : 0.0);
+      }
     }
   }
+  if (!DOTS) return;
 #pragma unroll
   for (int d = 0; d < ND; ++d)
     for (int o = 32; o > 0; o >>= 1) qd[d] += __shfl_xor(qd[d], o, 64);
@@ -1080,6 +1092,10 @@ void launch_stage_nt(const sun_prop_s& p, const double* xin, const double* vin, 
 template <int STAGE>
 void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
                     const double* coef, int64_t row, double dt, hipStream_t s) {
+  if (p.layout == 2) {
+    sun::prop_seg_stage(p, STAGE, xin, vin, acc, xout, coef, row, dt, s);
+    return;
+  }
   if (p.layout == 1) {
     const int64_t waves = p.nslices + p.nlong;
     unsigned grid = (unsigned)((waves + 3) / 4);
@@ -1196,16 +1212,16 @@ void prop_build_segments(sun_prop_s& p, hipStream_t s) {
 
 int64_t prop_rev_slots(const sun_prop_s& p) { return p.nslices + p.nlong; }
 
-template <int STAGE>
-void launch_rev_dot(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
-                    const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s) {
+template <int STAGE, bool DOTS>
+void launch_sell_seg(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                     const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s) {
   const int64_t waves = p.nslices + p.nlong;
   if (waves == 0) return;
   unsigned grid = (unsigned)((waves + 3) / 4);
   if (p.sell_remap) grid = (grid + 7) / 8 * 8;
-  auto kern = k_rev_dot<STAGE, 1>;
-  if (rd.nseg == 2) kern = k_rev_dot<STAGE, 2>;
-  else if (rd.nseg == 3) kern = k_rev_dot<STAGE, 3>;
+  auto kern = k_sell_seg<STAGE, 1, DOTS>;
+  if (rd.nseg == 2) kern = k_sell_seg<STAGE, 2, DOTS>;
+  else if (rd.nseg == 3) kern = k_sell_seg<STAGE, 3, DOTS>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(), p.sell_base.get(),
                      p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_seg.get(), p.sell_val.get(),
                      p.nslices, p.nshort, p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(), p.col.get(),
@@ -1218,14 +1234,32 @@ void prop_stage_dot(const sun_prop_s& p, int stage, const double* xin, const dou
               "fused reverse stage needs the segmented sliced layout of its terms");
   SUN_REQUIRE(rd.ntheta >= 0 && rd.ntheta <= 64, SUN_EINVAL, "at most 64 parameters per wavefront");
   switch (stage) {
-    case 4: launch_rev_dot<4>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
-    case 5: launch_rev_dot<5>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
-    case 6: launch_rev_dot<6>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
-    case 7: launch_rev_dot<7>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
-    case 8: launch_rev_dot<8>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 4: launch_sell_seg<4, true>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 5: launch_sell_seg<5, true>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 6: launch_sell_seg<6, true>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 7: launch_sell_seg<7, true>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
+    case 8: launch_sell_seg<8, true>(p, xin, vin, acc, xout, xdot, rd, krow, dt, s); break;
     default: SUN_THROW(SUN_EINVAL, "fused reverse stages are 4..8");
   }
   HIP_LAUNCH_OK();
+}
+
+void prop_seg_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
+                    const double* coef, int64_t row, double dt, hipStream_t s) {
+  RevDot rd;
+  rd.nseg = p.ndyn;
+  for (int d = 0; d < p.ndyn && d < kMaxRevSeg; ++d) rd.slot[d] = d;   // segment d: coefficient c_d(t)
+  rd.coef = coef;
+  rd.ncoef = p.ndyn;
+  SUN_REQUIRE(p.sell_segs == p.ndyn && p.ndyn >= 1 && p.ndyn <= kMaxRevSeg, SUN_EINVAL,
+              "segmented layout does not match the time-dependent terms");
+  switch (stage) {
+    case 0: launch_sell_seg<0, false>(p, xin, vin, acc, xout, nullptr, rd, row, dt, s); break;
+    case 1: launch_sell_seg<1, false>(p, xin, vin, acc, xout, nullptr, rd, row, dt, s); break;
+    case 2: launch_sell_seg<2, false>(p, xin, vin, acc, xout, nullptr, rd, row, dt, s); break;
+    case 3: launch_sell_seg<3, false>(p, xin, vin, acc, xout, nullptr, rd, row, dt, s); break;
+    default: SUN_THROW(SUN_ENOTSUP, "the segmented layout runs the forward stages 0..3");
+  }
 }
 
 }  // namespace sun
@@ -1301,8 +1335,14 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
       // chains (measured on the dimer: 5.3 against 7.4 us per stage at
       // 45,773 nonzeros, 6.0 against 6.6 at 93,000; from ~190,000 on the
       // sliced kernel is ahead)
-      p->layout = (ndyn <= 1 && p->nnz > kStreamMaxNnz) ? 1 : 0;
+      p->layout = p->nnz > kStreamMaxNnz ? (ndyn <= 1 ? 1 : (ndyn <= kMaxRevSeg ? 2 : 0)) : 0;
       if (p->layout == 1) build_sell(*p, s);
+      if (p->layout == 2) {
+        // 2-3 time-dependent terms: one segment each in the sliced layout
+        p->long_len = std::min(p->long_len, 255);
+        p->sell_segs = ndyn;
+        build_sell(*p, s);
+      }
       // one workgroup wins while the whole generator is small (measured on
       // the dimer: 2.9x faster at 140 nonzeros, 1.1x at 4,200, slower from
       // ~9,000 on, where four wide launches per step hide latency better)
@@ -1346,7 +1386,9 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
                                     int32_t flags, void* stream) {
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
-    SUN_REQUIRE(p->ndyn <= 1, SUN_ENOTSUP, "the sliced layout supports at most one time-dependent term");
+    SUN_REQUIRE(p->ndyn <= kMaxRevSeg, SUN_ENOTSUP, "the sliced layouts support at most three time-dependent terms");
+    SUN_REQUIRE(p->ndyn <= 1 || long_len <= 255, SUN_EINVAL,
+                "with 2-3 time-dependent terms long_len must be at most 255");
     SUN_REQUIRE(sigma >= 64 && sigma <= 4096 && (sigma & (sigma - 1)) == 0, SUN_EINVAL,
                 "sigma must be a power of two in [64, 4096]");
     SUN_REQUIRE(long_len >= 1 && long_len <= 4096, SUN_EINVAL, "long_len must be in [1, 4096]");
@@ -1363,7 +1405,8 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     p->sell_nt = (flags & 2) ? 1 : 0;
     p->sell_unroll = u ? u : 8;
     p->resident = 0;
-    p->layout = 1;
+    p->layout = p->ndyn <= 1 ? 1 : 2;
+    p->sell_segs = p->ndyn <= 1 ? 0 : p->ndyn;
     build_sell(*p, as_stream(stream));
   });
 }
@@ -1372,7 +1415,7 @@ extern "C" int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, i
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
     if (nnz_fused) *nnz_fused = p->nnz;
-    if (nblocks) *nblocks = p->layout == 1 ? p->nslices + p->nlong : p->nblocks;
+    if (nblocks) *nblocks = p->layout >= 1 ? p->nslices + p->nlong : p->nblocks;
     if (M) *M = p->M;
   });
 }
@@ -1393,12 +1436,12 @@ extern "C" int sun_prop_layout(sun_prop p, int32_t* layout, int64_t* stored_entr
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
     if (layout) *layout = p->layout;
-    if (stored_entries) *stored_entries = p->layout == 1 ? p->sell_nnz : p->nnz;
-    if (long_rows) *long_rows = p->layout == 1 ? p->nlong : 0;
+    if (stored_entries) *stored_entries = p->layout >= 1 ? p->sell_nnz : p->nnz;
+    if (long_rows) *long_rows = p->layout >= 1 ? p->nlong : 0;
     if (bytes_per_launch) {
       // matrix stream + per-row metadata, excluding the vectors
       int64_t b = 0;
-      if (p->layout == 1) {
+      if (p->layout >= 1) {
         int64_t long_nnz = 0;  // long rows stream their CSR entries
         b = p->sell_nnz * 8 + p->sell_col_bytes + (p->sell_nnz / kSlice) * 4 + p->nslices * kSlice * 8 +
             (p->nslices + 1) * 8;

@@ -129,3 +129,38 @@ def test_driven_dimer_periodic_steady_state():
     obs = np.array([x @ n12 for x in rec])
     assert np.max(np.abs(rec[-1] - vstar)) < 1e-12
     assert obs.max() - obs.min() > 1e-3
+
+
+def test_time_dependent_rates_rho_form_equals_bloch_form():
+    """Two dissipation channels, the second with a time-dependent rate, and a
+    square-wave drive: the density-matrix RK4 with a rate table and the
+    Bloch RK4 with the channel's eq. 10 matrix and eq. 11 vector as one
+    time-dependent term give the same trajectory (RK4 commutes with the
+    affine map rho <-> v), and both differ from the constant-rate run."""
+    N = 4
+    p = dimer.plain_config(N)
+    p.steps_per_period = 40
+    ops = dimer.dimer_operators(p)
+    L2 = random_ops.random_complex_csr(N, 0.5, seed=77)
+    F = basis.generators(N)
+    steps = 100
+    eps = dimer.drive_table_square(p, steps=steps)
+    assert eps[0] == p.E + p.A and eps[2 * p.steps_per_period - 1] == p.E - p.A
+    assert eps[p.steps_per_period] == p.E - p.A and eps[2 * p.steps_per_period] == p.E + p.A
+    t = np.arange(2 * steps + 1) * 0.5 * p.dt
+    g2 = 0.05 * (1.0 + 0.5 * np.sin(2.0 * t))
+    rho0 = np.zeros((N, N), complex)
+    rho0[1, 1] = 1.0
+    rates = np.stack([np.full_like(t, p.gamma_eff), g2], axis=1)
+    rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"], L2], [p.gamma_eff, 0.05], rho0, eps[:, None], p.dt, steps,
+                     rates=rates)
+    G0 = lb.q_hamiltonian(F, ops["H0"].to_dense()) + p.gamma_eff * lb.q_dissipator(F, ops["L"].to_dense())
+    K0 = p.gamma_eff * lb.k_dissipator(F, ops["L"].to_dense())
+    G1 = lb.q_hamiltonian(F, ops["H1"].to_dense())
+    R2 = lb.q_dissipator(F, L2.to_dense())
+    K2 = lb.k_dissipator(F, L2.to_dense())
+    v = pr.rk4_bloch(G0, [G1, R2], K0, lb.bloch_vector(F, rho0), np.stack([eps, g2], axis=1), p.dt, steps,
+                     Ks=[None, K2])
+    np.testing.assert_allclose(lb.bloch_vector(F, rho), v, atol=1e-13)
+    rho_c = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"], L2], [p.gamma_eff, 0.05], rho0, eps[:, None], p.dt, steps)
+    assert np.max(np.abs(rho_c - rho)) > 1e-4

@@ -189,6 +189,20 @@ def drive_table(p: DimerParams, steps: int | None = None, t0: float = 0.0,
     return p.E + p.A * np.cos(p.omega * t)
 
 
+def drive_table_square(p: DimerParams, steps: int | None = None) -> np.ndarray:
+    """eps = E + A theta(t) with the square wave theta = +1 on the first half
+    of every period and -1 on the second (paper Sec. III), on the half-step
+    grid t_k = k dt/2 of a run that starts at t = 0 with steps_per_period
+    steps per period.  The half is decided by the integer phase index
+    k mod (2 steps_per_period), so the jumps fall exactly on grid points
+    (t = T/2 takes -1, t = T takes +1)."""
+    steps = p.steps if steps is None else steps
+    k = np.arange(2 * steps + 1)
+    half = p.steps_per_period
+    theta = np.where((k % (2 * half)) < half, 1.0, -1.0)
+    return p.E + p.A * theta
+
+
 def drive_table_dA(p: DimerParams, steps: int | None = None, t0: float = 0.0,
                    dt: float | None = None) -> np.ndarray:
     """d eps / dA on the same half-step grid (= cos(omega t_k))."""
