@@ -165,6 +165,46 @@ def small_configs_report(sb, torch, steps=2000):
     return res
 
 
+def general_drive_report(sb, torch, steps=400):
+    """General time dependence at N = 1001: square-wave drive on H1 and a
+    second dissipation channel L2 = b1^+ b2 whose rate varies in time, i.e.
+    two time-dependent terms; the segmented sliced layout (default) against
+    the CSR stream layout, RK4 steps/s."""
+    from workloads import dimer
+    N = 1001
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    s2 = np.sqrt((np.arange(N - 1) + 1.0) * (N - 1.0 - np.arange(N - 1)))
+    L2 = dimer.ZCSR.from_diagonals(N, {-1: s2})
+    basis = sb.build_basis(N)
+    lind = sb.Lindbladian(basis, [ops["H0"], ops["H1"]], [ops["L"], L2])
+    prop = lind.propagator([1.0, 0.0, p.gamma_eff, 0.0], [1, 3])
+    t = np.arange(2 * (steps + 50) + 1) * 0.5 * p.dt
+    table = np.stack([dimer.drive_table_square(p, steps=steps + 50), 0.3 * p.gamma_eff * (1 + 0.5 * np.sin(2 * t))],
+                     axis=1)
+    coef = torch.as_tensor(table).cuda().contiguous()
+    res = {"workload": "dimer-plain-N1001, square-wave drive, second channel b1^+b2 with a time-dependent rate",
+           "nnz_fused": prop.info()["nnz_fused"]}
+    for name in ("sliced-segmented", "stream"):
+        if name == "stream":
+            prop.tune(1024, 256, True)
+        assert prop.layout()["layout"] == name
+        v = _fock_v0(sb, basis, N)
+        prop.propagate(v, coef, p.dt, 20)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        prop.propagate(v, coef[100:], p.dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[name] = {"steps_per_s": steps / (ms / 1e3), "stage_mean_us": 1e3 * ms / (4 * steps),
+                     "finite": bool(torch.isfinite(v).all())}
+        log(f"general drive N=1001 ({name}): {res[name]['steps_per_s']:.0f} steps/s")
+    return res
+
+
 def batched_report(sb, torch, steps=200):
     """Batched form: the 512-instance dimer workload (N in {51,...,301},
     A ~ U[0.5,3], gamma ~ logU[0.01,0.5]), one launch per RK4 stage for all
@@ -418,6 +458,7 @@ def main():
 
     # ---- batched and adjoint forms, reported against plain -----------------
     out["plain_other_configs"] = small_configs_report(sb, torch)
+    out["general_drive"] = general_drive_report(sb, torch)
     out["batched"] = None if args.no_batched else batched_report(sb, torch)
     out["adjoint"] = None if args.no_adjoint else adjoint_report(sb, torch)
 
