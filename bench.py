@@ -205,6 +205,47 @@ def general_drive_report(sb, torch, steps=400):
     return res
 
 
+def bifurcation_report(sb, torch, N=101, count=128):
+    """Stroboscopic population diagram: count values of U at N, ten drive
+    periods from |0, N-1><0, N-1| in one batched group over [H_J, H_U, H1, L]
+    (autotuned), then P(n1) = rho_ii at t = 10T for every U from the GPU
+    readout.  Reports instance-steps/s of the propagation and the wall time
+    of the whole diagram."""
+    from workloads import dimer
+    inst = dimer.bifurcation_instances(N, count=count)
+    p0 = inst[0]
+    ops = dimer.dimer_operators(p0)
+    basis = sb.build_basis(N)
+    lind = sb.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
+    w = np.array([[-q.J, q.U_eff, q.E, q.gamma_eff] for q in inst])
+    u = np.array([[0.0, 0.0, q.A, 0.0] for q in inst])
+    bp = sb.BatchedPropagator([dict(lind=lind, w=w, u=u, wave=dimer.drive_table_dA(p0, steps=p0.steps), dt=p0.dt,
+                                    steps=p0.steps)])
+    v0 = _fock_v0(sb, basis, N)
+    start = v0.unsqueeze(0).repeat(count, 1)
+    bp.set_state(0, start)
+    tuned = sb.autotune_batched(bp, probe_steps=4, log=log)
+    bp.set_state(0, start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bp.run(p0.steps)
+    V = bp.get_state(0)
+    P = torch.stack([basis.density(V[j].contiguous()).diagonal().real for j in range(count)])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    Pc = P.cpu().numpy()
+    mean_n1 = (Pc * np.arange(N)).sum(axis=1)
+    res = {"workload": f"dimer U scan N={N}, {count} values of U in [0.05, 2] (U_eff = U/(N-1)), "
+                       f"{p0.periods} periods x {p0.steps_per_period} steps",
+           "instance_steps_per_s": count * p0.steps / el, "diagram_wall_s": el,
+           "tile": tuned[0]["tile"], "rows_per_item": tuned[0]["rows_per_item"], "path": tuned[0]["path"],
+           "population_sum_max_dev": float(np.abs(Pc.sum(axis=1) - 1.0).max()),
+           "mean_n1_at_10T": {f"{q.U:.3f}": float(m) for q, m in list(zip(inst, mean_n1))[::16]}}
+    log(f"bifurcation N={N}: {count} U values x {p0.steps} steps in {el:.2f} s "
+        f"({res['instance_steps_per_s']:.0f} instance-steps/s)")
+    return res
+
+
 def batched_report(sb, torch, steps=200):
     """Batched form: the 512-instance dimer workload (N in {51,...,301},
     A ~ U[0.5,3], gamma ~ logU[0.01,0.5]), one launch per RK4 stage for all
@@ -460,6 +501,7 @@ def main():
     out["plain_other_configs"] = small_configs_report(sb, torch)
     out["general_drive"] = general_drive_report(sb, torch)
     out["batched"] = None if args.no_batched else batched_report(sb, torch)
+    out["bifurcation"] = None if args.no_batched else bifurcation_report(sb, torch)
     out["adjoint"] = None if args.no_adjoint else adjoint_report(sb, torch)
 
     if not args.no_cpu_baseline:

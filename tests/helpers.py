@@ -94,3 +94,20 @@ def dimer_adjoint_problem(sb, p, steps, S_avg, ckpt_every):
 
     prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S_avg, ckpt_every)
     return prob, lind, basis
+
+
+def bifurcation_batch(sb, instances):
+    """One batched group over the terms [H_J, H_U, H1, L] with per-instance
+    coefficients (-J, U_eff, E + A cos(omega t), gamma_eff): the U scan of
+    workloads.dimer.bifurcation_instances.  Returns (bp, lind, basis)."""
+    import numpy as np
+    from workloads import dimer
+    p0 = instances[0]
+    ops = dimer.dimer_operators(p0)
+    basis = sb.build_basis(p0.N)
+    lind = sb.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
+    w = np.array([[-q.J, q.U_eff, q.E, q.gamma_eff] for q in instances])
+    u = np.array([[0.0, 0.0, q.A, 0.0] for q in instances])
+    wave = dimer.drive_table_dA(p0, steps=p0.steps)
+    bp = sb.BatchedPropagator([dict(lind=lind, w=w, u=u, wave=wave, dt=p0.dt, steps=p0.steps)])
+    return bp, lind, basis

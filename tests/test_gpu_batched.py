@@ -147,3 +147,39 @@ def test_autotuner_picks_valid_tiling(lib, tmp_path, monkeypatch):
         assert chosen[g]["path"] in (0, 2, 3)
     again = lib.autotune_batched(bp)
     assert all(c["cached"] for c in again.values())
+
+
+def test_bifurcation_scan_against_plain_and_oracle(lib):
+    """The U scan behind the stroboscopic population diagram (16 values of
+    U at N = 51, ten drive periods, one batched group over [H_J, H_U, H1, L]
+    with per-instance U): sampled instances against plain propagation; the
+    populations P(n1) = rho_ii at t = 10T from the GPU readout sum to 1, are
+    >= 0, depend on U, and for one instance equal the oracle's density-matrix
+    RK4 populations."""
+    from helpers import bifurcation_batch
+    N = 51
+    flush(f"[batched] bifurcation scan N={N}")
+    inst = dimer.bifurcation_instances(N, count=16)
+    steps = inst[0].steps
+    bp, lind, basis = bifurcation_batch(lib, inst)
+    bp.set_state(0, torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(inst))))
+    bp.run(steps)
+    V = bp.get_state(0)
+    for j in (0, 7, 15):
+        q = inst[j]
+        prop = lind.propagator([-q.J, q.U_eff, 0.0, q.gamma_eff], [2])
+        v = torch.as_tensor(fock_bloch(N, 0)).cuda()
+        eps = torch.as_tensor(dimer.drive_table(q, steps=steps)).cuda().contiguous()
+        prop.propagate(v, eps, q.dt, steps)
+        assert rel_vec_err(V[j].cpu().numpy(), v.cpu().numpy()) <= TOL, j
+    P = [basis.density(V[j].contiguous()).diagonal().real.cpu().numpy() for j in range(len(inst))]
+    for x in P:
+        assert abs(x.sum() - 1.0) <= 1e-12 and x.min() >= -1e-10
+    assert np.max(np.abs(P[0] - P[-1])) > 1e-3
+    q = inst[7]
+    ops = dimer.dimer_operators(q)
+    rho0 = np.zeros((N, N), complex)
+    rho0[0, 0] = 1.0
+    rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [q.gamma_eff], rho0,
+                     dimer.drive_table(q, steps=steps)[:, None], q.dt, steps)
+    assert rel_vec_err(P[7], np.real(np.diag(rho))) <= TOL

@@ -277,6 +277,21 @@ def batched_instances(count: int = 512, seed: int = BATCH_SEED,
     return out
 
 
+def bifurcation_instances(N: int, count: int = 64, U_min: float = 0.05, U_max: float = 2.0,
+                          periods: int = 10) -> list:
+    """U scan for the stroboscopic population diagram (paper Sec. III, Fig. 2:
+    P(n bosons on site 1) at t = 10T against the interaction): count values
+    of U evenly spaced in [U_min, U_max], U_eff = U/(N-1), gamma_eff = 0.1/N,
+    A = 1.5, E = 1, J = 1, omega = 1, rho0 = |0, N-1><0, N-1|.  All share the
+    stable step count of the drive range E +- A."""
+    spp = stable_steps_per_period(N, 1.0 + 1.5)
+    out = []
+    for i, U in enumerate(np.linspace(U_min, U_max, count)):
+        out.append(DimerParams(N=N, U=float(U), U_scale=1.0 / (N - 1), gamma_scale=1.0 / N,
+                               steps_per_period=spp, periods=periods, label=f"bifurcation-{i}"))
+    return out
+
+
 def adjoint_config(N: int = 301) -> DimerParams:
     """Adjoint workload: N = 301, 100 periods, loss = <n1 - n2> averaged over
     the last period.  Small-N variants (N <= 6) use literal parameters."""
