@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--threads", type=int, default=256)
     ap.add_argument("--only", choices=("plain", "batched", "adjoint"), default=None,
                     help="run one leg only (for profiling); prints that leg's report")
+    ap.add_argument("--scan", action="store_true",
+                    help="assembly time and RK4 steps/s of the plain workload over a range of N (one JSON line)")
     ap.add_argument("--pmc-mode", action="store_true",
                     help="short run for rocprofv3 --pmc (stage kernel + calibration copy)")
     return ap.parse_args()
@@ -357,16 +359,17 @@ def adjoint_report(sb, torch, periods=2):
             "full_100_periods_estimated_gradient_s": t_grad * (100 / periods)}
 
 
-def pmc_mode(sb, torch, steps):
+def pmc_mode(sb, torch, steps, N=1001):
     """Short run for hardware-counter collection: the stage kernel on the
-    N = 1001 workload, then a plain 512 MiB device copy (known size) that
-    calibrates the byte counters."""
+    plain workload (N = 1001 unless --N says otherwise), then a plain 512 MiB
+    device copy (known size) that calibrates the byte counters."""
     from workloads import dimer
-    p = dimer.plain_config(1001)
+    p = dimer.plain_config(N)
+    p.steps_per_period = max(p.steps_per_period, dimer.stable_steps_per_period(N, p.E + p.A))
     ops = dimer.dimer_operators(p)
-    basis = sb.build_basis(1001)
+    basis = sb.build_basis(N)
     lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
-    v = _fock_v0(sb, basis, 1001)
+    v = _fock_v0(sb, basis, N)
     eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
     prop.propagate(v, eps, p.dt, steps)
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -376,6 +379,50 @@ def pmc_mode(sb, torch, steps):
     torch.cuda.synchronize()
     print(json.dumps({"pmc_mode": True, "steps": steps, "copy_bytes_read": a.numel() * 8,
                       "copy_bytes_written": b.numel() * 8, "layout": prop.layout()}), flush=True)
+
+
+def scan_report(sb, torch, Ns=(51, 101, 201, 301, 501, 701, 1001, 1501, 2001), steps=200):
+    """The plain dimer workload over a range of N (stable step counts from the
+    dimer estimate): assembly time, fused nonzeros, layout, RK4 steps/s and
+    the stage launch's algorithmic bandwidth, with the union nonzeros from
+    the closed form (37N^2 - 93N + 52)/2 (exact for N >= 11)."""
+    from workloads import dimer
+    rows = []
+    for N in Ns:
+        p = dimer.plain_config(N)
+        p.steps_per_period = dimer.stable_steps_per_period(N, p.E + p.A)
+        ops = dimer.dimer_operators(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        basis = sb.build_basis(N)
+        lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+        torch.cuda.synchronize()
+        t_asm = time.perf_counter() - t0
+        M = N * N - 1
+        v = _fock_v0(sb, basis, N)
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps + 40)).cuda().contiguous()
+        prop.propagate(v, eps, p.dt, 20)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        prop.propagate(v, eps[40:], p.dt, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        nnz_union = (37 * N * N - 93 * N + 52) // 2
+        b = 12 * nnz_union + 4 * (M + 1) + 20 * M
+        stage_us = 1e3 * ms / (4 * steps)
+        row = {"N": N, "M": M, "nnz_fused": prop.info()["nnz_fused"], "layout": prop.layout()["layout"],
+               "assembly_ms": 1e3 * t_asm, "steps_per_s": steps / (ms / 1e3), "stage_us": stage_us,
+               "algorithmic_bytes_per_launch": b, "achieved_GBs": b / stage_us / 1e3,
+               "frac_of_8TBs": b / stage_us / 1e3 / HBM_PEAK_GBS, "finite": bool(torch.isfinite(v).all())}
+        rows.append(row)
+        log(f"scan N={N}: assembly {row['assembly_ms']:.1f} ms, {row['steps_per_s']:.0f} steps/s, "
+            f"{row['achieved_GBs']:.0f} GB/s ({row['layout']})")
+        del lind, prop, basis, v, eps
+        torch.cuda.empty_cache()
+    return {"scan": rows}
 
 
 def main():
@@ -390,7 +437,10 @@ def main():
 
     sb.require_gpu()
     if args.pmc_mode:
-        pmc_mode(sb, torch, min(args.steps, 20))
+        pmc_mode(sb, torch, min(args.steps, 20), args.N)
+        return
+    if args.scan:
+        print(json.dumps(scan_report(sb, torch)), flush=True)
         return
     if args.only == "batched":
         print(json.dumps(batched_report(sb, torch)), flush=True)
