@@ -243,9 +243,10 @@ class Propagator:
                                       _stream()))
 
     def tune_sliced(self, sigma: int = 4096, long_len: int = 64, min_col_bytes: int = 1, xcd_remap: bool = True,
-                    nontemporal: bool = False, unroll: int = 8):
+                    nontemporal: bool = False, unroll: int = 8, pairs: bool = False):
         """Select the sliced-ELL layout with these knobs."""
-        flags = int(bool(xcd_remap)) | (int(bool(nontemporal)) << 1) | ((int(unroll) & 0xFF) << 16)
+        flags = int(bool(xcd_remap)) | (int(bool(nontemporal)) << 1) | (int(bool(pairs)) << 2) | \
+            ((int(unroll) & 0xFF) << 16)
         check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes), flags,
                                              _stream()))
 

@@ -25,6 +25,7 @@ struct sun_prop_s {
   int min_col_bytes = 1;     // narrowest column-delta width allowed (1, 2 or 4)
   int sell_remap = 1;        // XCD-contiguous slice ranges
   int sell_nt = 0;           // 1: non-temporal loads for the matrix stream
+  int sell_pairs = 0;        // 1: slices cut from the pair-interleaved row sequence
   int resident = 0;          // sun_propagate runs every step in one single-workgroup launch
   int sell_unroll = 8;       // entries per lane per load round (4, 6, 8, 12 or 16)
   int64_t nshort = 0, nlong = 0, nslices = 0, sell_nnz = 0, sell_col_bytes = 0;

@@ -310,21 +310,33 @@ __global__ __launch_bounds__(NT) void k_rk4_stage(
 // ---------------------------------------------------------------------------
 constexpr int kSlice = 64;
 
-__global__ void k_row_class(int64_t M, const int* __restrict__ rowptr, int long_len,
+// Row taken at position q of the sequence the slices are cut from: the
+// natural order (P = 0), or pairs interleaved (S_p at 2p, J_p at 2p+1, the
+// D rows after them): the diagonal part of the Hamiltonian couples S_p with
+// J_p, P rows apart in the natural order, so with interleaving the rows of a
+// contiguous range of slices gather from one range of the state vector
+// instead of two.
+__device__ inline int64_t seq_row(int64_t q, int64_t P) {
+  return q < 2 * P ? ((q & 1) ? P + (q >> 1) : (q >> 1)) : q;
+}
+
+__global__ void k_row_class(int64_t M, int64_t P, const int* __restrict__ rowptr, int long_len,
                             int64_t* __restrict__ is_short, int64_t* __restrict__ is_long) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < M; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = seq_row(q, P);
     const int len = rowptr[r + 1] - rowptr[r];
-    is_short[r] = len <= long_len;
-    is_long[r] = len > long_len;
+    is_short[q] = len <= long_len;
+    is_long[q] = len > long_len;
   }
 }
 
-__global__ void k_row_scatter(int64_t M, const int64_t* __restrict__ is_short, const int64_t* __restrict__ spos,
-                              const int64_t* __restrict__ lpos, int* __restrict__ short_rows,
-                              int* __restrict__ long_rows) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (int64_t)gridDim.x * blockDim.x) {
-    if (is_short[r]) short_rows[spos[r]] = (int)r;
-    else long_rows[lpos[r]] = (int)r;
+__global__ void k_row_scatter(int64_t M, int64_t P, const int64_t* __restrict__ is_short,
+                              const int64_t* __restrict__ spos, const int64_t* __restrict__ lpos,
+                              int* __restrict__ short_rows, int* __restrict__ long_rows) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < M; q += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)seq_row(q, P);
+    if (is_short[q]) short_rows[spos[q]] = r;
+    else long_rows[lpos[q]] = r;
   }
 }
 
@@ -987,14 +999,15 @@ void build_sell(sun_prop_s& p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old layout
   const int64_t M = p.M;
   DevBuf<int64_t> is_short(M), is_long(M), spos(M), lpos(M);
-  hipLaunchKernelGGL(k_row_class, dim3(grid_for(M, 256)), dim3(256), 0, s, M, p.rowptr.get(), p.long_len,
+  const int64_t P = p.sell_pairs ? p.lind->basis->P : 0;
+  hipLaunchKernelGGL(k_row_class, dim3(grid_for(M, 256)), dim3(256), 0, s, M, P, p.rowptr.get(), p.long_len,
                      is_short.get(), is_long.get());
   HIP_LAUNCH_OK();
   p.nshort = exclusive_scan_i64(is_short.get(), spos.get(), M, s);
   p.nlong = exclusive_scan_i64(is_long.get(), lpos.get(), M, s);
   DevBuf<int> short_rows(p.nshort > 0 ? p.nshort : 1);
   p.long_rows.alloc(p.nlong > 0 ? p.nlong : 1);
-  hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(M, 256)), dim3(256), 0, s, M, is_short.get(), spos.get(),
+  hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(M, 256)), dim3(256), 0, s, M, P, is_short.get(), spos.get(),
                      lpos.get(), short_rows.get(), p.long_rows.get());
   HIP_LAUNCH_OK();
   p.nslices = (p.nshort + kSlice - 1) / kSlice;
@@ -1400,8 +1413,9 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     const int u = (flags >> 16) & 0xFF;
     SUN_REQUIRE(u == 0 || u == 4 || u == 6 || u == 8 || u == 12 || u == 16, SUN_EINVAL,
                 "entries per load round (flags bits 16-23) must be 0, 4, 6, 8, 12 or 16");
-    SUN_REQUIRE((flags & ~0xFF0003) == 0, SUN_EINVAL, "unknown flag bits");
+    SUN_REQUIRE((flags & ~0xFF0007) == 0, SUN_EINVAL, "unknown flag bits");
     p->sell_remap = (flags & 1) ? 1 : 0;
+    p->sell_pairs = (flags & 4) ? 1 : 0;
     p->sell_nt = (flags & 2) ? 1 : 0;
     p->sell_unroll = u ? u : 8;
     p->resident = 0;
