@@ -213,9 +213,10 @@ def test_sliced_layout_matches_stream_layout(lib):
 
 
 def test_sliced_kernel_variants_are_bitwise_identical(lib):
-    """XCD remapping, load hints and entries per load round change only which
-    wavefront handles a slice and how its loads are issued, never the order
-    of a row's sum: results are bitwise equal."""
+    """XCD remapping, load hints, entries per load round and the row sequence
+    the slices are cut from change only which wavefront handles a row and how
+    its loads are issued, never the order of a row's sum: results are bitwise
+    equal."""
     N = 101
     flush(f"[propagate] sliced variants N={N}")
     p = dimer.plain_config(N)
@@ -228,7 +229,8 @@ def test_sliced_kernel_variants_are_bitwise_identical(lib):
     ref = v0.clone()
     prop.propagate(ref, eps, p.dt, steps)
     for kw in (dict(xcd_remap=False), dict(nontemporal=True), dict(unroll=4), dict(unroll=12),
-               dict(unroll=16, nontemporal=True), dict(unroll=4, xcd_remap=False)):
+               dict(unroll=16, nontemporal=True), dict(unroll=4, xcd_remap=False), dict(pairs=True),
+               dict(pairs=True, xcd_remap=False, unroll=6)):
         prop.tune_sliced(**kw)
         v = v0.clone()
         prop.propagate(v, eps, p.dt, steps)
