@@ -242,14 +242,15 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  * bounds that width from below (4 = uncompressed).  flags of
  * sun_prop_tune_sliced: bit 0 gives each XCD one contiguous range of slices
  * (so the state entries its rows gather stay in that XCD's L2); bit 1 reads
- * the matrix stream with non-temporal loads (by default ordinary loads, which
- * let the matrix stay in the memory-side cache between launches when it
- * fits); bit 2 cuts the slices from the pair-interleaved row sequence (S_p,
+ * the matrix stream with non-temporal loads (sun_prop_create chooses them
+ * when one launch streams more than 288 MiB of matrix data, too much for the
+ * memory-side cache to hold between launches, and ordinary loads, which let
+ * the matrix stay there, otherwise); bit 2 cuts the slices from the pair-interleaved row sequence (S_p,
  * J_p adjacent: one gathered range per slice range instead of two, but wider
  * column offsets; off by default); bits 16-23 the entries a lane loads per
  * round (0 = 8, or 4, 6, 12, 16).  Other bits must be 0 (else SUN_EINVAL).  Defaults: block_nnz 1024,
  * threads 256, xcd_remap 1; sigma 4096, long_len 64, min_col_bytes 1,
- * flags 1. */
+ * flags 1 (3 when the matrix stream exceeds 288 MiB per launch). */
 int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
                   void* stream);
 int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,

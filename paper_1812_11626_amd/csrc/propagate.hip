@@ -995,6 +995,20 @@ __global__ __launch_bounds__(kResidentThreads) void k_rk4_resident(const int* __
 
 size_t resident_lds_bytes(int64_t M) { return (size_t)(4 * (M + 1)) * sizeof(double); }
 
+// Matrix data and per-row metadata one launch of the sliced stage kernel
+// streams (long rows' CSR entries excluded).
+int64_t sell_matrix_bytes(const sun_prop_s& p) {
+  return p.sell_nnz * 8 + p.sell_col_bytes + (p.sell_nnz / kSlice) * 4 + p.nslices * kSlice * 8 +
+         (p.nslices + 1) * 8;
+}
+
+// Above this many matrix bytes per launch the stream cannot stay in the
+// 256 MB Infinity Cache between launches, and non-temporal loads (which keep
+// it from evicting the gathered state vector) are faster; below it ordinary
+// loads let it stay there (dimer: 62.0 against 65.9 us per stage at 265 MB,
+// 82.1 against 77.5 at 311 MB, 194 against 170 at 732 MB).
+constexpr int64_t kNontemporalMinBytes = 288ll << 20;
+
 void build_sell(sun_prop_s& p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old layout
   const int64_t M = p.M;
@@ -1349,7 +1363,10 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
       // 45,773 nonzeros, 6.0 against 6.6 at 93,000; from ~190,000 on the
       // sliced kernel is ahead)
       p->layout = p->nnz > kStreamMaxNnz ? (ndyn <= 1 ? 1 : (ndyn <= kMaxRevSeg ? 2 : 0)) : 0;
-      if (p->layout == 1) build_sell(*p, s);
+      if (p->layout == 1) {
+        build_sell(*p, s);
+        p->sell_nt = sell_matrix_bytes(*p) > kNontemporalMinBytes ? 1 : 0;
+      }
       if (p->layout == 2) {
         // 2-3 time-dependent terms: one segment each in the sliced layout
         p->long_len = std::min(p->long_len, 255);
@@ -1456,10 +1473,7 @@ extern "C" int sun_prop_layout(sun_prop p, int32_t* layout, int64_t* stored_entr
       // matrix stream + per-row metadata, excluding the vectors
       int64_t b = 0;
       if (p->layout >= 1) {
-        int64_t long_nnz = 0;  // long rows stream their CSR entries
-        b = p->sell_nnz * 8 + p->sell_col_bytes + (p->sell_nnz / kSlice) * 4 + p->nslices * kSlice * 8 +
-            (p->nslices + 1) * 8;
-        (void)long_nnz;
+        b = sell_matrix_bytes(*p);
       } else {
         b = p->nnz * 12 + (p->M + 1) * 4 + (int64_t)p->ndyn * p->M * 4;
       }
