@@ -11,14 +11,21 @@
 //     k_r = sum_static + sum_d c_d(t) sum_dyn_d,
 // reading every matrix byte once and no separate K vector.
 //
-// Kernel.  The rows are cut into blocks of about `block_nnz` nonzeros.  A
-// workgroup streams its block's values and column indices with unit stride
-// (every lane a different nonzero), multiplies by the gathered x, parks the
-// products in LDS, then one lane per row sums its row segments and applies
-// the RK4 stage update, so that the row-wise vectors (v, the accumulator,
-// the next stage input) are touched once per stage.  Workgroup ids are
-// remapped so that each of the 8 XCDs walks one contiguous range of rows,
-// keeping the x gathers of neighbouring rows in that XCD's L2.
+// Kernels, by layout of that matrix (chosen at creation, retunable):
+//  * sliced ELL (k_rk4_sell; large generators, at most one time-dependent
+//    term): rows packed 64 per slice, one lane per row, compressed column
+//    offsets, one wavefront per slice, each XCD on a contiguous slice range;
+//  * segmented sliced ELL (k_sell_seg; 2-3 time-dependent terms): the same
+//    with each time-dependent term as its own segment of the lane's row;
+//  * CSR stream (k_rk4_stage; small generators, or 4 terms): the rows cut
+//    into blocks of about `block_nnz` nonzeros; a workgroup streams its
+//    block's values and columns with unit stride, multiplies by the gathered
+//    x, parks the products in LDS, then one lane per row sums its segments;
+//  * resident (k_rk4_resident; tiny generators): one workgroup keeps the
+//    state in LDS and runs all steps of a call in one launch.
+// Every layout sums a row's segments in nonzero order and applies the RK4
+// stage update in the same pass, so the row-wise vectors (v, the
+// accumulator, the next stage input) are touched once per stage.
 //
 // Stage arithmetic (same order as the textbook formula):
 //   s=1: x2 = v + dt/2 k1,  acc = k1
