@@ -16,7 +16,10 @@
 //     grad   += sum_i sum_a dc_a/dtheta(t_i) kb_i . (T_a x_i + K_a)
 // where x_i are the forward stage inputs of step n.  The transposed
 // generator runs on the same fused stage kernels (a second propagator built
-// from the transposed terms, with the reverse-mode vector updates fused in).
+// from the transposed terms, with the reverse-mode vector updates fused in);
+// with at most three parameter-dependent terms those terms are separate
+// segments of its rows and each reverse stage also forms
+// kb_i . (T_a x_i + K_a) = (T_a^T kb_i) . x_i + kb_i . K_a in the same pass.
 // States are checkpointed every `ckpt_every` steps in the forward sweep; the
 // backward sweep recomputes one checkpoint interval at a time, except the
 // last, whose states and stage inputs the forward sweep leaves in place.

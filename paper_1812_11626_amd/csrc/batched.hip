@@ -22,12 +22,18 @@
 // the L2 holds them.  Each row keeps its entries in the grouped column
 // order, so the sums are formed exactly as in the plain propagator.  The state of a
 // group is row-major [M+1][ld] with the instance index fastest (ld = number
-// of instances rounded up to the tile width), and X[M][b] = 1.  A wavefront
-// is split into 64/T lane groups of T lanes; each lane group handles one row
-// and T consecutive instances, so every nonzero's gather reads T contiguous
-// doubles of one state row, and the matrix row is read once per tile of T
-// instances.  Work items (group, block of rows, tile of instances) are
-// walked by a grid-stride loop of a fixed-size grid.
+// of instances rounded up to 128), and X[M][b] = 1.
+//
+// Kernels.  A lane group of T lanes handles one row for a tile of T (one
+// instance per lane) or 2T (two per lane, 16-byte gathers) consecutive
+// instances, so every nonzero's gather reads contiguous doubles of one state
+// row and the matrix row is read once per tile.  k_batch_stage_lds (default)
+// takes one (instance tile, block of rows) item per workgroup with the
+// block's columns, values and row/segment pointers staged in LDS, items
+// numbered tile-major and each XCD taking one eighth of every group;
+// k_batch_stage_xlds also stages the block's distinct gathered state rows;
+// k_batch_stage (rows of more than 1024 entries) reads the matrix from
+// global memory, one wavefront per item.
 #include <algorithm>
 #include <vector>
 
