@@ -313,14 +313,17 @@ def batched_report(sb, torch, steps=200):
             "full_20_periods_estimated_s": total_20T / batched_rate}
 
 
-def adjoint_report(sb, torch, periods=2):
-    """Adjoint form at N = 301: d<n1-n2>_(last period)/d(A, gamma, U) by the
-    discrete adjoint; time of gradient / time of the forward objective."""
+def adjoint_report(sb, torch, periods=2, N=301, ckpt=None):
+    """Adjoint form at N (301: the adjoint workload; 1001: the plain one):
+    d<n1-n2>_(last period)/d(A, gamma, U) by the discrete adjoint, checkpoint
+    every `ckpt` steps (default: every period); time of gradient / time of
+    the forward objective."""
     import copy
     from workloads import dimer
-    p = dimer.adjoint_config(301)
+    p = dimer.adjoint_config(N) if N == 301 else dimer.plain_config(N)
     steps = periods * p.steps_per_period
     S = p.steps_per_period
+    ckpt = S if ckpt is None else ckpt
     ops = dimer.dimer_operators(p)
     basis = sb.build_basis(p.N)
     lind = sb.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
@@ -339,7 +342,7 @@ def adjoint_report(sb, torch, periods=2):
         return dict(static_w=[-p.J, U * p.U_scale, 0.0, g * p.gamma_scale], dyn=[2],
                     coef=dimer.drive_table(q, steps=steps)[:, None], dstatic=dstatic, dcoef=dcoef)
 
-    prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S, ckpt_every=S)
+    prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S, ckpt_every=ckpt)
     theta = np.array([p.A, p.gamma, p.U])
     adj, coef, dstatic, dcoef = prob._setup(theta)
     adj.objective(prob.v0, coef, prob.cobs, p.dt, 16, 8)       # warm
@@ -348,15 +351,16 @@ def adjoint_report(sb, torch, periods=2):
     J_f = adj.objective(prob.v0, coef, prob.cobs, p.dt, steps, S)
     t_fwd = time.perf_counter() - t0
     t0 = time.perf_counter()
-    J, g = adj.run(prob.v0, coef, dstatic, dcoef, prob.cobs, p.dt, steps, S, S)
+    J, g = adj.run(prob.v0, coef, dstatic, dcoef, prob.cobs, p.dt, steps, S, ckpt)
     t_grad = time.perf_counter() - t0
-    log(f"adjoint N=301: forward {t_fwd:.2f} s, gradient {t_grad:.2f} s, ratio {t_grad/t_fwd:.2f}")
-    return {"workload": f"dimer-adjoint-N301 ({periods} periods x {p.steps_per_period} steps, "
-                        f"loss = <n1-n2> averaged over the last period, theta = (A, gamma, U))",
+    log(f"adjoint N={N}: forward {t_fwd:.2f} s, gradient {t_grad:.2f} s, ratio {t_grad/t_fwd:.2f}")
+    return {"workload": f"dimer-adjoint-N{N} ({periods} periods x {p.steps_per_period} steps, checkpoint every "
+                        f"{ckpt} steps, loss = <n1-n2> averaged over the last period, theta = (A, gamma, U))",
             "steps": steps, "J": J, "J_forward_only": J_f, "grad": {"A": g[0], "gamma": g[1], "U": g[2]},
             "forward_s": t_fwd, "gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
             "forward_steps_per_s": steps / t_fwd,
-            "full_100_periods_estimated_gradient_s": t_grad * (100 / periods)}
+            "full_horizon_periods": p.periods,
+            "full_horizon_estimated_gradient_s": t_grad * (p.periods / periods)}
 
 
 def pmc_mode(sb, torch, steps, N=1001):
@@ -553,6 +557,7 @@ def main():
     out["batched"] = None if args.no_batched else batched_report(sb, torch)
     out["bifurcation"] = None if args.no_batched else bifurcation_report(sb, torch)
     out["adjoint"] = None if args.no_adjoint else adjoint_report(sb, torch)
+    out["adjoint_N1001"] = None if args.no_adjoint else adjoint_report(sb, torch, periods=1, N=1001, ckpt=2048)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -349,7 +349,7 @@ int sun_adjoint_create(sun_lind l, const double* static_w, const int32_t* dyn, i
  * in the reverse sweep, except the last interval, which the forward sweep
  * keeps (memory: (steps/ckpt_every + ckpt_every + 10) vectors of M+1
  * doubles, plus 3*ckpt_every vectors of stage inputs when they fit in
- * 24 GiB).  When at most three terms depend on a parameter, the reverse
+ * 64 GiB).  When at most three terms depend on a parameter, the reverse
  * stages form the parameter dot products in the same pass, on a transposed
  * generator that keeps those terms as separate segments (built on the first
  * call, kept with the object); with more, one extra launch per step forms

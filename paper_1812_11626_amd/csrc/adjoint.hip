@@ -291,7 +291,7 @@ namespace {
 
 // Stage inputs x2, x3, x4 of a whole checkpoint interval are kept when they
 // need at most this many bytes; otherwise they are recomputed per step.
-constexpr double kStageStoreBytes = 24.0 * (1ull << 30);
+constexpr double kStageStoreBytes = 64.0 * (1ull << 30);
 
 struct Work {
   DevBuf<double> ck;        // checkpoints [(nck) * (M+1)]
