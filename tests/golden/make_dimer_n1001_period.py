@@ -5,8 +5,8 @@ period of 16,384 RK4 steps, integrated by the oracle's density-matrix RK4
 form reaches the same state up to rounding).  Records <n1 - n2> every 1024
 steps and the Bloch vector v_j = Tr(F_j rho) at seeded sample indices.
 
-Calls only oracle/ and the workload input generators; takes about half an
-hour on one CPU core."""
+Calls only oracle/ and the workload input generators; takes about two hours
+on one CPU core."""
 
 import os
 import sys
@@ -25,12 +25,20 @@ NSAMPLE = 1500
 
 
 def sample_indices(N: int) -> np.ndarray:
-    """Seeded uniform sample over all M generators plus every other D_l."""
+    """Seeded uniform sample over all M generators, every other D_l, and the
+    S and J generators of near-diagonal pairs (k = j + 1 for every third j,
+    k = j + 2 for every third j), where the coherences are largest."""
     M = N * N - 1
     P = N * (N - 1) // 2
     rng = np.random.default_rng(1001)
     idx = rng.choice(M, size=NSAMPLE, replace=False)
-    return np.unique(np.concatenate([idx, np.arange(2 * P, M, 2)]))
+
+    def pair(j, k):   # grouped order: S_jk at p, J_jk at P + p
+        return j * (2 * N - j - 1) // 2 + (k - j - 1)
+
+    near = [pair(j, j + 1) for j in range(0, N - 1, 3)] + [pair(j, j + 2) for j in range(1, N - 2, 3)]
+    near = np.asarray(near)
+    return np.unique(np.concatenate([idx, np.arange(2 * P, M, 2), near, P + near]))
 
 
 def main():
