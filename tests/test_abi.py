@@ -4,6 +4,8 @@
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -59,3 +61,13 @@ def test_host_side_argument_checks():
     assert lib.sun_bloch_expect(None, None, 1, 0, None, None, None, None, None, None) == _lib.SUN_EINVAL
     n = ctypes.c_int64()
     assert lib.sun_lind_nnz(None, 0, 0, ctypes.byref(n)) == _lib.SUN_EINVAL
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
+def test_header_is_plain_c99(tmp_path):
+    """The boundary header compiles as strict C99 (no C++ or HIP types)."""
+    src = tmp_path / "use.c"
+    src.write_text('#include "sunbloch.h"\nint main(void) { return sun_last_error() == 0; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
