@@ -249,7 +249,7 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  * J_p adjacent: one gathered range per slice range instead of two, but wider
  * column offsets; off by default); bits 16-23 the entries a lane loads per
  * round (0 = 8, or 4, 6, 12, 16).  Other bits must be 0 (else SUN_EINVAL).  Defaults: block_nnz 1024,
- * threads 256, xcd_remap 1; sigma 4096, long_len 64, min_col_bytes 1,
+ * threads 256, xcd_remap 1; sigma 4096, long_len 32, min_col_bytes 1,
  * flags 1 (3 when the matrix stream exceeds 288 MiB per launch). */
 int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
                   void* stream);

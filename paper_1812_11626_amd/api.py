@@ -242,7 +242,7 @@ class Propagator:
         check(self._lib.sun_prop_tune(self.handle, int(block_nnz), int(threads), int(bool(xcd_remap)),
                                       _stream()))
 
-    def tune_sliced(self, sigma: int = 4096, long_len: int = 64, min_col_bytes: int = 1, xcd_remap: bool = True,
+    def tune_sliced(self, sigma: int = 4096, long_len: int = 32, min_col_bytes: int = 1, xcd_remap: bool = True,
                     nontemporal: bool = False, unroll: int = 8, pairs: bool = False):
         """Select the sliced-ELL layout with these knobs."""
         flags = int(bool(xcd_remap)) | (int(bool(nontemporal)) << 1) | (int(bool(pairs)) << 2) | \

@@ -457,7 +457,7 @@ extern "C" int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, 
           if (st != SUN_OK) SUN_THROW(st, std::string("term propagator: ") + sun_last_error());
           // the dot-product kernel reads the sliced layout (small terms start in the stream layout)
           if (q->layout != 1) {
-            st = sun_prop_tune_sliced(q, 4096, 64, 1, 1, stream);
+            st = sun_prop_tune_sliced(q, 4096, 32, 1, 1, stream);
             if (st != SUN_OK) {
               sun_prop_free(q);
               SUN_THROW(st, std::string("term propagator layout: ") + sun_last_error());

@@ -21,7 +21,7 @@ struct sun_prop_s {
   // sliced-ELL layout (used when ndyn <= 1)
   int layout = 1;            // 0 = CSR stream, 1 = sliced ELL + long rows, 2 = segmented sliced ELL (2-3 dyn terms)
   int sigma = 4096;          // rows sorted by length inside windows of sigma rows
-  int long_len = 64;         // rows longer than this use the wave-per-row path
+  int long_len = 32;         // rows longer than this use the wave-per-row path
   int min_col_bytes = 1;     // narrowest column-delta width allowed (1, 2 or 4)
   int sell_remap = 1;        // XCD-contiguous slice ranges
   int sell_nt = 0;           // 1: non-temporal loads for the matrix stream

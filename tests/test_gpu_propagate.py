@@ -368,7 +368,7 @@ def test_resident_path_matches_sliced_kernel(lib):
     a = v0.clone()
     prop.propagate(a, eps, p.dt, steps)              # one launch for all steps
     ra, _ = prop.record(v0.clone(), eps, p.dt, steps, 60)
-    prop.tune_sliced()                               # four launches per step
+    prop.tune_sliced(long_len=64)                    # four launches per step, every row on a lane
     b = v0.clone()
     prop.propagate(b, eps, p.dt, steps)
     rb, _ = prop.record(v0.clone(), eps, p.dt, steps, 60)
