@@ -28,9 +28,15 @@ S grid states of that period).  The derivative is that of this discrete J
                            along every step; an independent route to the
                            same numbers.
 * ``objective``         -- J alone (used for finite differences).
+* ``tangent_gradient_rho`` -- forward-mode sensitivities of classical RK4
+                           applied to the density matrix itself (eq. 1),
+                           J = mean of Re Tr(X rho_n); never touches the
+                           SU(N) basis, so it is a third, independent route,
+                           and cheap at large N for banded operators.
 
 Parity: pinned -- central finite differences of ``objective`` and agreement
-of the two routes (tests/test_oracle_adjoint.py).
+of the Bloch-form routes with each other and with the density-matrix route
+(tests/test_oracle_adjoint.py).
 """
 
 from __future__ import annotations
@@ -174,4 +180,92 @@ def tangent_gradient(Gs, Ks, coef, dcoef, v0, cvec, dt, steps, S):
         if n + 1 >= steps - S + 1:
             J += (cvec @ v) / S
             grad += (cvec @ W) / S
+    return J, grad
+
+
+def tangent_gradient_rho(terms, coef, dcoef, rho0, X, dt, steps, S):
+    """Return (J, dJ/dtheta) for RK4 on the density matrix (eq. 1).
+
+    terms: list of (kind, op) with kind 'H' (contributes c_a(t) (-i[H_a, rho]))
+    or 'L' (contributes c_a(t) D_{L_a}(rho), D_L(r) = L r L^+ - {L^+ L, r}/2);
+    op dense, scipy sparse or workloads.ZCSR.  coef (2*steps+1, nterms) and
+    dcoef (2*steps+1, nterms, ntheta) on the half-step grid, as for the Bloch
+    form.  J = (1/S) sum_{n=steps-S+1}^{steps} Re Tr(X rho_n).
+
+    The map rho -> rhs is linear in rho and in the coefficients, so the
+    sensitivity W = d rho/d theta obeys dW/dt = rhs(W, c) + sum_a dc_a/dtheta
+    term_a(rho), stepped with the same RK4 stages.  Since RK4 commutes with
+    the affine map rho <-> v (eq. 5) and Re Tr(X rho) = Tr(X)/N + c.v with
+    c_j = Tr(F_j X) for Hermitian X, this J (minus Tr(X)/N) and its gradient
+    equal the Bloch-form ones in exact arithmetic.
+    """
+    import scipy.sparse as _sp
+
+    def as_sp(op):
+        if _sp.issparse(op):
+            return op.tocsr().astype(np.complex128)
+        if hasattr(op, "indptr") and hasattr(op, "re"):
+            return _sp.csr_matrix((op.re + 1j * op.im, op.indices, op.indptr), shape=(op.n, op.n))
+        return _sp.csr_matrix(np.asarray(op, dtype=np.complex128))
+
+    ops = []
+    for kind, op in terms:
+        A = as_sp(op)
+        if kind == "H":
+            ops.append(("H", A, None, None))
+        elif kind == "L":
+            Ad = A.conj().T.tocsr()
+            ops.append(("L", A, Ad, (Ad @ A).tocsr()))
+        else:
+            raise ValueError(kind)
+    nt = len(ops)
+    ntheta = dcoef.shape[2]
+    Xd = as_sp(X)
+
+    def right(r, B):                       # r @ B with B sparse
+        return (B.T @ r.T).T
+
+    def term(a, r):
+        kind, A, Ad, AdA = ops[a]
+        if kind == "H":
+            return -1j * (A @ r - right(r, A))
+        return A @ right(r, Ad) - 0.5 * (AdA @ r + right(r, AdA))
+
+    def rhs(r, c):
+        out = np.zeros_like(r)
+        for a in range(nt):
+            if c[a] != 0.0:
+                out += c[a] * term(a, r)
+        return out
+
+    def stage(c, dc, x, Wx):
+        k = rhs(x, c)
+        dk = [rhs(Wx[th], c) for th in range(ntheta)]
+        for a in range(nt):
+            if np.any(dc[a] != 0.0):
+                t = term(a, x)
+                for th in range(ntheta):
+                    if dc[a, th] != 0.0:
+                        dk[th] = dk[th] + dc[a, th] * t
+        return k, dk
+
+    def obs(r):
+        return float(np.real((Xd.multiply(r.T)).sum()))     # Re Tr(X r)
+
+    rho = np.array(rho0, dtype=np.complex128, copy=True)
+    W = [np.zeros_like(rho) for _ in range(ntheta)]
+    J = 0.0
+    grad = np.zeros(ntheta)
+    for n in range(steps):
+        c0, ch, c1 = coef[2 * n], coef[2 * n + 1], coef[2 * n + 2]
+        d0, dh, d1 = dcoef[2 * n], dcoef[2 * n + 1], dcoef[2 * n + 2]
+        k1, W1 = stage(c0, d0, rho, W)
+        k2, W2 = stage(ch, dh, rho + 0.5 * dt * k1, [W[t] + 0.5 * dt * W1[t] for t in range(ntheta)])
+        k3, W3 = stage(ch, dh, rho + 0.5 * dt * k2, [W[t] + 0.5 * dt * W2[t] for t in range(ntheta)])
+        k4, W4 = stage(c1, d1, rho + dt * k3, [W[t] + dt * W3[t] for t in range(ntheta)])
+        rho = rho + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        W = [W[t] + (dt / 6.0) * (W1[t] + 2.0 * W2[t] + 2.0 * W3[t] + W4[t]) for t in range(ntheta)]
+        if n + 1 >= steps - S + 1:
+            J += obs(rho) / S
+            grad += np.array([obs(w) for w in W]) / S
     return J, grad

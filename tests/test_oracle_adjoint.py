@@ -79,3 +79,58 @@ def test_planted_sign_error_is_caught():
     _, g1 = adj.adjoint_gradient(bad, Ks, coef, dcoef, v0, c, p.dt, steps, S)
     _, g2 = adj.tangent_gradient(Gs, Ks, coef, dcoef, v0, c, p.dt, steps, S)
     assert not np.allclose(g1, g2, rtol=1e-6)
+
+
+def _rho_route(N, steps, S, A=1.5, gamma=0.1, U=0.5):
+    """The same problem for the density-matrix route: terms H_J, H_U, H1 and L
+    with their coefficient tables, rho0 = |0><0| and X = n1 - n2."""
+    p = dimer.adjoint_config(N)
+    p.A, p.gamma, p.U = A, gamma, U
+    ops = dimer.dimer_operators(p)
+    terms = [("H", ops["HJ"]), ("H", ops["HU"]), ("H", ops["H1"]), ("L", ops["L"])]
+    coef = np.zeros((2 * steps + 1, 4))
+    coef[:, 0] = -p.J
+    coef[:, 1] = p.U_eff
+    coef[:, 2] = dimer.drive_table(p, steps=steps)
+    coef[:, 3] = p.gamma_eff
+    dcoef = np.zeros((2 * steps + 1, 4, 3))
+    dcoef[:, 2, 0] = dimer.drive_table_dA(p, steps=steps)
+    dcoef[:, 3, 1] = p.gamma_scale
+    dcoef[:, 1, 2] = p.U_scale
+    rho0 = np.zeros((N, N), complex)
+    rho0[0, 0] = 1
+    X = np.diag(2.0 * np.arange(N) - (N - 1)).astype(complex)
+    return p, terms, coef, dcoef, rho0, X
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_density_matrix_tangent_equals_bloch_adjoint(N):
+    """The density-matrix route (eq. 1, no SU(N) basis) against the Bloch-form
+    discrete adjoint built from explicit traces: same J and gradient, since
+    RK4 commutes with the affine map of eq. 5 (X = n1 - n2 is traceless)."""
+    steps, S = 40, 10
+    p, Gs, Ks, coef, dcoef, v0, c = _terms(N, steps=steps)
+    J1, g1 = adj.adjoint_gradient(Gs, Ks, coef, dcoef, v0, c, p.dt, steps, S)
+    _, terms, coef2, dcoef2, rho0, X = _rho_route(N, steps, S)
+    J2, g2 = adj.tangent_gradient_rho(terms, coef2, dcoef2, rho0, X, p.dt, steps, S)
+    assert abs(J1 - J2) <= 1e-12 * abs(J1)
+    np.testing.assert_allclose(g2, g1, rtol=1e-10)
+
+
+def test_density_matrix_tangent_matches_central_differences():
+    """Central differences of the density-matrix objective itself (h = 1e-6)."""
+    N, steps, S = 4, 40, 10
+    h = 1e-6
+    base = dict(A=1.5, gamma=0.1, U=0.5)
+    p, terms, coef, dcoef, rho0, X = _rho_route(N, steps, S, **base)
+    _, g = adj.tangent_gradient_rho(terms, coef, dcoef, rho0, X, p.dt, steps, S)
+    zero = np.zeros((2 * steps + 1, 4, 3))
+    for i, name in enumerate(("A", "gamma", "U")):
+        vals = []
+        for sgn in (+1, -1):
+            kw = dict(base)
+            kw[name] += sgn * h
+            q, terms2, coef2, _, rho02, X2 = _rho_route(N, steps, S, **kw)
+            vals.append(adj.tangent_gradient_rho(terms2, coef2, zero, rho02, X2, q.dt, steps, S)[0])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * abs(g[i]) + 1e-12, (name, fd, g[i])
