@@ -50,7 +50,9 @@ enum {
   SUN_ENOMEM = -2,   /* device allocation failed */
   SUN_EDEVICE = -3,  /* a HIP runtime call failed */
   SUN_ENOTSUP = -4,  /* valid input outside what the library supports (limits stated per call) */
-  SUN_ERANGE = -5    /* caller buffer too small; the needed size is returned */
+  SUN_ERANGE = -5,   /* caller buffer too small; the needed size is returned */
+  SUN_EDIVERGED = -6,/* the propagated state (or a result computed from it) is not finite */
+  SUN_EUNSTABLE = -7 /* dt * |lambda|max beyond the RK4 stability bound set by sun_prop_guard_stability */
 };
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -184,9 +186,14 @@ int sun_prop_create(sun_lind l, const double* static_w, const int32_t* dyn,
                     int32_t ndyn, void* stream, sun_prop* out);
 /* Advance v (device double[M], in/out) by `steps` RK4 steps of size dt.
  * coef: device double[(2*steps+1) * ndyn]; row k holds c_d(t0 + k dt/2), so
- * the stages of step n read rows 2n, 2n+1, 2n+1, 2n+2.  Asynchronous on
- * `stream`.  Four kernel launches per step (one per stage), or one launch
- * for all steps on the resident path (see sun_prop_tune_resident). */
+ * the stages of step n read rows 2n, 2n+1, 2n+1, 2n+2.  Four kernel launches
+ * per step (one per stage), or one launch for all steps on the resident path
+ * (see sun_prop_tune_resident).  With the finite check on (the default) the
+ * call synchronises `stream` at the end and returns SUN_EDIVERGED for a
+ * non-finite state; with it off the call is asynchronous on `stream`.  With a
+ * stability guard set (sun_prop_guard_stability) a larger |dt| returns
+ * SUN_EUNSTABLE before any launch.  A propagator whose re-layout failed
+ * part-way returns SUN_EINVAL until a layout is selected again. */
 int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
                   int64_t steps, void* stream);
 /* Same as sun_propagate, recording along the way (Sec. IV step 3.2): after
@@ -201,6 +208,34 @@ int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
 int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt,
                          int64_t steps, int64_t every, double* states, int64_t ld,
                          const double* x, double x0, double* obs, void* stream);
+/* Stability guard (RK4 is stable only while every eigenvalue lambda of the
+ * generator's linear part has lambda*dt inside its stability region): the
+ * spectral radius is estimated by power iteration (as sun_prop_spectral_radius,
+ * `iters` applications) at every corner of the box [coef_lo, coef_hi] of the
+ * time-dependent coefficients (host double[ndyn] each; 2^ndyn estimates), and
+ * from then on sun_propagate, sun_propagate_record and
+ * sun_propagate_profile refuse, with SUN_EUNSTABLE and before any launch, a
+ * step with |dt| * rho_max > limit.  limit = 0 takes 2.6, just below 2.6156,
+ * the smallest radius of the boundary of RK4's stability region
+ * |1 + z + z^2/2 + z^3/6 + z^4/24| <= 1 in the closed left half-plane (on the
+ * imaginary axis it is 2 sqrt 2), so that any eigenvalue with Re <= 0 and
+ * |lambda| dt <= 2.6 is stable; limit < 0 turns the guard off (the default).
+ * The corners bound the spectral radius when it is convex in the
+ * coefficients, as it is for the driven dimer (|lambda|max ~ 2 sqrt(eps^2 +
+ * J^2)(N-1)); it is an estimate otherwise.  *rho_max (host, may be NULL)
+ * receives the largest estimate.  Synchronises `stream`. */
+int sun_prop_guard_stability(sun_prop p, const double* coef_lo, const double* coef_hi, int32_t iters,
+                             double limit, double* rho_max, void* stream);
+/* Finite check (on by default): at the end of every sun_propagate,
+ * sun_propagate_record and sun_propagate_profile call, one kernel
+ * checks the state for NaN and infinite entries, the call synchronises
+ * `stream`, and a non-finite state is returned as computed with status
+ * SUN_EDIVERGED.  A non-finite entry never becomes finite again under RK4
+ * (each step adds to the previous value), so the check at the end of a call
+ * catches divergence at any step of it; call per period to detect it per
+ * period.  on = 0 turns the check off, and with it the synchronisation: the
+ * calls are then asynchronous on `stream`. */
+int sun_prop_check_finite(sun_prop p, int32_t on);
 /* Spectral radius |lambda|max of the linear part of the generator, G with
  * the time-dependent coefficients frozen at coef (host double[ndyn]), by
  * power iteration: `iters` applications of G to a normalised pseudo-random
@@ -218,6 +253,13 @@ int sun_prop_spectral_radius(sun_prop p, const double* coef, int32_t iters, doub
 int sun_propagate_profile(sun_prop p, double* v, const double* coef, double dt,
                           int64_t steps, void* stream, double* stage_ms,
                           int64_t* launches);
+/* For tests of the error paths: site 1 makes the next layout build (by
+ * sun_prop_tune, sun_prop_tune_sliced or the adjoint's first run) fail with
+ * SUN_ENOMEM after it has rewritten part of the propagator, as a device
+ * allocation failure there would; site 0 clears a pending injection.  A
+ * propagator left incomplete that way refuses every launching call with
+ * SUN_EINVAL until a layout is selected again. */
+int sun_debug_inject_failure(int32_t site);
 /* Layout facts for measurement: nnz of the fused matrix (static + dynamic
  * segments + folded free vector), number of work units per stage launch
  * (row blocks, or slices + long rows), rows M. */
@@ -301,7 +343,8 @@ int sun_batch_get_state(sun_batch b, int32_t g, double* V, void* stream);
  * RK4 steps, never past its own step count.  Each step is four launches
  * (one per stage) that cover all active groups: work items (group, block of
  * rows, tile of instances) are spread over a fixed grid of wavefronts.
- * Synchronises at the end. */
+ * Synchronises at the end; a non-finite state of a group the call advanced
+ * returns SUN_EDIVERGED. */
 int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream);
 /* Per-group tiling.  tile = instances per lane group (8, 16, 32 or 64; a
  * lane group of `tile` lanes sums one row for `tile` instances; 128: 64
@@ -325,6 +368,16 @@ int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, 
 int sun_batch_info(sun_batch b, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,
                    int32_t* rows_per_item);
 void sun_batch_free(sun_batch b);
+/* The batched form in one call: sun_batch_create with these arguments,
+ * states loaded from V[g] (device double[B[g]][M_g], one Bloch vector per
+ * instance), every group advanced through all of its steps[g] steps with the
+ * default tiling, and the final states written back to V[g].  A non-finite
+ * final state returns SUN_EDIVERGED (the states are still written back).
+ * Synchronises `stream`. */
+int sun_propagate_batched(const sun_lind* lind, int32_t ngroups, const int32_t* B,
+                          const double* const* w, const double* const* u,
+                          const double* const* wave, const double* dt, const int64_t* steps,
+                          double* const* V, void* stream);
 
 /* ------------------------------------------------------------------------
  * Adjoint: gradient of a time-averaged observable through the RK4 map
@@ -359,6 +412,36 @@ int sun_adjoint_run(sun_adj a, const double* v0, const double* coef, const doubl
                     const double* dcoef, int32_t ntheta, const double* cobs, double dt,
                     int64_t steps, int64_t S_avg, int64_t ckpt_every, double* J_out,
                     double* grad_out, void* stream);
+/* Plan -> allocate -> execute form of sun_adjoint_run, for callers that own
+ * the device memory (a PyTorch tensor, say).  sun_adjoint_plan returns, for a
+ * run with these parameters (the set of parameter-dependent terms follows
+ * from dstatic and the time-dependent term), the workspace size that keeps
+ * the stage inputs of a checkpoint interval (*workspace_bytes; equal to the
+ * minimum when they would exceed 64 GiB) and the minimum, which recomputes
+ * them (*min_workspace_bytes, host, may be NULL).  It builds, on first use,
+ * the layouts the object keeps for those terms (the segmented transposed
+ * generator or the per-term propagators) and may synchronise `stream`.
+ * sun_adjoint_execute runs sun_adjoint_run's computation on the caller's
+ * workspace (device, 256-byte aligned, workspace_bytes long; smaller than the
+ * minimum: SUN_ERANGE, no work done) and allocates no device memory of its
+ * own for the run.  The workspace holds, laid out by the library: checkpoints
+ * every ckpt_every steps, the states of one interval, optionally its stage
+ * inputs, and the cotangent, stage and partial-sum vectors.  Its contents
+ * need no initialisation and are meaningless afterwards.  A non-finite J or
+ * gradient returns SUN_EDIVERGED (also from sun_adjoint_run). */
+int sun_adjoint_plan(sun_adj a, const double* dstatic, int32_t ntheta, int64_t steps, int64_t ckpt_every,
+                     void* stream, size_t* workspace_bytes, size_t* min_workspace_bytes);
+int sun_adjoint_execute(sun_adj a, const double* v0, const double* coef, const double* dstatic,
+                        const double* dcoef, int32_t ntheta, const double* cobs, double dt,
+                        int64_t steps, int64_t S_avg, int64_t ckpt_every, void* workspace,
+                        size_t workspace_bytes, double* J_out, double* grad_out, void* stream);
+/* New static weights (host double[nH+P]; dissipation rates >= 0) for the
+ * same terms and time-dependent term: rebuilds the forward propagator only.
+ * The transposed terms are kept, and so is the segmented transposed generator
+ * while the weights of the terms it merges (those that depend on no
+ * parameter) are unchanged.  For parameter scans and optimisation loops
+ * over one sun_adj.  Synchronises `stream`. */
+int sun_adjoint_set_weights(sun_adj a, const double* static_w, void* stream);
 /* The forward objective J alone (same definition), e.g. for finite differences. */
 int sun_adjoint_objective(sun_adj a, const double* v0, const double* coef, const double* cobs,
                           double dt, int64_t steps, int64_t S_avg, double* J_out, void* stream);

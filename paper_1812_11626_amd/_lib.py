@@ -14,11 +14,14 @@ SUN_ENOMEM = -2
 SUN_EDEVICE = -3
 SUN_ENOTSUP = -4
 SUN_ERANGE = -5
+SUN_EDIVERGED = -6
+SUN_EUNSTABLE = -7
 SUN_TERM_H = 0
 SUN_TERM_L = 1
 
 _STATUS_NAMES = {SUN_EINVAL: "SUN_EINVAL", SUN_ENOMEM: "SUN_ENOMEM", SUN_EDEVICE: "SUN_EDEVICE",
-                 SUN_ENOTSUP: "SUN_ENOTSUP", SUN_ERANGE: "SUN_ERANGE"}
+                 SUN_ENOTSUP: "SUN_ENOTSUP", SUN_ERANGE: "SUN_ERANGE", SUN_EDIVERGED: "SUN_EDIVERGED",
+                 SUN_EUNSTABLE: "SUN_EUNSTABLE"}
 
 
 class SunError(RuntimeError):
@@ -60,6 +63,9 @@ PROTOS = {
     "sun_propagate_record": (C.c_int, [vp, vp, vp, f64, i64, i64, vp, i64, vp, f64, vp, vp]),
     "sun_prop_info": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
     "sun_prop_spectral_radius": (C.c_int, [vp, P(f64), i32, P(f64), vp]),
+    "sun_prop_guard_stability": (C.c_int, [vp, P(f64), P(f64), i32, f64, P(f64), vp]),
+    "sun_prop_check_finite": (C.c_int, [vp, i32]),
+    "sun_debug_inject_failure": (C.c_int, [i32]),
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),
     "sun_prop_tune_resident": (C.c_int, [vp, i32]),
@@ -72,9 +78,14 @@ PROTOS = {
     "sun_batch_info": (C.c_int, [vp, i32, P(i64), P(i64), P(i32), P(i32)]),
     "sun_batch_tune": (C.c_int, [vp, i32, i32, i32, i32, vp]),
     "sun_batch_free": (None, [vp]),
+    "sun_propagate_batched": (C.c_int, [P(vp), i32, P(i32), P(vp), P(vp), P(vp), P(f64), P(i64), P(vp), vp]),
     "sun_adjoint_create": (C.c_int, [vp, P(f64), P(i32), i32, vp, P(vp)]),
     "sun_adjoint_run": (C.c_int, [vp, vp, vp, P(f64), vp, i32, vp, f64, i64, i64, i64, P(f64), P(f64), vp]),
     "sun_adjoint_objective": (C.c_int, [vp, vp, vp, vp, f64, i64, i64, P(f64), vp]),
+    "sun_adjoint_plan": (C.c_int, [vp, P(f64), i32, i64, i64, vp, P(C.c_size_t), P(C.c_size_t)]),
+    "sun_adjoint_execute": (C.c_int, [vp, vp, vp, P(f64), vp, i32, vp, f64, i64, i64, i64, vp, C.c_size_t, P(f64),
+                                      P(f64), vp]),
+    "sun_adjoint_set_weights": (C.c_int, [vp, P(f64), vp]),
     "sun_adjoint_free": (None, [vp]),
 }
 

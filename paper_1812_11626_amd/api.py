@@ -271,6 +271,26 @@ class Propagator:
         check(self._lib.sun_propagate(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), _stream()))
         return v
 
+    def guard_stability(self, coef_lo=(), coef_hi=(), iters: int = 200, limit: float = 0.0) -> float:
+        """Estimate |lambda|max at the corners of the coefficient box and
+        refuse later steps with |dt| |lambda|max > limit (0: 2.6, inside RK4's
+        stability region everywhere in the left half-plane; < 0: guard off).
+        Returns the estimate."""
+        lo, hi = list(coef_lo), list(coef_hi)
+        assert len(lo) == len(hi) == self.ndyn
+        blo = (C.c_double * max(1, len(lo)))(*[float(x) for x in lo])
+        bhi = (C.c_double * max(1, len(hi)))(*[float(x) for x in hi])
+        rho = C.c_double()
+        check(self._lib.sun_prop_guard_stability(self.handle, blo, bhi, int(iters), float(limit), C.byref(rho),
+                                                 _stream()))
+        self._guard = (lo, hi) if limit >= 0 else None
+        return rho.value
+
+    def check_finite(self, on: bool = True):
+        """Finite check of the state at the end of every propagation call
+        (on by default; SUN_EDIVERGED when it fails)."""
+        check(self._lib.sun_prop_check_finite(self.handle, int(bool(on))))
+
     def spectral_radius(self, coef=(), iters: int = 200) -> float:
         """|lambda|max of the generator's linear part with the time-dependent
         coefficients frozen at `coef` (power iteration on the GPU)."""
@@ -298,8 +318,9 @@ class Propagator:
             x, x0 = observable
             assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == self.M
             obs = torch.empty(nrec, dtype=torch.float64, device="cuda")
-        check(self._lib.sun_propagate_record(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), int(every),
-                                             _ptr(st), self.M, _ptr(x), float(x0), _ptr(obs), _stream()))
+        fn = self._lib.sun_propagate_record
+        check(fn(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), int(every), _ptr(st), self.M, _ptr(x),
+                 float(x0), _ptr(obs), _stream()))
         return st, obs
 
 
@@ -318,13 +339,25 @@ Propagator.profile = _profile
 
 
 def propagate(prop: Propagator, v0, eps, dt: float, steps: int) -> torch.Tensor:
-    """propagate(v0, eps(t), dt, steps): eps is a (2*steps+1,) table (numpy or
-    tensor) or a callable sampled on the half-step grid t = k dt/2."""
+    """propagate(v0, eps(t), dt, steps): eps is a (2*steps+1,) table (numpy)
+    or a callable sampled on the half-step grid t = k dt/2.  Sets the
+    propagator's stability guard over the table's range first (a step beyond
+    RK4's stability bound raises SUN_EUNSTABLE) and returns the new state (the
+    finite check raises SUN_EDIVERGED for a non-finite one)."""
     if callable(eps):
         t = np.arange(2 * steps + 1) * (0.5 * dt)
         eps = np.asarray([eps(x) for x in t], dtype=np.float64)
-    coef = torch.as_tensor(np.asarray(eps, dtype=np.float64).reshape(2 * steps + 1, -1)).cuda().contiguous() \
-        if prop.ndyn else None
+    table = np.asarray(eps, dtype=np.float64).reshape(2 * steps + 1, -1) if prop.ndyn else None
+    if table is not None and steps > 0:
+        # stability guard over the drive range of this table (estimated once
+        # per propagator and range; SUN_EUNSTABLE for a step that is too large)
+        lo, hi = list(np.nanmin(table, axis=0)), list(np.nanmax(table, axis=0))   # NaNs: the finite check
+        g = getattr(prop, "_guard", None)
+        if g is None or any(a < b for a, b in zip(lo, g[0])) or any(a > b for a, b in zip(hi, g[1])):
+            prop.guard_stability(lo, hi)
+    elif getattr(prop, "_guard", None) is None and steps > 0:
+        prop.guard_stability()
+    coef = torch.as_tensor(table).cuda().contiguous() if table is not None else None
     v = torch.as_tensor(np.asarray(v0, dtype=np.float64)).cuda().clone() if not torch.is_tensor(v0) \
         else v0.detach().to("cuda", torch.float64).clone()
     return prop.propagate(v, coef, dt, steps)
@@ -425,17 +458,36 @@ class Adjoint:
             self._lib.sun_adjoint_free(self.handle)
             self.handle = None
 
-    def run(self, v0, coef, dstatic, dcoef, cobs, dt, steps, S_avg, ckpt_every):
+    def set_weights(self, static_w):
+        """New static weights for the same terms (only the forward propagator is rebuilt)."""
+        w = (C.c_double * self.nt)(*[float(x) for x in static_w])
+        check(self._lib.sun_adjoint_set_weights(self.handle, w, _stream()))
+
+    def plan(self, dstatic, steps, ckpt_every):
+        """(workspace bytes that keep the stage inputs, minimum workspace bytes)."""
+        dstatic = np.ascontiguousarray(np.asarray(dstatic, dtype=np.float64).reshape(self.nt, -1))
+        full, low = C.c_size_t(), C.c_size_t()
+        check(self._lib.sun_adjoint_plan(self.handle, dstatic.ctypes.data_as(C.POINTER(C.c_double)),
+                                         dstatic.shape[1], int(steps), int(ckpt_every), _stream(), C.byref(full),
+                                         C.byref(low)))
+        return full.value, low.value
+
+    def run(self, v0, coef, dstatic, dcoef, cobs, dt, steps, S_avg, ckpt_every, workspace=None):
         """(J, dJ/dtheta).  dstatic: host (nt, ntheta); dcoef: device
-        (2*steps+1, ndyn, ntheta) tensor or None."""
+        (2*steps+1, ndyn, ntheta) tensor or None.  The workspace is a uint8
+        CUDA tensor from PyTorch's allocator (sized by ``plan`` when not
+        given), so the run's device memory is PyTorch's."""
         dstatic = np.ascontiguousarray(np.asarray(dstatic, dtype=np.float64).reshape(self.nt, -1))
         ntheta = dstatic.shape[1]
         ds = dstatic.ctypes.data_as(C.POINTER(C.c_double))
+        if workspace is None:
+            full, _ = self.plan(dstatic, steps, ckpt_every)
+            workspace = torch.empty(full, dtype=torch.uint8, device="cuda")
         J = C.c_double()
         g = (C.c_double * max(1, ntheta))()
-        check(self._lib.sun_adjoint_run(self.handle, _ptr(v0), _ptr(coef), ds, _ptr(dcoef), ntheta, _ptr(cobs),
-                                        float(dt), int(steps), int(S_avg), int(ckpt_every), C.byref(J), g,
-                                        _stream()))
+        check(self._lib.sun_adjoint_execute(self.handle, _ptr(v0), _ptr(coef), ds, _ptr(dcoef), ntheta, _ptr(cobs),
+                                            float(dt), int(steps), int(S_avg), int(ckpt_every), _ptr(workspace),
+                                            workspace.numel(), C.byref(J), g, _stream()))
         return J.value, np.array(g[:ntheta])
 
     def objective(self, v0, coef, cobs, dt, steps, S_avg):
@@ -464,11 +516,20 @@ class AdjointProblem:
         self.dt, self.steps, self.S_avg, self.ckpt_every = float(dt), int(steps), int(S_avg), int(ckpt_every)
 
     def _setup(self, theta):
+        """The Adjoint object (kept across calls: its transposed terms and
+        reverse layouts do not depend on theta; new static weights only
+        rebuild the forward propagator) and the tables for theta."""
         p = self.param_map(np.asarray(theta, dtype=np.float64))
-        adj = Adjoint(self.lind, p["static_w"], p["dyn"])
-        coef = torch.as_tensor(np.ascontiguousarray(p["coef"], dtype=np.float64)).cuda() if len(p["dyn"]) else None
+        dyn = list(p["dyn"])
+        adj = getattr(self, "_adj", None)
+        if adj is None or self._adj_dyn != dyn:
+            adj = Adjoint(self.lind, p["static_w"], dyn)
+            self._adj, self._adj_dyn = adj, dyn
+        else:
+            adj.set_weights(p["static_w"])
+        coef = torch.as_tensor(np.ascontiguousarray(p["coef"], dtype=np.float64)).cuda() if len(dyn) else None
         dcoef = torch.as_tensor(np.ascontiguousarray(p["dcoef"], dtype=np.float64)).cuda() \
-            if len(p["dyn"]) and p.get("dcoef") is not None else None
+            if len(dyn) and p.get("dcoef") is not None else None
         return adj, coef, p["dstatic"], dcoef
 
     def value_and_grad(self, theta):
@@ -486,9 +547,19 @@ class SunBlochLoss(torch.autograd.Function):
         J = SunBlochLoss.apply(theta, problem);  J.backward()
     """
 
+    @classmethod
+    def apply(cls, theta, problem):
+        # no gradient wanted (theta does not require it, or grad mode is off):
+        # the forward objective alone, 2-3x cheaper than the adjoint run
+        if not (torch.is_grad_enabled() and theta.requires_grad):
+            J = problem.value(theta.detach().cpu().numpy())
+            return torch.tensor(J, dtype=theta.dtype, device=theta.device)
+        return super().apply(theta, problem)
+
     @staticmethod
     def forward(ctx, theta, problem):
-        J, g = problem.value_and_grad(theta.detach().cpu().numpy())
+        th = theta.detach().cpu().numpy()
+        J, g = problem.value_and_grad(th)
         ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
         return torch.tensor(J, dtype=theta.dtype, device=theta.device)
 

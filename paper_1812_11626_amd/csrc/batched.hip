@@ -35,6 +35,7 @@
 // k_batch_stage (rows of more than 1024 entries) reads the matrix from
 // global memory, one wavefront per item.
 #include <algorithm>
+#include <memory>
 #include <vector>
 
 #include "internal.hpp"
@@ -1066,9 +1067,47 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     }
     HIP_LAUNCH_OK();
     for (int g = 0; g < bt->ngroups; ++g) bt->done[g] += todo[g];
+    // finite check of the states the call advanced (a non-finite entry stays
+    // non-finite under RK4, so the end of the call catches any step of it)
+    DevBuf<int> bad(1);
+    set_int(bad.get(), 0, s);
+    for (int g = 0; g < bt->ngroups; ++g)
+      if (todo[g] > 0) flag_nonfinite(bt->v[g].get(), (bt->M[g] + 1) * bt->ld[g], bad.get(), s);
+    int h = 0;
+    HIP_OK(hipMemcpyAsync(&h, bad.get(), sizeof(int), hipMemcpyDeviceToHost, s));
     // the step table and group order are freed on return
     HIP_OK(hipStreamSynchronize(s));
+    SUN_REQUIRE(h == 0, SUN_EDIVERGED, "a batched state is not finite after this call (NaN or Inf)");
   });
 }
 
 extern "C" void sun_batch_free(sun_batch bt) { delete bt; }
+
+extern "C" int sun_propagate_batched(const sun_lind* lind, int32_t ngroups, const int32_t* B, const double* const* w,
+                                     const double* const* u, const double* const* wave, const double* dt,
+                                     const int64_t* steps, double* const* V, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(V != nullptr, SUN_EINVAL, "V is NULL");
+    for (int g = 0; g < ngroups; ++g) SUN_REQUIRE(V[g] != nullptr, SUN_EINVAL, "V[g] is NULL");
+    sun_batch bt = nullptr;
+    int st = sun_batch_create(lind, ngroups, B, w, u, wave, dt, steps, stream, &bt);
+    if (st != SUN_OK) SUN_THROW(st, sun_last_error());
+    std::unique_ptr<sun_batch_s> hold(bt);
+    int64_t most = 0;
+    for (int g = 0; g < ngroups; ++g) {
+      st = sun_batch_set_state(bt, g, V[g], stream);
+      if (st != SUN_OK) SUN_THROW(st, sun_last_error());
+      most = std::max(most, steps[g]);
+    }
+    st = sun_batch_run(bt, most, -1, stream);
+    const int run_st = st;
+    const std::string run_msg = st != SUN_OK ? sun_last_error() : "";
+    if (st != SUN_OK && st != SUN_EDIVERGED) SUN_THROW(st, run_msg);
+    for (int g = 0; g < ngroups; ++g) {
+      st = sun_batch_get_state(bt, g, V[g], stream);
+      if (st != SUN_OK) SUN_THROW(st, sun_last_error());
+    }
+    HIP_OK(hipStreamSynchronize(as_stream(stream)));
+    if (run_st != SUN_OK) SUN_THROW(run_st, run_msg);
+  });
+}

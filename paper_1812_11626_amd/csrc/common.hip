@@ -101,6 +101,29 @@ __global__ __launch_bounds__(256) void k_max_partial(const double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// |x| <= DBL_MAX is false exactly for NaN and infinities; threads that find
+// one all store the same value.
+__global__ void k_flag_nonfinite(int64_t n, const double* __restrict__ x, int* __restrict__ bad) {
+  bool b = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b |= !(fabs(x[i]) <= 1.7976931348623157e308);
+  if (b) bad[0] = 1;
+}
+
+__global__ void k_set_int(int* __restrict__ a, int v) { a[0] = v; }
+
+void flag_nonfinite(const double* x, int64_t n, int* bad, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_flag_nonfinite, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, s, n, x,
+                     bad);
+  HIP_LAUNCH_OK();
+}
+
+void set_int(int* a, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, a, v);
+  HIP_LAUNCH_OK();
+}
+
 double device_max(const double* in, int64_t n, hipStream_t s) {
   if (n <= 0) return 0.0;
   const int nb = 512;

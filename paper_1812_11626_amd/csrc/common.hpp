@@ -137,6 +137,11 @@ int64_t device_max_i64(const int64_t* in, int64_t n, hipStream_t s);
 // Sum of an int64 array, result on host.
 int64_t device_sum_i64(const int64_t* in, int64_t n, hipStream_t s);
 
+// bad[0] = 1 if some x[i], i < n, is NaN or infinite (queued on s); and
+// a[0] = v (a one-thread kernel, used to reset such flags without memsets).
+void flag_nonfinite(const double* x, int64_t n, int* bad, hipStream_t s);
+void set_int(int* a, int v, hipStream_t s);
+
 // Per-workgroup LDS limit of the current device, in bytes.
 size_t lds_limit();
 

@@ -37,9 +37,23 @@ struct sun_prop_s {
   // starts of up to kMaxRevSeg time-dependent segments per lane, 8 bits each
   int sell_segs = 0;
   DevBuf<int> sell_seg;
+  // run-time checks
+  int usable = 1;            // 0 after a re-layout failed part-way: every launching call refuses
+  int check_finite = 1;      // finite check of the state at the end of each propagation call
+  DevBuf<int> bad;           // [1] set by the finite check, reset after it is read
+  double dt_max = 0.0;       // > 0: stability guard, larger dt is refused (SUN_EUNSTABLE)
+  double rho_guard = 0.0;    // |lambda|max estimate behind dt_max
 };
 
 namespace sun {
+
+// Refuse a propagator whose layout is not in a launchable state.
+void prop_require_usable(const sun_prop_s& p);
+// Queue the finite check of x[0..n) (sets p.bad[0]); read and reset it with
+// prop_finite_result, which synchronises the stream.  Both are no-ops when
+// the propagator's check is off.
+void prop_finite_check(const sun_prop_s& p, const double* x, int64_t n, hipStream_t s);
+bool prop_finite_result(const sun_prop_s& p, hipStream_t s);
 
 // Largest fused generator (stored nonzeros) that sun_prop_create puts in the
 // CSR stream layout rather than the sliced one.

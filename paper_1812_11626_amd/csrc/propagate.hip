@@ -34,6 +34,7 @@
 //   s=4: v  = v + dt/6 (acc + k4)
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 
 #include "internal.hpp"
 
@@ -1016,6 +1017,16 @@ int64_t sell_matrix_bytes(const sun_prop_s& p) {
 // 82.1 against 77.5 at 311 MB, 194 against 170 at 732 MB).
 constexpr int64_t kNontemporalMinBytes = 288ll << 20;
 
+// Failure injection for tests of the error paths (sun_debug_inject_failure):
+// when set, the next layout build throws after it has rewritten part of the
+// propagator, as a device allocation failure there would.
+std::atomic<int> g_inject_layout_failure{0};
+
+void maybe_inject_layout_failure() {
+  if (g_inject_layout_failure.exchange(0) != 0)
+    SUN_THROW(SUN_ENOMEM, "injected failure (sun_debug_inject_failure) in the middle of a layout build");
+}
+
 void build_sell(sun_prop_s& p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old layout
   const int64_t M = p.M;
@@ -1028,6 +1039,7 @@ void build_sell(sun_prop_s& p, hipStream_t s) {
   p.nlong = exclusive_scan_i64(is_long.get(), lpos.get(), M, s);
   DevBuf<int> short_rows(p.nshort > 0 ? p.nshort : 1);
   p.long_rows.alloc(p.nlong > 0 ? p.nlong : 1);
+  maybe_inject_layout_failure();
   hipLaunchKernelGGL(k_row_scatter, dim3(grid_for(M, 256)), dim3(256), 0, s, M, P, is_short.get(), spos.get(),
                      lpos.get(), short_rows.get(), p.long_rows.get());
   HIP_LAUNCH_OK();
@@ -1096,6 +1108,7 @@ void build_partition(sun_prop_s& p, hipStream_t s) {
   HIP_LAUNCH_OK();
   p.nblocks = exclusive_scan_i64(flag.get(), id.get(), M, s);
   p.blk_row.alloc(p.nblocks + 1);
+  maybe_inject_layout_failure();
   hipLaunchKernelGGL(k_block_rows, dim3(grid_for(M, 256)), dim3(256), 0, s, M, flag.get(), id.get(), p.nblocks,
                      p.blk_row.get());
   HIP_LAUNCH_OK();
@@ -1172,6 +1185,25 @@ void launch_stage(const sun_prop_s& p, const double* xin, double* xout, const do
 
 namespace sun {
 
+void prop_require_usable(const sun_prop_s& p) {
+  SUN_REQUIRE(p.usable, SUN_EINVAL,
+              "propagator layout is incomplete after a failed re-layout; select a layout again (sun_prop_tune*)");
+}
+
+void prop_finite_check(const sun_prop_s& p, const double* x, int64_t n, hipStream_t s) {
+  if (!p.check_finite || n <= 0) return;
+  flag_nonfinite(x, n, p.bad.get(), s);
+}
+
+bool prop_finite_result(const sun_prop_s& p, hipStream_t s) {
+  if (!p.check_finite) return true;
+  int h = 0;
+  HIP_OK(hipMemcpyAsync(&h, p.bad.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (h != 0) set_int(p.bad.get(), 0, s);
+  return h == 0;
+}
+
 void prop_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
                 const double* coef, int64_t row, double dt, hipStream_t s) {
   switch (stage) {
@@ -1239,9 +1271,11 @@ void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, con
 
 void prop_build_segments(sun_prop_s& p, hipStream_t s) {
   SUN_REQUIRE(p.ndyn >= 1 && p.ndyn <= kMaxRevSeg, SUN_ENOTSUP, "1 to 3 segments for the fused reverse stages");
+  p.usable = 0;
   p.long_len = std::min(p.long_len, 255);   // segment starts are stored in 8 bits
   p.sell_segs = p.ndyn;
   build_sell(p, s);
+  p.usable = 1;
 }
 
 int64_t prop_rev_slots(const sun_prop_s& p) { return p.nslices + p.nlong; }
@@ -1384,6 +1418,8 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
       // the dimer: 2.9x faster at 140 nonzeros, 1.1x at 4,200, slower from
       // ~9,000 on, where four wide launches per step hide latency better)
       p->resident = (ndyn <= 1 && p->nnz <= kResidentMaxNnz && resident_lds_bytes(M) <= lds_limit()) ? 1 : 0;
+      p->bad.alloc(1);
+      set_int(p->bad.get(), 0, s);
       p->vaug.alloc(M + 1);
       p->xa.alloc(M + 1);
       p->xb.alloc(M + 1);
@@ -1410,12 +1446,14 @@ extern "C" int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int
     SUN_REQUIRE(block_nnz >= 128 && block_nnz <= 8192 && (block_nnz & (block_nnz - 1)) == 0, SUN_EINVAL,
                 "block_nnz must be a power of two in [128, 8192]");
     SUN_REQUIRE(threads == 64 || threads == 128 || threads == 256, SUN_EINVAL, "threads must be 64, 128 or 256");
+    p->usable = 0;
     p->block_nnz = block_nnz;
     p->threads = threads;
     p->xcd_remap = xcd_remap ? 1 : 0;
     p->resident = 0;
     p->layout = 0;
     build_partition(*p, as_stream(stream));
+    p->usable = 1;
   });
 }
 
@@ -1442,10 +1480,12 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     p->sell_pairs = (flags & 4) ? 1 : 0;
     p->sell_nt = (flags & 2) ? 1 : 0;
     p->sell_unroll = u ? u : 8;
+    p->usable = 0;
     p->resident = 0;
     p->layout = p->ndyn <= 1 ? 1 : 2;
     p->sell_segs = p->ndyn <= 1 ? 0 : p->ndyn;
     build_sell(*p, as_stream(stream));
+    p->usable = 1;
   });
 }
 
@@ -1489,11 +1529,29 @@ extern "C" int sun_prop_layout(sun_prop p, int32_t* layout, int64_t* stored_entr
   });
 }
 
+namespace {
+
+void check_step_size(const sun_prop_s& p, double dt) {
+  if (p.dt_max > 0.0 && std::fabs(dt) > p.dt_max)
+    SUN_THROW(SUN_EUNSTABLE, "dt = " + std::to_string(dt) + " exceeds the stable step " + std::to_string(p.dt_max) +
+                                 " (|lambda|max ~ " + std::to_string(p.rho_guard) + ")");
+}
+
+void require_finite(const sun_prop_s& p, hipStream_t s, int64_t steps) {
+  if (!prop_finite_result(p, s))
+    SUN_THROW(SUN_EDIVERGED, "the state is not finite after " + std::to_string(steps) +
+                                 " RK4 steps (NaN or Inf in v; it is returned as computed)");
+}
+
+}  // namespace
+
 extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double dt, int64_t steps, void* stream) {
   return guarded([&] {
     SUN_REQUIRE(p != nullptr && v != nullptr, SUN_EINVAL, "NULL argument");
     SUN_REQUIRE(steps >= 0, SUN_EINVAL, "steps must be >= 0");
     SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    prop_require_usable(*p);
+    check_step_size(*p, dt);
     if (steps == 0) return;
     hipStream_t s = as_stream(stream);
     const int64_t M = p->M;
@@ -1502,6 +1560,8 @@ extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double d
                          p->rowptr.get(), p->col.get(), p->val.get(), p->seg.get(), p->ndyn, (int)M, coef, steps, dt,
                          v);
       HIP_LAUNCH_OK();
+      prop_finite_check(*p, v, M, s);
+      require_finite(*p, s, steps);
       return;
     }
     HIP_OK(hipMemcpyAsync(p->vaug.get(), v, M * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1515,62 +1575,91 @@ extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double d
       launch_stage<3>(*p, xa, va, coef, 2 * n + 2, dt, s);
     }
     HIP_LAUNCH_OK();
+    prop_finite_check(*p, va, M, s);
     HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    require_finite(*p, s, steps);
   });
 }
+
+namespace {
+
+// Body of sun_propagate_record: `part` holds the 2*nb partial sums of the
+// observable's dot products (nb = record_blocks(M)); it may be NULL when obs
+// is NULL.
+int record_blocks(int64_t M) { return (int)std::min<int64_t>(512, std::max<int64_t>(1, (M + 4095) / 4096)); }
+
+void propagate_record(sun_prop_s& P, double* v, const double* coef, double dt, int64_t steps, int64_t every,
+                      double* states, int64_t ld, const double* x, double x0, double* obs, double* part,
+                      hipStream_t s) {
+  sun_prop_s* p = &P;
+  const int64_t M = p->M;
+  const int nb = record_blocks(M);
+  HIP_OK(hipMemcpyAsync(p->vaug.get(), v, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double* va = p->vaug.get();
+  double* xa = p->xa.get();
+  double* xb = p->xb.get();
+  int64_t rec = 0;
+  if (p->resident) {
+    // one launch per recording interval (and one for the remaining steps)
+    for (int64_t n0 = 0; n0 < steps; n0 += every) {
+      const int64_t cnt = std::min<int64_t>(every, steps - n0);
+      const double* c = p->ndyn ? coef + 2 * n0 * p->ndyn : nullptr;
+      hipLaunchKernelGGL(k_rk4_resident, dim3(1), dim3(kResidentThreads), resident_lds_bytes(M), s,
+                         p->rowptr.get(), p->col.get(), p->val.get(), p->seg.get(), p->ndyn, (int)M, c, cnt, dt,
+                         va);
+      if (cnt == every) {
+        if (states)
+          HIP_OK(hipMemcpyAsync(states + rec * ld, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (obs) expect_launch(M, va, 1, M, x, nullptr, x0, 0.0, obs + rec, nullptr, part, nb, s);
+        ++rec;
+      }
+    }
+    HIP_LAUNCH_OK();
+    prop_finite_check(*p, va, M, s);
+    HIP_OK(hipMemcpyAsync(v, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    require_finite(*p, s, steps);
+    return;
+  }
+  for (int64_t n = 0; n < steps; ++n) {
+    launch_stage<0>(*p, va, xa, coef, 2 * n, dt, s);
+    launch_stage<1>(*p, xa, xb, coef, 2 * n + 1, dt, s);
+    launch_stage<2>(*p, xb, xa, coef, 2 * n + 1, dt, s);
+    launch_stage<3>(*p, xa, va, coef, 2 * n + 2, dt, s);
+    if ((n + 1) % every == 0) {
+      if (states)
+        HIP_OK(hipMemcpyAsync(states + rec * ld, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (obs) expect_launch(M, va, 1, M, x, nullptr, x0, 0.0, obs + rec, nullptr, part, nb, s);
+      ++rec;
+    }
+  }
+  HIP_LAUNCH_OK();
+  prop_finite_check(*p, va, M, s);
+  HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  require_finite(*p, s, steps);
+}
+
+void check_record_args(const sun_prop_s* p, const double* v, const double* coef, int64_t steps, int64_t every,
+                       const double* states, int64_t ld, const double* x, const double* obs) {
+  SUN_REQUIRE(p != nullptr && v != nullptr, SUN_EINVAL, "NULL argument");
+  SUN_REQUIRE(steps >= 0 && every >= 1, SUN_EINVAL, "steps must be >= 0 and every >= 1");
+  SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+  SUN_REQUIRE(states == nullptr || ld >= p->M, SUN_EINVAL, "ld must be >= M");
+  SUN_REQUIRE(obs == nullptr || x != nullptr, SUN_EINVAL, "obs needs x");
+  prop_require_usable(*p);
+}
+
+}  // namespace
 
 extern "C" int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt, int64_t steps,
                                     int64_t every, double* states, int64_t ld, const double* x, double x0,
                                     double* obs, void* stream) {
   return guarded([&] {
-    SUN_REQUIRE(p != nullptr && v != nullptr, SUN_EINVAL, "NULL argument");
-    SUN_REQUIRE(steps >= 0 && every >= 1, SUN_EINVAL, "steps must be >= 0 and every >= 1");
-    SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
-    SUN_REQUIRE(states == nullptr || ld >= p->M, SUN_EINVAL, "ld must be >= M");
-    SUN_REQUIRE(obs == nullptr || x != nullptr, SUN_EINVAL, "obs needs x");
+    check_record_args(p, v, coef, steps, every, states, ld, x, obs);
+    check_step_size(*p, dt);
     if (steps == 0) return;
-    hipStream_t s = as_stream(stream);
-    const int64_t M = p->M;
-    const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M + 4095) / 4096));
+    const int nb = record_blocks(p->M);
     if (obs && p->rec_part.n < (size_t)(2 * nb)) p->rec_part.alloc(2 * nb);
-    HIP_OK(hipMemcpyAsync(p->vaug.get(), v, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    double* va = p->vaug.get();
-    double* xa = p->xa.get();
-    double* xb = p->xb.get();
-    int64_t rec = 0;
-    if (p->resident) {
-      // one launch per recording interval (and one for the remaining steps)
-      for (int64_t n0 = 0; n0 < steps; n0 += every) {
-        const int64_t cnt = std::min<int64_t>(every, steps - n0);
-        const double* c = p->ndyn ? coef + 2 * n0 * p->ndyn : nullptr;
-        hipLaunchKernelGGL(k_rk4_resident, dim3(1), dim3(kResidentThreads), resident_lds_bytes(M), s,
-                           p->rowptr.get(), p->col.get(), p->val.get(), p->seg.get(), p->ndyn, (int)M, c, cnt, dt,
-                           va);
-        if (cnt == every) {
-          if (states)
-            HIP_OK(hipMemcpyAsync(states + rec * ld, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-          if (obs) expect_launch(M, va, 1, M, x, nullptr, x0, 0.0, obs + rec, nullptr, p->rec_part.get(), nb, s);
-          ++rec;
-        }
-      }
-      HIP_LAUNCH_OK();
-      HIP_OK(hipMemcpyAsync(v, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-      return;
-    }
-    for (int64_t n = 0; n < steps; ++n) {
-      launch_stage<0>(*p, va, xa, coef, 2 * n, dt, s);
-      launch_stage<1>(*p, xa, xb, coef, 2 * n + 1, dt, s);
-      launch_stage<2>(*p, xb, xa, coef, 2 * n + 1, dt, s);
-      launch_stage<3>(*p, xa, va, coef, 2 * n + 2, dt, s);
-      if ((n + 1) % every == 0) {
-        if (states)
-          HIP_OK(hipMemcpyAsync(states + rec * ld, va, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-        if (obs) expect_launch(M, va, 1, M, x, nullptr, x0, 0.0, obs + rec, nullptr, p->rec_part.get(), nb, s);
-        ++rec;
-      }
-    }
-    HIP_LAUNCH_OK();
-    HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    propagate_record(*p, v, coef, dt, steps, every, states, ld, x, x0, obs, p->rec_part.get(), as_stream(stream));
   });
 }
 
@@ -1597,43 +1686,105 @@ __global__ void k_spec_scale(int64_t M, const double* __restrict__ y, const doub
 
 }  // namespace
 
+namespace {
+
+// |lambda|max of the linear part of G at the frozen coefficients coef (host
+// double[ndyn]) by `iters` power-iteration steps (mean growth per application
+// over the second half).
+double spectral_radius(sun_prop_s& P, const double* coef, int iters, hipStream_t s) {
+  sun_prop_s* p = &P;
+  const int64_t M = p->M;
+  DevBuf<double> x(M + 1), y(M + 1), zero(M + 1), acc(M + 1), n2(iters), cdev(p->ndyn > 0 ? p->ndyn : 1);
+  const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M + 4095) / 4096));
+  DevBuf<double> part(2 * nb);
+  if (p->ndyn > 0) HIP_OK(hipMemcpyAsync(cdev.get(), coef, p->ndyn * sizeof(double), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M + 1, 0.0, zero.get());
+  hipLaunchKernelGGL(k_spec_init, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get());
+  HIP_LAUNCH_OK();
+  // start from the normalised pseudo-random vector
+  expect_launch(M, y.get(), 1, M, y.get(), nullptr, 0.0, 0.0, n2.get(), nullptr, part.get(), nb, s);
+  hipLaunchKernelGGL(k_spec_scale, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get(), n2.get(), x.get());
+  HIP_LAUNCH_OK();
+  for (int i = 0; i < iters; ++i) {
+    // stage 0 with a zero base vector and dt = 2: y = G x (x[M] = 0 leaves K out)
+    prop_stage(*p, 0, x.get(), zero.get(), acc.get(), y.get(), cdev.get(), 0, 2.0, s);
+    expect_launch(M, y.get(), 1, M, y.get(), nullptr, 0.0, 0.0, n2.get() + i, nullptr, part.get(), nb, s);
+    hipLaunchKernelGGL(k_spec_scale, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get(), n2.get() + i,
+                       x.get());
+    HIP_LAUNCH_OK();
+  }
+  std::vector<double> h(iters);
+  HIP_OK(hipMemcpyAsync(h.data(), n2.get(), iters * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  // mean log growth per application over the second half of the iterations
+  double acc_log = 0.0;
+  const int first = iters / 2;
+  for (int i = first; i < iters; ++i) {
+    SUN_REQUIRE(h[i] > 0.0 && std::isfinite(h[i]), SUN_ERANGE, "power iteration lost its vector (G x = 0 or overflow)");
+    acc_log += 0.5 * std::log(h[i]);
+  }
+  return std::exp(acc_log / (double)(iters - first));
+}
+
+// Smallest |z| on the boundary of classical RK4's stability region
+// |1 + z + z^2/2 + z^3/6 + z^4/24| <= 1 over the closed left half-plane:
+// 2.6156 (at arg z ~ 122.6 degrees; 2.785 on the negative real axis, 2.828 on
+// the imaginary axis).  Any eigenvalue with Re <= 0 and |lambda| dt below it
+// is inside the region.
+constexpr double kRk4SafeRadius = 2.6;
+
+}  // namespace
+
 extern "C" int sun_prop_spectral_radius(sun_prop p, const double* coef, int32_t iters, double* rho, void* stream) {
   return guarded([&] {
     SUN_REQUIRE(p != nullptr && rho != nullptr, SUN_EINVAL, "NULL argument");
     SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
     SUN_REQUIRE(iters >= 2 && iters <= 100000, SUN_EINVAL, "iters must be in [2, 100000]");
+    prop_require_usable(*p);
+    *rho = spectral_radius(*p, coef, iters, as_stream(stream));
+  });
+}
+
+extern "C" int sun_prop_guard_stability(sun_prop p, const double* coef_lo, const double* coef_hi, int32_t iters,
+                                        double limit, double* rho_max, void* stream) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
+    if (limit < 0.0) {   // guard off
+      p->dt_max = 0.0;
+      p->rho_guard = 0.0;
+      if (rho_max) *rho_max = 0.0;
+      return;
+    }
+    SUN_REQUIRE(p->ndyn == 0 || (coef_lo != nullptr && coef_hi != nullptr), SUN_EINVAL, "coefficient range is NULL");
+    SUN_REQUIRE(iters >= 2 && iters <= 100000, SUN_EINVAL, "iters must be in [2, 100000]");
+    prop_require_usable(*p);
+    const double lim = limit > 0.0 ? limit : kRk4SafeRadius;
     hipStream_t s = as_stream(stream);
-    const int64_t M = p->M;
-    DevBuf<double> x(M + 1), y(M + 1), zero(M + 1), acc(M + 1), n2(iters), cdev(p->ndyn > 0 ? p->ndyn : 1);
-    const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, (M + 4095) / 4096));
-    DevBuf<double> part(2 * nb);
-    if (p->ndyn > 0) HIP_OK(hipMemcpyAsync(cdev.get(), coef, p->ndyn * sizeof(double), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M + 1, 0.0, zero.get());
-    hipLaunchKernelGGL(k_spec_init, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get());
-    HIP_LAUNCH_OK();
-    // start from the normalised pseudo-random vector
-    expect_launch(M, y.get(), 1, M, y.get(), nullptr, 0.0, 0.0, n2.get(), nullptr, part.get(), nb, s);
-    hipLaunchKernelGGL(k_spec_scale, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get(), n2.get(), x.get());
-    HIP_LAUNCH_OK();
-    for (int i = 0; i < iters; ++i) {
-      // stage 0 with a zero base vector and dt = 2: y = G x (x[M] = 0 leaves K out)
-      prop_stage(*p, 0, x.get(), zero.get(), acc.get(), y.get(), cdev.get(), 0, 2.0, s);
-      expect_launch(M, y.get(), 1, M, y.get(), nullptr, 0.0, 0.0, n2.get() + i, nullptr, part.get(), nb, s);
-      hipLaunchKernelGGL(k_spec_scale, dim3(grid_for(M + 1, 256)), dim3(256), 0, s, M, y.get(), n2.get() + i,
-                         x.get());
-      HIP_LAUNCH_OK();
+    double worst = 0.0;
+    // every corner of the box [coef_lo, coef_hi] of the time-dependent coefficients
+    for (int corner = 0; corner < (1 << p->ndyn); ++corner) {
+      double c[kMaxDyn] = {};
+      for (int d = 0; d < p->ndyn; ++d) c[d] = (corner >> d & 1) ? coef_hi[d] : coef_lo[d];
+      worst = std::max(worst, spectral_radius(*p, c, iters, s));
     }
-    std::vector<double> h(iters);
-    HIP_OK(hipMemcpyAsync(h.data(), n2.get(), iters * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    // mean log growth per application over the second half of the iterations
-    double acc_log = 0.0;
-    const int first = iters / 2;
-    for (int i = first; i < iters; ++i) {
-      SUN_REQUIRE(h[i] > 0.0 && std::isfinite(h[i]), SUN_ERANGE, "power iteration lost its vector (G x = 0 or overflow)");
-      acc_log += 0.5 * std::log(h[i]);
-    }
-    *rho = std::exp(acc_log / (double)(iters - first));
+    SUN_REQUIRE(worst > 0.0 && std::isfinite(worst), SUN_ERANGE, "no finite spectral radius estimate");
+    p->rho_guard = worst;
+    p->dt_max = lim / worst;
+    if (rho_max) *rho_max = worst;
+  });
+}
+
+extern "C" int sun_debug_inject_failure(int32_t site) {
+  return guarded([&] {
+    SUN_REQUIRE(site == 0 || site == 1, SUN_EINVAL, "site must be 0 (clear) or 1 (the next layout build)");
+    g_inject_layout_failure.store(site);
+  });
+}
+
+extern "C" int sun_prop_check_finite(sun_prop p, int32_t on) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr, SUN_EINVAL, "prop is NULL");
+    p->check_finite = on ? 1 : 0;
   });
 }
 
@@ -1643,6 +1794,8 @@ extern "C" int sun_propagate_profile(sun_prop p, double* v, const double* coef, 
     SUN_REQUIRE(p != nullptr && v != nullptr && stage_ms != nullptr, SUN_EINVAL, "NULL argument");
     SUN_REQUIRE(steps >= 0, SUN_EINVAL, "steps must be >= 0");
     SUN_REQUIRE(p->ndyn == 0 || coef != nullptr, SUN_EINVAL, "coef is NULL");
+    prop_require_usable(*p);
+    check_step_size(*p, dt);
     hipStream_t s = as_stream(stream);
     const int64_t M = p->M;
     for (int i = 0; i < 4; ++i) stage_ms[i] = 0.0;
@@ -1675,8 +1828,10 @@ extern "C" int sun_propagate_profile(sun_prop p, double* v, const double* coef, 
       HIP_OK(hipEventRecord(e[7], s));
     }
     HIP_LAUNCH_OK();
+    prop_finite_check(*p, va, M, s);
     HIP_OK(hipMemcpyAsync(v, p->vaug.get(), M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
+    require_finite(*p, s, steps);
     for (int64_t n = 0; n < steps; ++n)
       for (int i = 0; i < 4; ++i) {
         float ms = 0.f;

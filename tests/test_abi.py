@@ -61,6 +61,28 @@ def test_host_side_argument_checks():
     assert lib.sun_bloch_expect(None, None, 1, 0, None, None, None, None, None, None) == _lib.SUN_EINVAL
     n = ctypes.c_int64()
     assert lib.sun_lind_nnz(None, 0, 0, ctypes.byref(n)) == _lib.SUN_EINVAL
+    assert lib.sun_prop_guard_stability(None, None, None, 100, 0.0, None, None) == _lib.SUN_EINVAL
+    assert lib.sun_prop_check_finite(None, 1) == _lib.SUN_EINVAL
+    assert lib.sun_debug_inject_failure(7) == _lib.SUN_EINVAL
+    assert lib.sun_debug_inject_failure(0) == _lib.SUN_OK
+    sz = ctypes.c_size_t()
+    assert lib.sun_adjoint_plan(None, None, 0, 10, 5, None, ctypes.byref(sz), None) == _lib.SUN_EINVAL
+    J = ctypes.c_double()
+    assert lib.sun_adjoint_execute(None, None, None, None, None, 0, None, 0.1, 10, 5, 5, None, 0, ctypes.byref(J),
+                                   None, None) == _lib.SUN_EINVAL
+    assert lib.sun_adjoint_set_weights(None, None, None) == _lib.SUN_EINVAL
+    assert lib.sun_propagate_batched(None, 1, None, None, None, None, None, None, None, None) == _lib.SUN_EINVAL
+
+
+def test_status_codes_match_header():
+    """The binding's status constants are the header's."""
+    from paper_1812_11626_amd import _lib
+    text = open(HEADER).read()
+    for name in ("SUN_EINVAL", "SUN_ENOMEM", "SUN_EDEVICE", "SUN_ENOTSUP", "SUN_ERANGE", "SUN_EDIVERGED",
+                 "SUN_EUNSTABLE"):
+        m = re.search(name + r"\s*=\s*(-?\d+)", text)
+        assert m is not None, name
+        assert int(m.group(1)) == getattr(_lib, name), name
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")

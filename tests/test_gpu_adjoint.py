@@ -3,10 +3,10 @@
 
 Checks: against the oracle's dense discrete adjoint at N = 6 (J to 1e-12,
 gradient to 1e-7 relative), against central finite differences (h = 1e-6)
-of the GPU objective at N = 6 and N = 51, at the benchmark's size N = 301
-(J against the oracle's sparse objective, the gradient against central
-differences), invariance under the checkpoint interval, and the
-torch.autograd.Function wrapper.
+of the GPU objective at N = 6 and N = 51, at the benchmark's sizes N = 301
+and N = 1001 against stored oracle values (J and the gradient, from the
+density-matrix tangent route), invariance under the checkpoint interval,
+and the torch.autograd.Function wrapper.
 """
 
 import numpy as np
@@ -14,7 +14,7 @@ import pytest
 import torch
 
 from helpers import dimer_adjoint_problem, flush
-from oracle import adjoint as oadj, basis as ob, lindblad as lb, propagate as opr
+from oracle import adjoint as oadj, basis as ob, lindblad as lb
 from workloads import dimer
 
 pytestmark = pytest.mark.gpu
@@ -74,30 +74,30 @@ def test_central_differences(lib, N):
         assert abs(fd - g[i]) <= 1e-7 * abs(g[i]) + 1e-11, (i, fd, g[i])
 
 
+def _golden(name):
+    """(N, steps, S, J, grad) stored by tests/golden/make_adjoint_goldens.py
+    (oracle density-matrix tangent route)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_goldens.txt")
+    for line in open(path):
+        f = line.split()
+        if f and f[0] == name:
+            return int(f[1]), int(f[2]), int(f[3]), float(f[4]), np.array([float(x) for x in f[5:8]])
+    raise KeyError(name)
+
+
 def test_N301_benchmark_configuration(lib):
     """N = 301 (M = 90,600) with a checkpoint every S steps as the benchmark
-    runs it, over 256 steps: J against the oracle (1e-12), dJ/d(A, gamma, U)
-    against central differences of the GPU objective (1e-7)."""
-    N = 301
+    runs it, over 256 steps: J (1e-12) and dJ/d(A, gamma, U) (1e-7) against
+    the stored oracle values (density-matrix tangent route, no SU(N) basis),
+    and the gradient against central differences of the GPU objective."""
+    N, steps, S, J_o, g_o = _golden("adjoint-N301")
     flush(f"[adjoint] N={N} benchmark configuration")
     p = dimer.adjoint_config(N)
-    steps, S = 256, 128
     prob, _, _ = dimer_adjoint_problem(lib, p, steps, S, ckpt_every=S)
     J, g = prob.value_and_grad(THETA.copy())
-    # oracle: RK4 on the density matrix itself (eq. 1; the same trajectory as
-    # RK4 on eq. 9 in exact arithmetic), J = mean of Tr(rho_n (n1 - n2)) over
-    # the last S grid states (n1 - n2 is traceless)
-    ops = dimer.dimer_operators(p)
-    eps = dimer.drive_table(p, steps=steps)[:, None]
-    rho0 = np.zeros((N, N), complex)
-    rho0[0, 0] = 1
-    rho = opr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho0, eps[: 2 * (steps - S) + 1],
-                      p.dt, steps - S)
-    _, rec = opr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho, eps[2 * (steps - S):], p.dt, S,
-                         record_every=1)
-    n12 = np.real(ops["H1"].to_dense().diagonal())
-    J_o = float(np.mean([np.real(np.diagonal(r)) @ n12 for r in rec]))
     assert abs(J - J_o) <= 1e-12 * abs(J_o), (J, J_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-7)
     h = 1e-6
     for i in range(3):
         tp, tm = THETA.copy(), THETA.copy()
@@ -105,6 +105,21 @@ def test_N301_benchmark_configuration(lib):
         tm[i] -= h
         fd = (prob.value(tp) - prob.value(tm)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-7 * abs(g[i]) + 1e-11, (i, fd, g[i])
+
+
+def test_N1001_plain_workload_gradient(lib):
+    """The plain N = 1001 workload (M = 1,002,000) on the adjoint path the
+    benchmark times there (fused reverse stages, several checkpoint intervals
+    recomputed, stage inputs kept): from the Fock state, J over the last half
+    of the stored run, four checkpoint intervals; J (1e-12) and the gradient
+    (1e-7) against the stored oracle values."""
+    N, steps, S, J_o, g_o = _golden("plain-N1001")
+    flush(f"[adjoint] N={N} plain workload, {steps} steps")
+    p = dimer.plain_config(N)
+    prob, _, _ = dimer_adjoint_problem(lib, p, steps, S, ckpt_every=steps // 4)
+    J, g = prob.value_and_grad(THETA.copy())
+    assert abs(J - J_o) <= 1e-12 * abs(J_o), (J, J_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-7)
 
 
 def test_checkpoint_interval_invariance(lib):
