@@ -18,10 +18,15 @@ the paper:
                      matrix itself (eq. 1), and matrix-exponential propagation.
 * ``adjoint``     -- the discrete adjoint of the RK4 map for a time-averaged
                      observable, plus forward-mode (tangent-linear)
-                     sensitivities, dense.
+                     sensitivities, dense, and the same sensitivities of RK4
+                     on the density matrix itself (no basis).
+* ``o2``          -- plain C + OpenMP (``o2.c``, compiled by build() into
+                     ``libo2.so``): Q, R, K by the same explicit traces column
+                     by column at any N, and a multi-core CSR RK4 (the timed
+                     CPU baseline).
 
 Parity status of each function is stated in its own docstring; every function
 is pinned by tests against values the paper or the mathematics fixes.
 """
 
-from . import basis, lindblad, propagate, adjoint  # noqa: F401
+from . import basis, lindblad, propagate, adjoint, o2  # noqa: F401

@@ -12,7 +12,7 @@ import pytest
 import scipy.sparse as sp
 
 from helpers import flush, rel_matrix_err, rel_vec_err, to_scipy
-from oracle import basis as ob, lindblad as lb
+from oracle import basis as ob, lindblad as lb, o2
 from workloads import dimer, random_ops
 
 pytestmark = pytest.mark.gpu
@@ -99,3 +99,24 @@ def test_dimer_1001_sampled_columns(lib):
         assert np.max(np.abs(Gc - O)) <= TOL * scale, name
     K = lind.export("L", 0)[3].cpu().numpy()
     assert rel_vec_err(K, lb.k_vector(ops["L"])) <= TOL
+
+
+@pytest.mark.parametrize("N", [301, 1001])
+def test_dimer_full_matrices_c_oracle(lib, N):
+    """Every entry of Q_H0, Q_H1, R and K at the adjoint size (N = 301,
+    M = 90,600) and the headline size (N = 1001, M = 1,002,000) against the
+    C/OpenMP oracle's explicit traces (Tr(F_s L(F_m)) column by column)."""
+    flush(f"[assembly dimer full, C oracle] N={N}")
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    b = lib.build_basis(N)
+    lind = lib.Lindbladian(b, [ops["H0"], ops["H1"]], [ops["L"]])
+    M = N * N - 1
+    for kind, idx, name in (("H", 0, "H0"), ("H", 1, "H1"), ("L", 0, "L")):
+        ex = lind.export(kind, idx)
+        G = to_scipy(ex[0], ex[1], ex[2], M)
+        O = o2.q_full(kind, ops[name])
+        assert G.nnz == O.nnz, name
+        assert rel_matrix_err(G, O) <= TOL, name
+    K = lind.export("L", 0)[3].cpu().numpy()
+    assert rel_vec_err(K, o2.k_vector(ops["L"])) <= TOL
