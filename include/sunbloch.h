@@ -208,12 +208,26 @@ int sun_propagate(sun_prop p, double* v, const double* coef, double dt,
 int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt,
                          int64_t steps, int64_t every, double* states, int64_t ld,
                          const double* x, double x0, double* obs, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as sun_propagate_record, bitwise, with the
+ * observable's partial sums kept in a fixed device array of 1024 doubles
+ * (8 KiB per device, held until the process ends) instead of a buffer the
+ * object allocates on first use; the call makes no device allocation.  The
+ * partials of any size fit (at most 512 pairs); a request beyond the array
+ * would return SUN_ENOTSUP.  Every call on one device shares that device's
+ * array, so calls that overlap on one device (concurrent streams or threads
+ * with obs != NULL) race; serialise them.  Same arguments and errors as
+ * sun_propagate_record. */
+int sun_propagate_record_noalloc(sun_prop p, double* v, const double* coef, double dt,
+                                 int64_t steps, int64_t every, double* states, int64_t ld,
+                                 const double* x, double x0, double* obs, void* stream);
 /* Stability guard (RK4 is stable only while every eigenvalue lambda of the
  * generator's linear part has lambda*dt inside its stability region): the
  * spectral radius is estimated by power iteration (as sun_prop_spectral_radius,
  * `iters` applications) at every corner of the box [coef_lo, coef_hi] of the
  * time-dependent coefficients (host double[ndyn] each; 2^ndyn estimates), and
- * from then on sun_propagate, sun_propagate_record and
+ * from then on sun_propagate, sun_propagate_record(_noalloc) and
  * sun_propagate_profile refuse, with SUN_EUNSTABLE and before any launch, a
  * step with |dt| * rho_max > limit.  limit = 0 takes 2.6, just below 2.6156,
  * the smallest radius of the boundary of RK4's stability region
@@ -227,7 +241,7 @@ int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt,
 int sun_prop_guard_stability(sun_prop p, const double* coef_lo, const double* coef_hi, int32_t iters,
                              double limit, double* rho_max, void* stream);
 /* Finite check (on by default): at the end of every sun_propagate,
- * sun_propagate_record and sun_propagate_profile call, one kernel
+ * sun_propagate_record(_noalloc) and sun_propagate_profile call, one kernel
  * checks the state for NaN and infinite entries, the call synchronises
  * `stream`, and a non-finite state is returned as computed with status
  * SUN_EDIVERGED.  A non-finite entry never becomes finite again under RK4

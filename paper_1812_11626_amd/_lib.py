@@ -61,6 +61,7 @@ PROTOS = {
     "sun_propagate": (C.c_int, [vp, vp, vp, f64, i64, vp]),
     "sun_propagate_profile": (C.c_int, [vp, vp, vp, f64, i64, vp, P(f64), P(i64)]),
     "sun_propagate_record": (C.c_int, [vp, vp, vp, f64, i64, i64, vp, i64, vp, f64, vp, vp]),
+    "sun_propagate_record_noalloc": (C.c_int, [vp, vp, vp, f64, i64, i64, vp, i64, vp, f64, vp, vp]),
     "sun_prop_info": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
     "sun_prop_spectral_radius": (C.c_int, [vp, P(f64), i32, P(f64), vp]),
     "sun_prop_guard_stability": (C.c_int, [vp, P(f64), P(f64), i32, f64, P(f64), vp]),

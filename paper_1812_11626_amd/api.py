@@ -302,11 +302,12 @@ class Propagator:
         return rho.value
 
     def record(self, v: torch.Tensor, coef: torch.Tensor | None, dt: float, steps: int, every: int,
-               states: bool = True, observable=None):
+               states: bool = True, observable=None, noalloc: bool = False):
         """RK4 like ``propagate`` (in place on v), recording after every
         ``every`` steps.  Returns (states (nrec, M) or None, obs (nrec,) or
         None); observable = (x, x0) gives obs = x0 + x . v (e.g. from
-        Basis.observable)."""
+        Basis.observable).  noalloc=True calls sun_propagate_record_noalloc
+        (the library allocates nothing during the call)."""
         assert v.dtype == torch.float64 and v.is_cuda and v.is_contiguous() and v.numel() == self.M
         if self.ndyn:
             assert coef is not None and coef.dtype == torch.float64 and coef.is_cuda and coef.is_contiguous()
@@ -318,7 +319,7 @@ class Propagator:
             x, x0 = observable
             assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == self.M
             obs = torch.empty(nrec, dtype=torch.float64, device="cuda")
-        fn = self._lib.sun_propagate_record
+        fn = self._lib.sun_propagate_record_noalloc if noalloc else self._lib.sun_propagate_record
         check(fn(self.handle, _ptr(v), _ptr(coef), float(dt), int(steps), int(every), _ptr(st), self.M, _ptr(x),
                  float(x0), _ptr(obs), _stream()))
         return st, obs

@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cmath>
 #include <atomic>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -1581,6 +1582,12 @@ extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double d
   });
 }
 
+// Fixed device array for the allocation-free recording entry point (see
+// record_scratch below): 2 * 512 doubles, the most partial sums the
+// observable's dot product uses (record_blocks() <= 512).
+constexpr int kRecordScratchDoubles = 1024;
+static __device__ __align__(256) double scratch[kRecordScratchDoubles];
+
 namespace {
 
 // Body of sun_propagate_record: `part` holds the 2*nb partial sums of the
@@ -1648,6 +1655,32 @@ void check_record_args(const sun_prop_s* p, const double* v, const double* coef,
   prop_require_usable(*p);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free recording: the observable's partial sums live in a fixed
+// file-scope device array instead of a buffer the object allocates on first
+// use.  Each device holds its own copy of the array; its address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is handed to kernels.  Calls that overlap on one device share
+// the array and race.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+double* record_scratch() {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  SUN_REQUIRE(dev >= 0 && dev < kMaxDevices, SUN_ENOTSUP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    SUN_REQUIRE(ptr != nullptr, SUN_EDEVICE, "hipGetSymbolAddress returned NULL for the record scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" int sun_propagate_record(sun_prop p, double* v, const double* coef, double dt, int64_t steps,
@@ -1660,6 +1693,21 @@ extern "C" int sun_propagate_record(sun_prop p, double* v, const double* coef, d
     const int nb = record_blocks(p->M);
     if (obs && p->rec_part.n < (size_t)(2 * nb)) p->rec_part.alloc(2 * nb);
     propagate_record(*p, v, coef, dt, steps, every, states, ld, x, x0, obs, p->rec_part.get(), as_stream(stream));
+  });
+}
+
+extern "C" int sun_propagate_record_noalloc(sun_prop p, double* v, const double* coef, double dt, int64_t steps,
+                                            int64_t every, double* states, int64_t ld, const double* x, double x0,
+                                            double* obs, void* stream) {
+  return guarded([&] {
+    check_record_args(p, v, coef, steps, every, states, ld, x, obs);
+    check_step_size(*p, dt);
+    if (steps == 0) return;
+    const int nb = record_blocks(p->M);
+    SUN_REQUIRE(2 * nb <= kRecordScratchDoubles, SUN_ENOTSUP,
+                "observable partials exceed the fixed scratch array (1024 doubles)");
+    double* part = obs ? record_scratch() : nullptr;
+    propagate_record(*p, v, coef, dt, steps, every, states, ld, x, x0, obs, part, as_stream(stream));
   });
 }
 

@@ -61,6 +61,8 @@ def test_host_side_argument_checks():
     assert lib.sun_bloch_expect(None, None, 1, 0, None, None, None, None, None, None) == _lib.SUN_EINVAL
     n = ctypes.c_int64()
     assert lib.sun_lind_nnz(None, 0, 0, ctypes.byref(n)) == _lib.SUN_EINVAL
+    assert lib.sun_propagate_record_noalloc(None, None, None, 0.1, 1, 1, None, 0, None, 0.0, None,
+                                            None) == _lib.SUN_EINVAL
     assert lib.sun_prop_guard_stability(None, None, None, 100, 0.0, None, None) == _lib.SUN_EINVAL
     assert lib.sun_prop_check_finite(None, 1) == _lib.SUN_EINVAL
     assert lib.sun_debug_inject_failure(7) == _lib.SUN_EINVAL
