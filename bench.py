@@ -105,25 +105,77 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(p, ops, budget_s=12.0):
-    """The oracle's density-matrix RK4 (eq. 1 integrated directly), timed on
-    the host on a bounded number of steps of the same workload."""
-    from oracle import propagate as pr
-    N = p.N
-    rho = np.zeros((N, N), complex)
-    rho[0, 0] = 1.0
-    steps_done = 0
-    t_start = time.perf_counter()
-    chunk = 2
+def _host_info():
+    """Host cores this process may use and the CPU model (lscpu)."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = ""
+    try:
+        import subprocess
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return ncpu, model
+
+
+def cpu_baseline(p, ops):
+    """The oracle's C/OpenMP tier timed on the host: assembly of Q_H0, Q_H1,
+    R and K by explicit traces, then its CSR RK4 on the same N = 1001 workload
+    on every host core (2000 steps after one warm-up step) and on one thread
+    (200 steps); the N = 51 workload over its full 100,000 steps on every core
+    (and 10,000 steps on one thread)."""
+    from oracle import o2
     from workloads import dimer
-    while time.perf_counter() - t_start < budget_s and steps_done < 400:
-        eps = dimer.drive_table(p, steps=chunk, t0=steps_done * p.dt)
-        rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [p.gamma_eff], rho, eps[:, None], p.dt, chunk)
-        steps_done += chunk
-    el = time.perf_counter() - t_start
-    return {"value": steps_done / el, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps_done} RK4 steps of the N={N} dimer by the oracle's density-matrix RK4 "
-                      f"(scipy sparse x dense, single thread), {el:.1f} s"}
+    ncpu, model = _host_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or ncpu)
+    threads = max(1, min(threads, ncpu))
+
+    def assemble(q, qops, nth):
+        t0 = time.perf_counter()
+        Q0 = o2.q_full("H", qops["H0"], threads=nth)
+        Q1 = o2.q_full("H", qops["H1"], threads=nth)
+        R = o2.q_full("L", qops["L"], threads=nth)
+        K = o2.k_vector(qops["L"])
+        t = time.perf_counter() - t0
+        return [((Q0 + q.gamma_eff * R).tocsr(), q.gamma_eff * K), (Q1, None)], t
+
+    def fock(N):
+        v = np.zeros(N * N - 1)
+        P = N * (N - 1) // 2
+        l = np.arange(1, N)
+        v[2 * P:] = 1.0 / np.sqrt(l * (l + 1.0))       # Bloch vector of |0><0|
+        return v
+
+    def rate(terms, q, N, steps, nth):
+        eps = dimer.drive_table(q, steps=steps + 1)
+        coef = np.stack([np.ones_like(eps), eps], axis=1)
+        v = o2.rk4(terms, coef[:3], fock(N), q.dt, 1, threads=nth)        # warm-up step
+        t0 = time.perf_counter()
+        v = o2.rk4(terms, coef[2:], v, q.dt, steps, threads=nth)
+        el = time.perf_counter() - t0
+        assert np.all(np.isfinite(v))
+        return steps / el, el
+
+    terms, t_asm = assemble(p, ops, threads)
+    r_mc, el_mc = rate(terms, p, p.N, 2000, threads)
+    r_1, el_1 = rate(terms, p, p.N, 200, 1)
+    q51 = dimer.plain_config(51)
+    ops51 = dimer.dimer_operators(q51)
+    terms51, t_asm51 = assemble(q51, ops51, threads)
+    r51_mc, el51_mc = rate(terms51, q51, 51, q51.steps, threads)
+    r51_1, el51_1 = rate(terms51, q51, 51, 10000, 1)
+    return {"value": r_mc, "unit": "RK4 steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"2000 RK4 steps ({el_mc:.1f} s) of the N={p.N} dimer by the oracle's C/OpenMP CSR RK4 on "
+                      f"{threads} threads after one warm-up step, on Q_H0 + gamma R, Q_H1 and K assembled by the "
+                      f"oracle's explicit traces ({t_asm:.1f} s on {threads} threads)",
+            "single_thread_steps_per_s": r_1, "single_thread_sample": f"200 steps, {el_1:.1f} s",
+            "assembly_s": t_asm, "host_cpus": ncpu, "host_model": model,
+            "N51": {"steps_per_s": r51_mc, "cores": threads, "full_100_periods_s": el51_mc,
+                    "single_thread_steps_per_s": r51_1, "assembly_s": t_asm51}}
 
 
 def _fock_v0(sb, basis, N, i=0):
@@ -563,7 +615,8 @@ def main():
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(p, ops)
         out["cpu_baseline"] = cb
-        log(f"cpu baseline: {cb['value']:.3f} steps/s")
+        log(f"cpu baseline: {cb['value']:.2f} steps/s on {cb['cores']} threads, "
+            f"{cb['single_thread_steps_per_s']:.2f} on one; N=51: {cb['N51']['steps_per_s']:.0f} steps/s")
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
