@@ -52,7 +52,8 @@ enum {
   SUN_ENOTSUP = -4,  /* valid input outside what the library supports (limits stated per call) */
   SUN_ERANGE = -5,   /* caller buffer too small; the needed size is returned */
   SUN_EDIVERGED = -6,/* the propagated state (or a result computed from it) is not finite */
-  SUN_EUNSTABLE = -7 /* dt * |lambda|max beyond the RK4 stability bound set by sun_prop_guard_stability */
+  SUN_EUNSTABLE = -7,/* dt * |lambda|max beyond the RK4 stability bound set by sun_prop_guard_stability */
+  SUN_ENOTCONVERGED = -8 /* an iterative solve stopped at its iteration limit above its tolerance */
 };
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -250,6 +251,27 @@ int sun_prop_guard_stability(sun_prop p, const double* coef_lo, const double* co
  * period.  on = 0 turns the check off, and with it the synchronisation: the
  * calls are then asynchronous on `stream`. */
 int sun_prop_check_finite(sun_prop p, int32_t on);
+/* Stationary state of the time-independent generator G obtained by freezing
+ * the time-dependent coefficients at coef (host double[ndyn]): the solution
+ * of G v = -K (eq. 9 with dv/dt = 0; the paper's asymptotic state of a
+ * time-independent Lindbladian, Sec. I, in Bloch form).  Restarted GMRES
+ * (restart vectors, at most max_iter iterations in total) on the RK4 time-tau
+ * map, tau = steps_per_map * dt: (I - Phi) v = phi with Phi = R4(dt G)^n and
+ * phi the map of the zero state, applied by the propagator's stage kernels.
+ * The fixed point of that map is exactly the solution of G v = -K; modes
+ * decaying faster than 1/tau are damped by the map, so GMRES only has to
+ * resolve the slower ones (choose tau of a few inverse decay rates; the
+ * driven dimer's slowest rate is about 0.15, and tau = 5 converges in about
+ * 17 iterations for N up to 301).  dt must be a stable RK4 step for G.
+ * v: device double[M], the initial guess on entry (e.g. zeros) and the
+ * solution on return.  Converged when ||G v + K||_2 <= tol ||K||_2 (K = 0:
+ * v = 0, the maximally mixed state, is returned).  *iters and *relres (host,
+ * may be NULL) receive the GMRES iterations and ||G v + K||_2 / ||K||_2.
+ * SUN_ENOTCONVERGED when max_iter is reached above tol (v holds the last
+ * iterate), SUN_EDIVERGED for a non-finite iterate.  Allocates (restart + 6)
+ * vectors of M+1 doubles for the call; synchronises `stream`. */
+int sun_stationary(sun_prop p, const double* coef, double dt, int64_t steps_per_map, int32_t restart,
+                   int32_t max_iter, double tol, double* v, int32_t* iters, double* relres, void* stream);
 /* Spectral radius |lambda|max of the linear part of the generator, G with
  * the time-dependent coefficients frozen at coef (host double[ndyn]), by
  * power iteration: `iters` applications of G to a normalised pseudo-random

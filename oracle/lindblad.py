@@ -27,9 +27,12 @@ Two tiers:
   ``k_vector``): column m of Q or R is the Bloch coordinate vector of
   L(F_m), with F_m sparse and H, L as scipy sparse matrices; any N.
 
+``stationary_bloch`` solves G v = -K for a time-independent generator.
+
 Parity: pinned -- qubit amplitude damping closed form, Larmor precession,
 skew-symmetry of the unitary part, dense-Liouvillian kernel, agreement of the
-two tiers (tests/test_oracle_lindblad.py).
+two tiers, the stationary state against the Liouvillian's kernel and against
+long-time RK4 (tests/test_oracle_lindblad.py).
 """
 
 from __future__ import annotations
@@ -289,3 +292,14 @@ def density_from_bloch_dense(v: np.ndarray, N: int) -> np.ndarray:
         d[l] += v[2 * P + l - 1] * (-l * c)
     rho[np.arange(N), np.arange(N)] = d
     return rho
+
+
+def stationary_bloch(G, K) -> np.ndarray:
+    """Stationary Bloch vector of a time-independent generator: the solution
+    of G v = -K (eq. 9 with dv/dt = 0; the asymptotic state of Sec. I in Bloch
+    form), by a sparse direct solve (scipy's LU as the library primitive).
+    G: dense or scipy sparse (M, M); K: (M,)."""
+    import scipy.sparse.linalg as spla
+    if sp.issparse(G):
+        return spla.spsolve(sp.csc_matrix(G), -np.asarray(K, dtype=np.float64))
+    return np.linalg.solve(np.asarray(G, dtype=np.float64), -np.asarray(K, dtype=np.float64))

@@ -16,12 +16,13 @@ SUN_ENOTSUP = -4
 SUN_ERANGE = -5
 SUN_EDIVERGED = -6
 SUN_EUNSTABLE = -7
+SUN_ENOTCONVERGED = -8
 SUN_TERM_H = 0
 SUN_TERM_L = 1
 
 _STATUS_NAMES = {SUN_EINVAL: "SUN_EINVAL", SUN_ENOMEM: "SUN_ENOMEM", SUN_EDEVICE: "SUN_EDEVICE",
                  SUN_ENOTSUP: "SUN_ENOTSUP", SUN_ERANGE: "SUN_ERANGE", SUN_EDIVERGED: "SUN_EDIVERGED",
-                 SUN_EUNSTABLE: "SUN_EUNSTABLE"}
+                 SUN_EUNSTABLE: "SUN_EUNSTABLE", SUN_ENOTCONVERGED: "SUN_ENOTCONVERGED"}
 
 
 class SunError(RuntimeError):
@@ -66,6 +67,7 @@ PROTOS = {
     "sun_prop_spectral_radius": (C.c_int, [vp, P(f64), i32, P(f64), vp]),
     "sun_prop_guard_stability": (C.c_int, [vp, P(f64), P(f64), i32, f64, P(f64), vp]),
     "sun_prop_check_finite": (C.c_int, [vp, i32]),
+    "sun_stationary": (C.c_int, [vp, P(f64), f64, i64, i32, i32, f64, vp, P(i32), P(f64), vp]),
     "sun_debug_inject_failure": (C.c_int, [i32]),
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),

@@ -286,6 +286,26 @@ class Propagator:
         self._guard = (lo, hi) if limit >= 0 else None
         return rho.value
 
+    def stationary(self, coef=(), dt: float = 0.0, tau: float = 5.0, restart: int = 40, max_iter: int = 400,
+                   tol: float = 1e-10, v0: torch.Tensor | None = None):
+        """Stationary state of the generator with the time-dependent
+        coefficients frozen at ``coef``: G v = -K by GMRES on the RK4
+        time-tau map (sun_stationary).  dt: a stable RK4 step (default: 2.5 /
+        |lambda|max from the power iteration).  Returns (v, iterations,
+        ||G v + K|| / ||K||)."""
+        c = list(coef)
+        assert len(c) == self.ndyn
+        buf = (C.c_double * max(1, len(c)))(*[float(x) for x in c])
+        if not dt:
+            dt = 2.5 / self.spectral_radius(c)
+        n = max(1, int(round(tau / dt)))
+        v = torch.zeros(self.M, dtype=torch.float64, device="cuda") if v0 is None \
+            else v0.detach().to("cuda", torch.float64).clone().contiguous()
+        it, rr = C.c_int32(), C.c_double()
+        check(self._lib.sun_stationary(self.handle, buf, float(dt), n, int(restart), int(max_iter), float(tol),
+                                       _ptr(v), C.byref(it), C.byref(rr), _stream()))
+        return v, it.value, rr.value
+
     def check_finite(self, on: bool = True):
         """Finite check of the state at the end of every propagation call
         (on by default; SUN_EDIVERGED when it fails)."""

@@ -21,7 +21,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "libsunbloch.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-SOURCES = ["common.hip", "basis.hip", "assemble.hip", "propagate.hip", "batched.hip", "adjoint.hip", "readout.hip"]
+SOURCES = ["common.hip", "basis.hip", "assemble.hip", "propagate.hip", "batched.hip", "adjoint.hip", "readout.hip",
+           "stationary.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

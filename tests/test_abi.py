@@ -74,6 +74,9 @@ def test_host_side_argument_checks():
                                    None, None) == _lib.SUN_EINVAL
     assert lib.sun_adjoint_set_weights(None, None, None) == _lib.SUN_EINVAL
     assert lib.sun_propagate_batched(None, 1, None, None, None, None, None, None, None, None) == _lib.SUN_EINVAL
+    it, rr = ctypes.c_int32(), ctypes.c_double()
+    assert lib.sun_stationary(None, None, 0.1, 10, 30, 100, 1e-10, None, ctypes.byref(it), ctypes.byref(rr),
+                              None) == _lib.SUN_EINVAL
 
 
 def test_status_codes_match_header():
@@ -81,7 +84,7 @@ def test_status_codes_match_header():
     from paper_1812_11626_amd import _lib
     text = open(HEADER).read()
     for name in ("SUN_EINVAL", "SUN_ENOMEM", "SUN_EDEVICE", "SUN_ENOTSUP", "SUN_ERANGE", "SUN_EDIVERGED",
-                 "SUN_EUNSTABLE"):
+                 "SUN_EUNSTABLE", "SUN_ENOTCONVERGED"):
         m = re.search(name + r"\s*=\s*(-?\d+)", text)
         assert m is not None, name
         assert int(m.group(1)) == getattr(_lib, name), name

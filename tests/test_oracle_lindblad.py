@@ -210,3 +210,41 @@ def test_gauge_identity_for_dissipator_with_trace():
     l = lb.expand(F, L)
     np.testing.assert_allclose(lb.expand(F, Hc).real, -np.imag(np.conj(c) * l), atol=1e-14)
 
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_stationary_bloch_is_liouvillian_kernel(N):
+    """lindblad.stationary_bloch (sparse solve of G v = -K) equals the Bloch
+    vector of the normalised kernel of the dense Liouvillian (Kronecker
+    products, no basis)."""
+    import scipy.sparse as sps
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    F = basis.generators(N)
+    H = ops["H0"].to_dense() + p.E * ops["H1"].to_dense()
+    L = ops["L"].to_dense()
+    G = lb.q_hamiltonian(F, H) + p.gamma_eff * lb.q_dissipator(F, L)
+    K = p.gamma_eff * lb.k_dissipator(F, L)
+    v = lb.stationary_bloch(sps.csr_matrix(G), K)
+    w, V = np.linalg.eig(lb.liouvillian(H, [L], [p.gamma_eff]))
+    k = np.argmin(np.abs(w))
+    rho = lb.unvec(V[:, k], N)
+    rho = rho / np.trace(rho)
+    np.testing.assert_allclose(v, lb.bloch_vector(F, rho), atol=1e-10)
+
+
+def test_stationary_bloch_is_long_time_limit():
+    """At N = 21 the stationary state is where RK4 with the static drive
+    ends up after t = 200 (every mode decays at a rate >= 0.15)."""
+    from oracle import propagate as pr
+    N = 21
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    G = lb.q_full("H", ops["H0"]) + p.E * lb.q_full("H", ops["H1"]) + p.gamma_eff * lb.q_full("L", ops["L"])
+    K = p.gamma_eff * lb.k_vector(ops["L"])
+    v = lb.stationary_bloch(G, K)
+    steps = 20000
+    dt = 200.0 / steps
+    v0 = np.zeros(N * N - 1)
+    vt = pr.rk4_bloch(G, [], K, v0, np.zeros((2 * steps + 1, 0)), dt, steps)
+    assert np.max(np.abs(vt - v)) <= 1e-9 * np.max(np.abs(v))
