@@ -151,15 +151,35 @@ enum { SUN_TERM_H = 0, SUN_TERM_L = 1 };
  * trace, L = c 1 + L' (c = Tr(L)/N), is handled by the identity
  * D_L = D_L' - i[H_c, .] with H_c = (i/2)(conj(c) L' - c L'^+): R_p is then
  * the R of L' plus the Q of H_c (eq. 6), and K_p is unchanged.
- * Limits: every assembled row must have at most 16384 raw contributions
- * (8192 on devices with less than 160 KB of LDS per workgroup; else
- * SUN_ENOTSUP, detected from the per-row counts before any fill); total nnz
- * of each matrix < 2^31.  Sparse operators (the dimer: <= 5N per row) are
- * far inside the limit; dense L beyond N ~ 30 is not.
+ * Limits: a term whose assembled rows have more than 16384 raw
+ * contributions (8192 on devices with less than 160 KB of LDS per
+ * workgroup), which dense L reaches beyond N ~ 60, is assembled by the dense
+ * path of sun_expand_lindbladian_dense instead (detected from the per-row
+ * counts before any fill); total nnz of each matrix < 2^31.  Sparse
+ * operators (the dimer: <= 5N per row) are far inside the limit.
  * Synchronises `stream` (sizes are read back).  */
 int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH,
                            const sun_zcsr* L, int32_t P, void* stream,
                            sun_lind* out);
+/* The same matrices by the dense path, for operators with many nonzeros
+ * (dense or random L and H): every row of the contractions is written into
+ * a dense M x M array by the thread that generates it, and the dissipative
+ * part is formed as one real matrix product on the matrix cores,
+ *     R_p = -(1/2) [Re B^T | -Im B^T] [Re A ; Im A] = -(1/2) Re(B^T A)
+ * (eq. 10 with dense sections; a K = 2M contraction), then compressed to CSR
+ * with the same drop rule.  No per-row limit; device memory about 5 M^2
+ * doubles while a dissipator is assembled (4 GB at N = 100).
+ * sun_expand_lindbladian itself switches to this path for a term whose rows
+ * exceed its per-row limit.  Synchronises `stream`. */
+int sun_expand_lindbladian_dense(sun_basis b, const sun_zcsr* H, int32_t nH,
+                                 const sun_zcsr* L, int32_t P, void* stream,
+                                 sun_lind* out);
+/* C = alpha A B + beta C in FP64 (row-major, device pointers; A: M x K with
+ * leading dimension lda >= K, B: K x N with ldb >= N, C: M x N with ldc >= N)
+ * on the matrix cores (the kernel the dense path uses; exposed for
+ * measurement).  beta = 0 does not read C.  Asynchronous on `stream`. */
+int sun_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, double beta, double* C, int64_t ldc, void* stream);
 /* nnz of Q_a (which = SUN_TERM_H) or R_p (which = SUN_TERM_L). */
 int sun_lind_nnz(sun_lind l, int32_t which, int32_t index, int64_t* nnz);
 /* Copy Q_a or R_p out as CSR into caller device buffers rowptr int32[M+1],

@@ -23,6 +23,7 @@ from .api import (  # noqa: F401
     Propagator,
     build_basis,
     expand_lindbladian,
+    gemm_f64,
     propagate,
     require_gpu,
     SunBlochLoss,

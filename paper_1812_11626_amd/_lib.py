@@ -53,6 +53,8 @@ PROTOS = {
     "sun_basis_free": (None, [vp]),
     "sun_expand_operator": (C.c_int, [vp, P(ZCSR), vp, vp, P(f64), vp]),
     "sun_expand_lindbladian": (C.c_int, [vp, P(ZCSR), i32, P(ZCSR), i32, vp, P(vp)]),
+    "sun_expand_lindbladian_dense": (C.c_int, [vp, P(ZCSR), i32, P(ZCSR), i32, vp, P(vp)]),
+    "sun_gemm_f64": (C.c_int, [i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64, vp]),
     "sun_lind_nnz": (C.c_int, [vp, i32, i32, P(i64)]),
     "sun_lind_export": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
     "sun_lind_free": (None, [vp]),

@@ -148,6 +148,23 @@ class Basis:
         return out if v.dim() == 2 else out[0]
 
 
+def gemm_f64(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
+             beta: float = 0.0) -> torch.Tensor:
+    """C = alpha A B + beta C on the matrix cores (sun_gemm_f64); float64
+    CUDA tensors, row-major with unit column stride."""
+    assert A.dtype == B.dtype == torch.float64 and A.is_cuda and B.is_cuda
+    assert A.dim() == B.dim() == 2 and A.shape[1] == B.shape[0] and A.stride(1) == 1 and B.stride(1) == 1
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device="cuda")
+        beta = 0.0
+    assert C.shape == (M, N) and C.stride(1) == 1
+    check(_lib.load().sun_gemm_f64(M, N, K, float(alpha), _ptr(A), A.stride(0), _ptr(B), B.stride(0), float(beta),
+                                   _ptr(C), C.stride(0), _stream()))
+    return C
+
+
 def build_basis(N: int) -> Basis:
     return Basis(N)
 
@@ -156,7 +173,10 @@ class Lindbladian:
     """Assembled Bloch-form generator: Q_a per Hamiltonian term, R_p and K_p
     per dissipator (unit rates), kept on the GPU (sun_expand_lindbladian)."""
 
-    def __init__(self, basis: Basis, H: list, L: list):
+    def __init__(self, basis: Basis, H: list, L: list, dense: bool = False):
+        """dense=True assembles every term by the dense path (dense sections,
+        R by a matrix-core product); otherwise the sparse row path, which
+        switches to the dense one for terms beyond its per-row limit."""
         self.basis = basis
         self._lib = basis._lib
         hs = [_dev_op(h) for h in H]
@@ -164,8 +184,8 @@ class Lindbladian:
         Harr = (ZCSR * max(1, len(hs)))(*[h.as_struct() for h in hs])
         Larr = (ZCSR * max(1, len(ls)))(*[l.as_struct() for l in ls])
         h = C.c_void_p()
-        check(self._lib.sun_expand_lindbladian(basis.handle, Harr, len(hs), Larr, len(ls), _stream(),
-                                               C.byref(h)))
+        fn = self._lib.sun_expand_lindbladian_dense if dense else self._lib.sun_expand_lindbladian
+        check(fn(basis.handle, Harr, len(hs), Larr, len(ls), _stream(), C.byref(h)))
         self.handle = h
         self.nH = len(hs)
         self.P = len(ls)

@@ -22,7 +22,7 @@ LIB_NAME = "libsunbloch.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 SOURCES = ["common.hip", "basis.hip", "assemble.hip", "propagate.hip", "batched.hip", "adjoint.hip", "readout.hip",
-           "stationary.hip"]
+           "stationary.hip", "gemm.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -372,6 +372,102 @@ __global__ void k_free_vector(int64_t M, int N, const int* __restrict__ bptr, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dense assembly (operators with many nonzeros: dense or random L, dense H).
+// Each row s of C(x; wf, wd) is written into a dense row by the thread that
+// generates it (the same contraction generator as the sparse path, so each
+// entry is summed in the same order); the sections then meet in one real
+// matrix product on the matrix cores:
+//   X = [Re B^T | -Im B^T]  (M x 2M),   Y = [Re A ; Im A]  (2M x M),
+//   R = -(1/2) X Y = -(1/2) Re(B^T A).
+// ---------------------------------------------------------------------------
+enum DenseMode : int { DM_REAL = 0, DM_BT = 1, DM_A = 2 };
+
+template <int MODE>
+__global__ void k_dense_rows(ContractGen<cplx> g, int64_t M, double* __restrict__ out, int64_t ld) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (int64_t)gridDim.x * blockDim.x) {
+    double* row = out + s * ld;
+    double* row_im = MODE == DM_A ? out + (M + s) * ld : row + M;
+    auto emit = [&](uint64_t n, cplx v) {
+      row[n] += v.re;
+      if (MODE == DM_BT) row_im[n] -= v.im;
+      if (MODE == DM_A) row_im[n] += v.im;
+    };
+    g.run((int)s, emit);
+  }
+}
+
+// K[s] = (1/N) Im(B^T l)[s] = (1/N) sum_l (X[s][l] Im l_l - X[s][M+l] Re l_l),
+// one workgroup per row, fixed-order reduction
+__global__ __launch_bounds__(256) void k_dense_free_vector(int64_t M, int N, const double* __restrict__ X,
+                                                           const cplx* __restrict__ l, double* __restrict__ K) {
+  __shared__ double sh[256];
+  for (int64_t s = blockIdx.x; s < M; s += gridDim.x) {
+    const double* xr = X + s * 2 * M;
+    double a = 0.0;
+    for (int64_t j = threadIdx.x; j < M; j += 256) a += xr[j] * l[j].im - xr[M + j] * l[j].re;
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) K[s] = sh[0] / (double)N;
+    __syncthreads();
+  }
+}
+
+// per-row max |a| of a dense M x M matrix (one wavefront per row)
+__global__ __launch_bounds__(256) void k_dense_rowmax(int64_t M, const double* __restrict__ a,
+                                                      double* __restrict__ rmax) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < M;
+       r += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+    double m = 0.0;
+    for (int64_t c = lane; c < M; c += 64) m = fmax(m, fabs(a[r * M + c]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if (lane == 0) rmax[r] = m;
+  }
+}
+
+// CSR of the entries with |a| > thr, in column order: mode 0 counts per row,
+// mode 1 fills (one wavefront per row, positions by ballot prefix counts)
+template <int FILL>
+__global__ __launch_bounds__(256) void k_dense_compress(int64_t M, const double* __restrict__ a, double thr,
+                                                        int64_t* __restrict__ cnt, const int64_t* __restrict__ off,
+                                                        int* __restrict__ col, double* __restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < M;
+       r += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+    int64_t base = FILL ? off[r] : 0;
+    for (int64_t c0 = 0; c0 < M; c0 += 64) {
+      const int64_t c = c0 + lane;
+      const double v = c < M ? a[r * M + c] : 0.0;
+      const bool keep = c < M && fabs(v) > thr;
+      const uint64_t mask = __ballot(keep);
+      if (FILL && keep) {
+        const int64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+        col[pos] = (int)c;
+        val[pos] = v;
+      }
+      base += __popcll(mask);
+    }
+    if (!FILL && lane == 0) cnt[r] = base;
+  }
+}
+
+__global__ void k_rowptr_from_off(int64_t M, const int64_t* __restrict__ off, int64_t nnz, int* __restrict__ rowptr) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    rowptr[i] = (int)off[i];
+    if (i == 0) rowptr[M] = (int)nnz;
+  }
+}
+
+__global__ void k_dense_fill(int64_t n, double v, double* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
 void check_zcsr(const sun_basis_s& b, const sun_zcsr& X, hipStream_t s) {
   SUN_REQUIRE(X.n == b.N, SUN_EINVAL, "operator dimension differs from basis N");
   SUN_REQUIRE(X.nnz >= 0, SUN_EINVAL, "negative nnz");
@@ -520,6 +616,100 @@ void assemble_dissipator(const sun_basis_s& b, const sun_zcsr& L, DevCSR& out, D
   HIP_OK(hipStreamSynchronize(s));
 }
 
+
+// ---- dense path -------------------------------------------------------------
+
+// Dense M x M matrix -> CSR, dropping |q| <= kRelDrop max|q| (the same rule
+// as the sparse path).
+void dense_to_csr(int64_t M, const double* a, DevCSR& out, hipStream_t s) {
+  DevBuf<double> rmax(M);
+  hipLaunchKernelGGL(k_dense_rowmax, dim3(grid_for(M * 64, 256)), dim3(256), 0, s, M, a, rmax.get());
+  HIP_LAUNCH_OK();
+  const double thr = kRelDrop * device_max(rmax.get(), M, s);
+  DevBuf<int64_t> cnt(M), off(M);
+  hipLaunchKernelGGL(k_dense_compress<0>, dim3(grid_for(M * 64, 256)), dim3(256), 0, s, M, a, thr, cnt.get(),
+                     nullptr, nullptr, nullptr);
+  HIP_LAUNCH_OK();
+  const int64_t nnz = exclusive_scan_i64(cnt.get(), off.get(), M, s);
+  SUN_REQUIRE(nnz < (int64_t)INT32_MAX, SUN_ENOTSUP, "assembled matrix has 2^31 or more nonzeros");
+  out.rows = M;
+  out.nnz = nnz;
+  out.rowptr.alloc(M + 1);
+  out.col.alloc(nnz > 0 ? nnz : 1);
+  out.val.alloc(nnz > 0 ? nnz : 1);
+  hipLaunchKernelGGL(k_dense_compress<1>, dim3(grid_for(M * 64, 256)), dim3(256), 0, s, M, a, thr, nullptr,
+                     off.get(), out.col.get(), out.val.get());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_rowptr_from_off, dim3(grid_for(M, 256)), dim3(256), 0, s, M, off.get(), nnz,
+                     out.rowptr.get());
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+template <int MODE>
+void dense_rows(const sun_basis_s& b, const Expansion& e, const cplx* x, const cplx* xd, cplx wf, cplx wd,
+                double* out, int64_t ld, hipStream_t s) {
+  ContractGen<cplx> g{b.view(), x, xd, e.adj_ptr.get(), e.adj_idx.get(), wf, wd,
+                      (wd.re != 0.0 || wd.im != 0.0) ? 1 : 0};
+  hipLaunchKernelGGL(k_dense_rows<MODE>, dim3(grid_for(b.M, 64)), dim3(64), 0, s, g, b.M, out, ld);
+  HIP_LAUNCH_OK();
+}
+
+void dense_zero(double* a, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_fill, dim3(std::min<unsigned>(grid_for(n, 256), 65536)), dim3(256), 0, s, n, 0.0, a);
+  HIP_LAUNCH_OK();
+}
+
+void assemble_hamiltonian_dense(const sun_basis_s& b, const sun_zcsr& H, DevCSR& out, hipStream_t s) {
+  Expansion e;
+  expand_operator(b, H, e, true, s);
+  SUN_REQUIRE(e.herm_dev <= 1e-12 * (e.maxabs > 0 ? e.maxabs : 1.0), SUN_EINVAL,
+              "Hamiltonian term is not Hermitian");
+  const int64_t M = b.M;
+  DevBuf<double> Q((size_t)M * M);
+  dense_zero(Q.get(), M * M, s);
+  dense_rows<DM_REAL>(b, e, e.x.get(), e.xd.get(), cx(1.0), cx(0.0), Q.get(), M, s);
+  dense_to_csr(M, Q.get(), out, s);
+}
+
+void assemble_dissipator_dense(const sun_basis_s& b, const sun_zcsr& L, DevCSR& out, DevBuf<double>& K,
+                               hipStream_t s) {
+  Expansion e;
+  expand_operator(b, L, e, false, s);
+  const int64_t M = b.M;
+  const double tr = fmax(fabs(e.trace.re), fabs(e.trace.im));
+  const bool gauge = tr > 1e-12 * b.N * (e.maxabs > 0 ? e.maxabs : 1.0);
+  DevBuf<double> R((size_t)M * M);
+  dense_zero(R.get(), M * M, s);
+  if (gauge) {
+    // the trace moves into the Hamiltonian term H_c (see assemble_dissipator)
+    const cplx c = cx(e.trace.re / b.N, e.trace.im / b.N);
+    DevBuf<cplx> h(M), hd(b.N);
+    hipLaunchKernelGGL(k_gauge_coef, dim3(grid_for(M, 256)), dim3(256), 0, s, M, b.N, e.x.get(), e.xd.get(), c,
+                       h.get(), hd.get());
+    HIP_LAUNCH_OK();
+    dense_rows<DM_REAL>(b, e, h.get(), hd.get(), cx(1.0), cx(0.0), R.get(), M, s);
+  }
+  DevBuf<cplx> xc(M), xdc(b.N);
+  hipLaunchKernelGGL(k_conj, dim3(grid_for(M, 256)), dim3(256), 0, s, M, e.x.get(), xc.get());
+  hipLaunchKernelGGL(k_conj, dim3(grid_for(b.N, 256)), dim3(256), 0, s, (int64_t)b.N, e.xd.get(), xdc.get());
+  HIP_LAUNCH_OK();
+  DevBuf<double> X((size_t)M * 2 * M), Y((size_t)2 * M * M);
+  dense_zero(X.get(), 2 * M * M, s);
+  dense_zero(Y.get(), 2 * M * M, s);
+  dense_rows<DM_BT>(b, e, xc.get(), xdc.get(), cx(1.0), cx(0.0), X.get(), 2 * M, s);
+  dense_rows<DM_A>(b, e, e.x.get(), e.xd.get(), cx(-1.0), cx(0.0, 1.0), Y.get(), M, s);
+  gemm_f64(M, M, 2 * M, -0.5, X.get(), 2 * M, Y.get(), M, gauge ? 1.0 : 0.0, R.get(), M, s);
+  K.alloc(M);
+  hipLaunchKernelGGL(k_dense_free_vector, dim3((unsigned)std::min<int64_t>(M, 65536)), dim3(256), 0, s, M, b.N,
+                     X.get(), e.x.get(), K.get());
+  HIP_LAUNCH_OK();
+  dense_to_csr(M, R.get(), out, s);
+}
+
+// Device memory of the dense path for one dissipator: X, Y and R.
+double dense_bytes(int64_t M) { return 5.0 * (double)M * (double)M * 8.0; }
+
 }  // namespace
 
 extern "C" int sun_expand_operator(sun_basis b, const sun_zcsr* X, double* coef_re, double* coef_im,
@@ -543,8 +733,13 @@ extern "C" int sun_expand_operator(sun_basis b, const sun_zcsr* X, double* coef_
   });
 }
 
-extern "C" int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH, const sun_zcsr* L,
-                                      int32_t P, void* stream, sun_lind* out) {
+namespace {
+
+// mode 0: sparse rows (SUN_ENOTSUP past the LDS row capacity); 1: dense path
+// for every term; 2: sparse, falling back to the dense path for a term whose
+// rows exceed the capacity
+int expand_impl(sun_basis b, const sun_zcsr* H, int32_t nH, const sun_zcsr* L, int32_t P, void* stream,
+                sun_lind* out, int mode) {
   return guarded([&] {
     SUN_REQUIRE(out != nullptr, SUN_EINVAL, "out is NULL");
     *out = nullptr;
@@ -561,14 +756,47 @@ extern "C" int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH
       lind->QH.resize(nH);
       lind->R.resize(P);
       lind->K.resize(P);
-      for (int a = 0; a < nH; ++a) assemble_hamiltonian(*b, H[a], lind->QH[a], s);
-      for (int p = 0; p < P; ++p) assemble_dissipator(*b, L[p], lind->R[p], lind->K[p], s);
+      auto ham = [&](int a) {
+        if (mode == 1) return assemble_hamiltonian_dense(*b, H[a], lind->QH[a], s);
+        try {
+          assemble_hamiltonian(*b, H[a], lind->QH[a], s);
+        } catch (const Error& err) {
+          if (mode != 2 || err.code != SUN_ENOTSUP) throw;
+          assemble_hamiltonian_dense(*b, H[a], lind->QH[a], s);
+        }
+      };
+      auto dis = [&](int p) {
+        if (mode == 1) return assemble_dissipator_dense(*b, L[p], lind->R[p], lind->K[p], s);
+        try {
+          assemble_dissipator(*b, L[p], lind->R[p], lind->K[p], s);
+        } catch (const Error& err) {
+          if (mode != 2 || err.code != SUN_ENOTSUP) throw;
+          assemble_dissipator_dense(*b, L[p], lind->R[p], lind->K[p], s);
+        }
+      };
+      if (mode >= 1) {
+        SUN_REQUIRE(b->M * b->M < (int64_t)INT32_MAX * 4, SUN_ENOTSUP, "dense path limited to M^2 < 2^33 entries");
+      }
+      for (int a = 0; a < nH; ++a) ham(a);
+      for (int p = 0; p < P; ++p) dis(p);
     } catch (...) {
       delete lind;
       throw;
     }
     *out = lind;
   });
+}
+
+}  // namespace
+
+extern "C" int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH, const sun_zcsr* L,
+                                      int32_t P, void* stream, sun_lind* out) {
+  return expand_impl(b, H, nH, L, P, stream, out, 2);
+}
+
+extern "C" int sun_expand_lindbladian_dense(sun_basis b, const sun_zcsr* H, int32_t nH, const sun_zcsr* L,
+                                            int32_t P, void* stream, sun_lind* out) {
+  return expand_impl(b, H, nH, L, P, stream, out, 1);
 }
 
 extern "C" int sun_lind_nnz(sun_lind l, int32_t which, int32_t index, int64_t* nnz) {

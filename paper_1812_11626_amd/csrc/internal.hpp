@@ -53,6 +53,10 @@ struct Expansion {
 void expand_operator(const sun_basis_s& b, const sun_zcsr& X, Expansion& e,
                      bool want_hermiticity, hipStream_t s);
 
+// C = alpha A B + beta C, FP64, row-major, on the matrix cores (gemm.hip).
+void gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+              int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
+
 }  // namespace sun
 
 struct sun_lind_s {
