@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "RK4 Bloch steps/s + HBM roofline % at N=1001; batched/adjoint vs plain, FP64"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 
 
 def parse():
@@ -45,7 +46,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--block-nnz", type=int, default=0)
     ap.add_argument("--threads", type=int, default=256)
-    ap.add_argument("--only", choices=("plain", "batched", "adjoint"), default=None,
+    ap.add_argument("--only", choices=("plain", "batched", "adjoint", "dense", "stationary"), default=None,
                     help="run one leg only (for profiling); prints that leg's report")
     ap.add_argument("--scan", action="store_true",
                     help="assembly time and RK4 steps/s of the plain workload over a range of N (one JSON line)")
@@ -300,10 +301,12 @@ def bifurcation_report(sb, torch, N=101, count=128):
     return res
 
 
-def batched_report(sb, torch, steps=200):
+def batched_report(sb, torch):
     """Batched form: the 512-instance dimer workload (N in {51,...,301},
     A ~ U[0.5,3], gamma ~ logU[0.01,0.5]), one launch per RK4 stage for all
-    instances, autotuned tiles; against sequential plain solves."""
+    instances, autotuned tiles, timed over its full horizon of 20 drive
+    periods (every group through all of its steps); against sequential plain
+    solves of the same instances."""
     from workloads import dimer
     inst = dimer.batched_instances()
     byN = {}
@@ -322,18 +325,34 @@ def batched_report(sb, torch, steps=200):
         specs.append(dict(lind=lind, w=w, u=u, wave=dimer.drive_table_dA(p0), dt=p0.dt, steps=p0.steps))
         meta.append((N, idx, basis, lind, p0))
     bp = sb.BatchedPropagator(specs)
+    starts = []
     for g, (N, idx, basis, lind, p0) in enumerate(meta):
         v0 = _fock_v0(sb, basis, N)
-        bp.set_state(g, v0.unsqueeze(0).repeat(len(idx), 1))
+        starts.append(v0.unsqueeze(0).repeat(len(idx), 1))
+        bp.set_state(g, starts[-1])
     setup_s = time.perf_counter() - t0
     tuned = sb.autotune_batched(bp, probe_steps=4, log=log)
-    bp.run(2)
+    for g in range(len(meta)):
+        bp.set_state(g, starts[g])          # from t = 0 after the tuning probes
+    total = sum(len(idx) * p0.steps for (_, idx, _, _, p0) in meta)
+    most = max(p0.steps for (_, _, _, _, p0) in meta)
+    log(f"batched: {len(inst)} instances, full 20 periods ({total} instance-steps, {most} steps in the longest group)")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    bp.run(steps)
+    bp.run(most)
+    torch.cuda.synchronize()
     el = time.perf_counter() - t1
-    inst_steps = sum(len(idx) * steps for (_, idx, _, _, _) in meta)
-    batched_rate = inst_steps / el
+    finite = all(bool(torch.isfinite(bp.get_state(g)).all()) for g in range(len(meta)))
+    batched_rate = total / el
+    # algorithmic bytes of the whole run (the batched byte model): per group
+    # and stage the fused CSR once (12 per stored entry + 4 per row pointer)
+    # plus 20 bytes per state row and instance (gather, base, accumulator and
+    # output streams: 80 M per instance-step)
+    alg_bytes = 0
+    for g, (N, idx, basis, lind, p0) in enumerate(meta):
+        info = bp.info(g)
+        M = info["M"]
+        alg_bytes += p0.steps * 4 * (12 * info["nnz"] + 4 * (M + 1)) + p0.steps * len(idx) * 80 * M
     # sequential plain solves: per-step time of one plain instance per N
     seq_time = 0.0
     per_N = {}
@@ -352,24 +371,27 @@ def batched_report(sb, torch, steps=200):
         per_N[N] = {"instances": len(idx), "steps_per_period": p0.steps_per_period, "plain_us_per_step": 1e6 * tstep,
                     "tile": tuned[g]["tile"], "rows_per_item": tuned[g]["rows_per_item"],
                     "path": tuned[g]["path"]}
-        seq_time += len(idx) * tstep
-    seq_rate = sum(len(idx) for (_, idx, _, _, _) in meta) / seq_time
-    total_20T = sum(len(idx) * p0.steps for (_, idx, _, _, p0) in meta)
-    log(f"batched: {batched_rate:.0f} instance-steps/s vs sequential plain {seq_rate:.0f}")
-    return {"workload": "dimer-batched-512 (N in {51,101,151,201,301}, A~U[0.5,3], gamma~logU[0.01,0.5]/N)",
-            "instances": len(inst), "steps_timed_per_group": steps,
-            "instance_steps_per_s": batched_rate, "ms_per_step_all_groups": 1e3 * el / steps,
-            "sequential_plain_instance_steps_per_s": seq_rate, "speedup_vs_sequential_plain": batched_rate / seq_rate,
-            "groups": per_N, "setup_s": setup_s,
-            "full_20_periods_instance_steps": total_20T,
-            "full_20_periods_estimated_s": total_20T / batched_rate}
+        seq_time += len(idx) * p0.steps * tstep
+    seq_rate = total / seq_time
+    log(f"batched: 20 periods in {el:.1f} s, {batched_rate:.0f} instance-steps/s vs sequential plain {seq_rate:.0f}; "
+        f"algorithmic {alg_bytes / el / 1e9:.0f} GB/s")
+    return {"workload": "dimer-batched-512 (N in {51,101,151,201,301}, A~U[0.5,3], gamma~logU[0.01,0.5]/N), "
+                        "20 periods",
+            "instances": len(inst), "instance_steps": total, "full_20_periods_s": el,
+            "instance_steps_per_s": batched_rate, "state_finite": finite,
+            "sequential_plain_instance_steps_per_s": seq_rate, "sequential_plain_20_periods_s_est": seq_time,
+            "speedup_vs_sequential_plain": batched_rate / seq_rate,
+            "roofline": {"bound": "hbm", "algorithmic_bytes": alg_bytes, "achieved": alg_bytes / el / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg_bytes / el / 1e9 / HBM_PEAK_GBS},
+            "groups": per_N, "setup_s": setup_s}
 
 
-def adjoint_report(sb, torch, periods=2, N=301, ckpt=None):
-    """Adjoint form at N (301: the adjoint workload; 1001: the plain one):
-    d<n1-n2>_(last period)/d(A, gamma, U) by the discrete adjoint, checkpoint
-    every `ckpt` steps (default: every period); time of gradient / time of
-    the forward objective."""
+def adjoint_report(sb, torch, periods=100, N=301, ckpt=None):
+    """Adjoint form at N (301: the adjoint workload over its full horizon of
+    100 periods with a checkpoint every period; 1001: the plain workload):
+    d<n1-n2>_(last period)/d(A, gamma, U) by the discrete adjoint on a
+    PyTorch workspace; time of the gradient over the time of the forward
+    objective (both warmed: layouts built, workspace allocated)."""
     import copy
     from workloads import dimer
     p = dimer.adjoint_config(N) if N == 301 else dimer.plain_config(N)
@@ -397,22 +419,96 @@ def adjoint_report(sb, torch, periods=2, N=301, ckpt=None):
     prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S, ckpt_every=ckpt)
     theta = np.array([p.A, p.gamma, p.U])
     adj, coef, dstatic, dcoef = prob._setup(theta)
-    adj.objective(prob.v0, coef, prob.cobs, p.dt, 16, 8)       # warm
+    full, low = adj.plan(dstatic, steps, ckpt)
+    ws = torch.empty(full, dtype=torch.uint8, device="cuda")
+    # warm: the forward objective and a short gradient (builds the reverse layout)
+    adj.objective(prob.v0, coef, prob.cobs, p.dt, 16, 8)
+    adj.run(prob.v0, coef, dstatic, dcoef, prob.cobs, p.dt, 16, 8, 8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     J_f = adj.objective(prob.v0, coef, prob.cobs, p.dt, steps, S)
     t_fwd = time.perf_counter() - t0
     t0 = time.perf_counter()
-    J, g = adj.run(prob.v0, coef, dstatic, dcoef, prob.cobs, p.dt, steps, S, ckpt)
+    J, g = adj.run(prob.v0, coef, dstatic, dcoef, prob.cobs, p.dt, steps, S, ckpt, workspace=ws)
     t_grad = time.perf_counter() - t0
-    log(f"adjoint N={N}: forward {t_fwd:.2f} s, gradient {t_grad:.2f} s, ratio {t_grad/t_fwd:.2f}")
+    log(f"adjoint N={N}: {periods} periods, forward {t_fwd:.2f} s, gradient {t_grad:.2f} s, "
+        f"ratio {t_grad/t_fwd:.2f}")
     return {"workload": f"dimer-adjoint-N{N} ({periods} periods x {p.steps_per_period} steps, checkpoint every "
                         f"{ckpt} steps, loss = <n1-n2> averaged over the last period, theta = (A, gamma, U))",
             "steps": steps, "J": J, "J_forward_only": J_f, "grad": {"A": g[0], "gamma": g[1], "U": g[2]},
             "forward_s": t_fwd, "gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
-            "forward_steps_per_s": steps / t_fwd,
-            "full_horizon_periods": p.periods,
-            "full_horizon_estimated_gradient_s": t_grad * (p.periods / periods)}
+            "forward_steps_per_s": steps / t_fwd, "workspace_bytes": full, "min_workspace_bytes": low}
+
+
+def dense_report(sb, torch, N=100):
+    """Random dense Lindbladian at N = 100 (the size of the paper's random
+    ensembles): dense assembly of a random Hermitian H and a random complex L
+    (dense sections + one matrix-core product for R), the product alone at
+    its shape (M x 2M by 2M x M) against the FP64 matrix peak, and the
+    stationary state of that generator."""
+    from workloads import random_ops
+    M = N * N - 1
+    H = random_ops.random_hermitian_csr(N, 1.0, seed=9001)
+    L = random_ops.random_complex_csr(N, 1.0, seed=9002)
+    basis = sb.build_basis(N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lind = sb.Lindbladian(basis, [H], [L], dense=True)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    g = torch.Generator(device="cuda").manual_seed(7)
+    X = torch.randn((M, 2 * M), dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.randn((2 * M, M), dtype=torch.float64, device="cuda", generator=g)
+    C = torch.empty((M, M), dtype=torch.float64, device="cuda")
+    sb.gemm_f64(X, Y, C, -0.5, 0.0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        sb.gemm_f64(X, Y, C, -0.5, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 2.0 * M * M * (2 * M)
+    tflops = flops / (ms / 1e3) / 1e12
+    del X, Y, C
+    torch.cuda.empty_cache()
+    prop = lind.propagator([1.0, 0.1], [])
+    t0 = time.perf_counter()
+    v, iters, relres = prop.stationary([], tau=5.0)
+    t_st = time.perf_counter() - t0
+    rho = basis.density(v)
+    ev = torch.linalg.eigvalsh(rho.cpu())
+    log(f"dense N={N}: assembly {t_asm:.2f} s, product {ms:.1f} ms = {tflops:.1f} TFLOP/s "
+        f"({100 * tflops / FP64_MFMA_PEAK_TFLOPS:.0f}% of FP64 peak); stationary {iters} it, {t_st:.2f} s")
+    return {"workload": f"random dense H and L at N={N} (M={M}), rate 0.1",
+            "assembly_s": t_asm, "nnz_R": lind.nnz("L", 0), "nnz_QH": lind.nnz("H", 0),
+            "roofline": {"bound": "mfma", "kernel": "k_gemm_f64", "shape": [M, M, 2 * M], "flops": flops,
+                         "ms": ms, "achieved": tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / FP64_MFMA_PEAK_TFLOPS},
+            "stationary": {"iterations": iters, "relres": relres, "seconds": t_st,
+                           "rho_min_eigenvalue": float(ev.min()), "rho_trace": float(rho.diagonal().real.sum())}}
+
+
+def stationary_report(sb, torch, Ns=(301, 1001)):
+    """Stationary state of the dimer generator at the static drive eps = E:
+    GMRES on the RK4 time-tau map (tau = 5), iterations, time and residual."""
+    from workloads import dimer
+    res = {}
+    for N in Ns:
+        p = dimer.plain_config(N)
+        ops = dimer.dimer_operators(p)
+        basis = sb.build_basis(N)
+        lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, iters, relres = prop.stationary([p.E], dt=p.dt, tau=5.0)
+        el = time.perf_counter() - t0
+        res[str(N)] = {"iterations": iters, "relres": relres, "seconds": el, "dt": p.dt,
+                       "steps_per_map": int(round(5.0 / p.dt))}
+        log(f"stationary N={N}: {iters} iterations, relres {relres:.1e}, {el:.2f} s")
+    return res
 
 
 def pmc_mode(sb, torch, steps, N=1001):
@@ -502,7 +598,13 @@ def main():
         print(json.dumps(batched_report(sb, torch)), flush=True)
         return
     if args.only == "adjoint":
-        print(json.dumps(adjoint_report(sb, torch, periods=1)), flush=True)
+        print(json.dumps(adjoint_report(sb, torch)), flush=True)
+        return
+    if args.only == "dense":
+        print(json.dumps(dense_report(sb, torch)), flush=True)
+        return
+    if args.only == "stationary":
+        print(json.dumps(stationary_report(sb, torch)), flush=True)
         return
     N = args.N
     p = dimer.plain_config(N)
@@ -603,13 +705,32 @@ def main():
         "state_finite": finite,
     }
 
-    # ---- batched and adjoint forms, reported against plain -----------------
+    # ---- the same stage kernel with the matrix streamed from HBM -----------
+    # (non-temporal loads keep it out of the memory-side cache between launches)
+    prop.tune_sliced(nontemporal=True)
+    vn = v0.clone()
+    prop.propagate(vn, eps, p.dt, 20)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    prop.propagate(vn, eps[2 * args.warmup:], p.dt, min(args.steps, 1000))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    nt_us = 1e3 * e0.elapsed_time(e1) / (4 * min(args.steps, 1000))
+    prop.tune_sliced()
+    out["roofline"]["hbm_sourced"] = {"avg_launch_us": nt_us, "achieved": bytes_per_launch / nt_us / 1e3,
+                                      "frac": bytes_per_launch / nt_us / 1e3 / HBM_PEAK_GBS,
+                                      "note": "same kernel with non-temporal matrix loads (stream from HBM)"}
+    log(f"stage kernel with the matrix from HBM: {nt_us:.2f} us ({bytes_per_launch / nt_us / 1e3:.0f} GB/s)")
+
+    # ---- further forms, reported against plain ------------------------------
     out["plain_other_configs"] = small_configs_report(sb, torch)
     out["general_drive"] = general_drive_report(sb, torch)
     out["batched"] = None if args.no_batched else batched_report(sb, torch)
     out["bifurcation"] = None if args.no_batched else bifurcation_report(sb, torch)
     out["adjoint"] = None if args.no_adjoint else adjoint_report(sb, torch)
     out["adjoint_N1001"] = None if args.no_adjoint else adjoint_report(sb, torch, periods=1, N=1001, ckpt=2048)
+    out["stationary"] = stationary_report(sb, torch)
+    out["dense"] = dense_report(sb, torch)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -655,6 +655,11 @@ void dense_rows(const sun_basis_s& b, const Expansion& e, const cplx* x, const c
   HIP_LAUNCH_OK();
 }
 
+// The dense path holds M x M arrays: limit it to M^2 < 2^33 entries (N < 300).
+void dense_require(int64_t M) {
+  SUN_REQUIRE(M * M < ((int64_t)1 << 33), SUN_ENOTSUP, "dense path limited to M^2 < 2^33 entries (N < 300)");
+}
+
 void dense_zero(double* a, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_fill, dim3(std::min<unsigned>(grid_for(n, 256), 65536)), dim3(256), 0, s, n, 0.0, a);
   HIP_LAUNCH_OK();
@@ -666,6 +671,7 @@ void assemble_hamiltonian_dense(const sun_basis_s& b, const sun_zcsr& H, DevCSR&
   SUN_REQUIRE(e.herm_dev <= 1e-12 * (e.maxabs > 0 ? e.maxabs : 1.0), SUN_EINVAL,
               "Hamiltonian term is not Hermitian");
   const int64_t M = b.M;
+  dense_require(M);
   DevBuf<double> Q((size_t)M * M);
   dense_zero(Q.get(), M * M, s);
   dense_rows<DM_REAL>(b, e, e.x.get(), e.xd.get(), cx(1.0), cx(0.0), Q.get(), M, s);
@@ -677,6 +683,7 @@ void assemble_dissipator_dense(const sun_basis_s& b, const sun_zcsr& L, DevCSR& 
   Expansion e;
   expand_operator(b, L, e, false, s);
   const int64_t M = b.M;
+  dense_require(M);
   const double tr = fmax(fabs(e.trace.re), fabs(e.trace.im));
   const bool gauge = tr > 1e-12 * b.N * (e.maxabs > 0 ? e.maxabs : 1.0);
   DevBuf<double> R((size_t)M * M);
@@ -774,9 +781,6 @@ int expand_impl(sun_basis b, const sun_zcsr* H, int32_t nH, const sun_zcsr* L, i
           assemble_dissipator_dense(*b, L[p], lind->R[p], lind->K[p], s);
         }
       };
-      if (mode >= 1) {
-        SUN_REQUIRE(b->M * b->M < (int64_t)INT32_MAX * 4, SUN_ENOTSUP, "dense path limited to M^2 < 2^33 entries");
-      }
       for (int a = 0; a < nH; ++a) ham(a);
       for (int p = 0; p < P; ++p) dis(p);
     } catch (...) {
