@@ -468,7 +468,9 @@ class BatchedPropagator:
         fits), 1 = one wavefront per (rows, tile) reading the matrix from
         global memory, 2 = path 0 with two instances per lane for every tile
         width, 3 = path 2 with the gathered state rows staged in LDS as well
-        (tiles 8, 16, 32)."""
+        (tiles 8, 16, 32). 4 = instance-major state on a
+        segmented sliced layout (tile = 2, 4 or 8 instances per wavefront;
+        needs 1 to 3 terms whose coefficients differ between instances)"""
         check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), int(path), _stream()))
 
     def info(self, g: int):

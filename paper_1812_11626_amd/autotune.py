@@ -17,14 +17,20 @@ import time
 
 import torch
 
+from ._lib import SunError
+
 TILES = (16, 32, 64, 128)
 ROWS = (32, 64, 128)
 # path 0: LDS-staged row blocks, one instance per lane below 128-instance
 # tiles; path 2: the same with two instances per lane for every tile width;
 # path 3: path 2 with the gathered state rows staged in LDS (tiles 8-32)
-PATHS = (0, 2, 3)
+# path 4: instance-major state on a segmented sliced layout, 4 or 8 instances
+# per wavefront (the tile value); rows_per_item does not apply
+PATHS = (0, 2, 3, 4)
 TILES3 = (8, 16, 32)
-UNIFORM = ((128, 64, 0), (128, 32, 0), (64, 64, 0), (16, 64, 2), (32, 64, 2), (16, 128, 3), (8, 128, 3))
+TILES4 = (4, 8)
+UNIFORM = ((128, 64, 0), (128, 32, 0), (64, 64, 0), (16, 64, 2), (32, 64, 2), (16, 128, 3), (8, 128, 3),
+           (4, 64, 4), (8, 64, 4))
 
 
 def cache_path() -> str:
@@ -53,12 +59,15 @@ def _save(path, data):
 
 def _key(G) -> str:
     name = torch.cuda.get_device_name(0).replace(" ", "_")
-    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4"
+    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4|p4"
 
 
 def _candidates(tiles, rows, paths):
     out = []
     for p in paths:
+        if p == 4:
+            out += [(t, 64, 4) for t in TILES4]
+            continue
         for t in (TILES3 if p == 3 else tiles):
             if p == 2 and t == 128:
                 continue               # 128-instance tiles are two per lane on path 0 already
@@ -85,7 +94,10 @@ def autotune_batched(bp, tiles=TILES, rows=ROWS, paths=PATHS, probe_steps: int =
         best = None
         steps = min(probe_steps, max(1, G["steps"]))
         for (t, r, p) in _candidates(tiles, rows, paths):
-            bp.tune(g, t, r, p)
+            try:
+                bp.tune(g, t, r, p)
+            except SunError:
+                continue                        # path 4 needs 1-3 instance-dependent terms
             bp.set_state(g, saved)
             bp.run(1, only_group=g)            # warm
             t0 = time.perf_counter()
@@ -111,11 +123,16 @@ def autotune_batched(bp, tiles=TILES, rows=ROWS, paths=PATHS, probe_steps: int =
         steps = min(probe_steps, max(1, min(G["steps"] for G in bp.groups)))
         cands = [[(chosen[g]["tile"], chosen[g]["rows_per_item"], chosen[g]["path"]) for g in range(len(bp.groups))]]
         cands += [[(t, r, p)] * len(bp.groups) for (t, r, p) in UNIFORM
-                  if (t in TILES3 if p == 3 else t in tiles) and p in paths]
+                  if (t in TILES3 if p == 3 else (t in TILES4 if p == 4 else t in tiles)) and p in paths]
         best = None
         for cand in cands:
-            for g, (t, r, p) in enumerate(cand):
-                bp.tune(g, t, r, p)
+            try:
+                for g, (t, r, p) in enumerate(cand):
+                    bp.tune(g, t, r, p)
+                    bp.set_state(g, saved[g])
+            except SunError:
+                continue
+            for g in range(len(bp.groups)):
                 bp.set_state(g, saved[g])
             bp.run(1)                                  # warm
             t0 = time.perf_counter()

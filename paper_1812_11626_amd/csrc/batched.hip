@@ -38,7 +38,7 @@
 #include <memory>
 #include <vector>
 
-#include "internal.hpp"
+#include "prop_internal.hpp"
 
 using namespace sun;
 
@@ -95,6 +95,16 @@ struct sun_batch_s {
   std::vector<int> xl;      // 1 when the group runs path 3
   std::vector<DevBuf<int>> xu_ptr, xu_col;
   std::vector<DevBuf<unsigned short>> xu_lidx;
+  // path 4: instance-major state ([B][M+1], grouped order, entry M = 1) on a
+  // segmented sliced layout of the group's generator (the terms whose
+  // coefficients differ between instances as segments, the rest merged)
+  std::vector<sun_prop> mprop;
+  std::vector<std::vector<int>> mterm;   // the segment terms
+  std::vector<DevBuf<double>> mv, mxa, mxb, macc;
+  ~sun_batch_s() {
+    for (sun_prop q : mprop)
+      if (q) sun_prop_free(q);
+  }
 };
 
 namespace {
@@ -164,6 +174,47 @@ __global__ void k_from_rowmajor(int M, int P, int B, int ld, const double* __res
 __global__ void k_b_fill(int64_t n, double v, double* __restrict__ a) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
+}
+
+// path 4 state (instance-major [B][ldv], grouped order, entry M = 1) from a
+// row-major stored state ([M+1][ld], interleaved order), and back
+__global__ void k_rm_to_im(int M, int P, int B, int ld, int64_t ldv, const double* __restrict__ src,
+                           double* __restrict__ dst) {
+  const int64_t total = (int64_t)B * (M + 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(i / (M + 1)), r = (int)(i % (M + 1));
+    dst[(int64_t)b * ldv + r] = r < M ? src[inter(r, P) * ld + b] : 1.0;
+  }
+}
+
+__global__ void k_im_to_rm(int M, int P, int B, int ld, int64_t ldv, const double* __restrict__ src,
+                           double* __restrict__ dst) {
+  const int64_t total = (int64_t)M * ld;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(i / ld), b = (int)(i % ld);
+    dst[inter(r, P) * ld + b] = b < B ? src[(int64_t)b * ldv + r] : 0.0;
+  }
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < ld; b += (int64_t)gridDim.x * blockDim.x)
+    dst[(int64_t)M * ld + b] = 1.0;
+}
+
+// instance-major [B][M] caller layout <-> path 4 state [B][ldv] (entry M = 1)
+__global__ void k_to_im(int M, int B, int64_t ldv, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t total = (int64_t)B * (M + 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / (M + 1);
+    const int r = (int)(i % (M + 1));
+    dst[b * ldv + r] = r < M ? src[b * M + r] : 1.0;
+  }
+}
+
+__global__ void k_from_im(int M, int B, int64_t ldv, const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t total = (int64_t)B * M;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / M;
+    const int r = (int)(i % M);
+    dst[i] = src[b * ldv + r];
+  }
 }
 
 // One RK4 stage for every active group.  stage_in/stage_out select the
@@ -701,10 +752,14 @@ void refresh_items(sun_batch_s& bt) {
     G.ld = bt.ld[g];
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
     G.tiles = (G.B + G.tile * G.vec - 1) / (G.tile * G.vec);
+    if (bt.path[g] == 4) {   // advanced by the multi-instance sliced kernel instead
+      G.row_blocks = 0;
+      G.tiles = 0;
+    }
   }
   for (int gi : bt.order) {
     GroupDev& G = bt.ghost[gi];
-    G.nblk = bt.nblk[gi];
+    G.nblk = bt.path[gi] == 4 ? 0 : bt.nblk[gi];
     G.blk_row = bt.blk_row[gi].get();
     G.item0 = item;
     if (G.nblk == 0) item += (int64_t)G.row_blocks * G.tiles;
@@ -718,6 +773,14 @@ void repartition(sun_batch_s& bt, int g) {
   const int max_rows = std::min(bt.rows_per_item[g], kLdsRows);
   std::vector<int> blk;
   bt.xl[g] = 0;
+  if (bt.path[g] == 4) {
+    bt.xu_ptr[g].release();
+    bt.xu_col[g].release();
+    bt.xu_lidx[g].release();
+    bt.nblk[g] = 0;
+    bt.blk_row[g].release();
+    return;
+  }
   if (bt.path[g] == 3) {
     std::vector<int> hcol(bt.nnz[g]);
     if (bt.nnz[g] > 0)
@@ -779,6 +842,72 @@ void alloc_state(sun_batch_s& bt, int g, hipStream_t s) {
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Path 4 set-up: classify the terms (a term is merged into the static part
+// when every instance has the same constant coefficient, u = 0 and equal w),
+// build the segmented sliced layout of the others (1 to 3 segments) and the
+// instance-major state buffers.
+void setup_multi(sun_batch_s& bt, int g, hipStream_t s) {
+  if (bt.mprop[g]) return;
+  const int nt = bt.nt[g], B = bt.B[g];
+  std::vector<double> hw((size_t)B * nt), hu((size_t)B * nt);
+  HIP_OK(hipMemcpy(hw.data(), bt.w[g], hw.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(hu.data(), bt.u[g], hu.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> static_w(nt, 0.0);
+  std::vector<int> dyn;
+  for (int a = 0; a < nt; ++a) {
+    bool same = true;
+    for (int b = 0; b < B && same; ++b) same = hu[(size_t)b * nt + a] == 0.0 && hw[(size_t)b * nt + a] == hw[a];
+    if (same) static_w[a] = hw[a];
+    else dyn.push_back(a);
+  }
+  SUN_REQUIRE(!dyn.empty() && (int)dyn.size() <= kMaxRevSeg, SUN_ENOTSUP,
+              "path 4 needs 1 to 3 terms whose coefficients differ between instances");
+  for (int a = bt.lind[g]->nH; a < nt; ++a)
+    SUN_REQUIRE(static_w[a] >= 0.0, SUN_EINVAL, "dissipation rates must be >= 0");
+  sun_prop q = nullptr;
+  const int st = sun_prop_create(const_cast<sun_lind_s*>(bt.lind[g]), static_w.data(), dyn.data(), (int)dyn.size(), s, &q);
+  if (st != SUN_OK) SUN_THROW(st, std::string("path 4 layout: ") + sun_last_error());
+  try {
+    prop_build_segments(*q, s);
+  } catch (...) {
+    sun_prop_free(q);
+    throw;
+  }
+  q->layout = 2;
+  q->resident = 0;
+  bt.mprop[g] = q;
+  bt.mterm[g] = dyn;
+  const int64_t n = (int64_t)B * (bt.M[g] + 1);
+  for (DevBuf<double>* b : {&bt.mv[g], &bt.mxa[g], &bt.mxb[g], &bt.macc[g]}) {
+    b->alloc(n);
+    hipLaunchKernelGGL(k_b_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, n, 1.0, b->get());
+    HIP_LAUNCH_OK();
+  }
+}
+
+// One RK4 stage of every active path-4 group.
+template <int STAGE>
+void launch_multi(sun_batch_s& bt, const std::vector<int>& groups, const int64_t* stepidx, hipStream_t s) {
+  for (int g : groups) {
+    const sun_prop_s& p = *bt.mprop[g];
+    MultiCoef mc;
+    mc.w = bt.w[g];
+    mc.u = bt.u[g];
+    mc.wave = bt.wave[g];
+    mc.widx = 2 * stepidx[g] + (STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1));
+    mc.nt = bt.nt[g];
+    for (int d = 0; d < (int)bt.mterm[g].size(); ++d) mc.term[d] = bt.mterm[g][d];
+    mc.B = bt.B[g];
+    mc.ldv = bt.M[g] + 1;
+    double* v = bt.mv[g].get();
+    double* xa = bt.mxa[g].get();
+    double* xb = bt.mxb[g].get();
+    const double* xin = STAGE == 0 ? v : (STAGE == 1 ? xa : (STAGE == 2 ? xb : xa));
+    double* xout = STAGE == 0 ? xa : (STAGE == 1 ? xb : (STAGE == 2 ? xa : v));
+    prop_stage_multi(p, STAGE, xin, v, bt.macc[g].get(), xout, mc, bt.tile[g], bt.dt[g], s);
+  }
+}
 
 // One RK4 stage over all active groups: the per-wavefront kernel, the LDS
 // kernels (one or two instances per lane) and the path-3 kernel, each
@@ -855,6 +984,12 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->xu_ptr.resize(ngroups);
       bt->xu_col.resize(ngroups);
       bt->xu_lidx.resize(ngroups);
+      bt->mprop.assign(ngroups, nullptr);
+      bt->mterm.resize(ngroups);
+      bt->mv.resize(ngroups);
+      bt->mxa.resize(ngroups);
+      bt->mxb.resize(ngroups);
+      bt->macc.resize(ngroups);
       for (int g = 0; g < ngroups; ++g) {
         const sun_lind_s* l = lind[g];
         SUN_REQUIRE(l != nullptr, SUN_EINVAL, "group system is NULL");
@@ -938,6 +1073,14 @@ extern "C" int sun_batch_set_state(sun_batch bt, int32_t g, const double* V, voi
     SUN_REQUIRE(bt != nullptr && V != nullptr, SUN_EINVAL, "NULL argument");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
     hipStream_t s = as_stream(stream);
+    if (bt->path[g] == 4) {
+      const int64_t total = (int64_t)bt->B[g] * (bt->M[g] + 1);
+      hipLaunchKernelGGL(k_to_im, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g], bt->B[g],
+                         bt->M[g] + 1, V, bt->mv[g].get());
+      HIP_LAUNCH_OK();
+      bt->done[g] = 0;
+      return;
+    }
     const int64_t total = (bt->M[g] + 1) * bt->ld[g];
     hipLaunchKernelGGL(k_to_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g],
                        bt->P[g], bt->B[g],
@@ -953,6 +1096,12 @@ extern "C" int sun_batch_get_state(sun_batch bt, int32_t g, double* V, void* str
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
     hipStream_t s = as_stream(stream);
     const int64_t total = bt->M[g] * bt->B[g];
+    if (bt->path[g] == 4) {
+      hipLaunchKernelGGL(k_from_im, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g], bt->B[g],
+                         bt->M[g] + 1, bt->mv[g].get(), V);
+      HIP_LAUNCH_OK();
+      return;
+    }
     hipLaunchKernelGGL(k_from_rowmajor, dim3(grid_for(total, 256)), dim3(256), 0, s, (int)bt->M[g],
                        bt->P[g], bt->B[g],
                        bt->ld[g], bt->v[g].get(), V);
@@ -965,13 +1114,32 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
   return guarded([&] {
     SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
-    SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
-                "tile must be 8, 16, 32, 64 or 128");
+    SUN_REQUIRE(path >= 0 && path <= 4, SUN_EINVAL, "path must be 0, 1, 2, 3 or 4");
+    if (path == 4) {
+      SUN_REQUIRE(tile == 2 || tile == 4 || tile == 8, SUN_EINVAL, "path 4 takes 2, 4 or 8 instances per wavefront");
+    } else {
+      SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
+                  "tile must be 8, 16, 32, 64 or 128");
+    }
     SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= 65536, SUN_EINVAL, "rows_per_item out of range");
-    SUN_REQUIRE(path >= 0 && path <= 3, SUN_EINVAL, "path must be 0, 1, 2 or 3");
     SUN_REQUIRE(path != 3 || tile == 8 || tile == 16 || tile == 32, SUN_EINVAL, "path 3 takes tiles 8, 16 or 32");
     hipStream_t s = as_stream(stream);
     HIP_OK(hipStreamSynchronize(s));
+    if (path == 4) setup_multi(*bt, g, s);
+    // the state moves with the layout
+    const int old = bt->path[g];
+    const int M = (int)bt->M[g];
+    if (old != 4 && path == 4) {
+      const int64_t total = (int64_t)bt->B[g] * (M + 1);
+      hipLaunchKernelGGL(k_rm_to_im, dim3(grid_for(total, 256)), dim3(256), 0, s, M, bt->P[g], bt->B[g], bt->ld[g],
+                         (int64_t)M + 1, bt->v[g].get(), bt->mv[g].get());
+      HIP_LAUNCH_OK();
+    } else if (old == 4 && path != 4) {
+      const int64_t total = (int64_t)M * bt->ld[g];
+      hipLaunchKernelGGL(k_im_to_rm, dim3(grid_for(total, 256)), dim3(256), 0, s, M, bt->P[g], bt->B[g], bt->ld[g],
+                         (int64_t)M + 1, bt->mv[g].get(), bt->v[g].get());
+      HIP_LAUNCH_OK();
+    }
     bt->tile[g] = tile;
     bt->rows_per_item[g] = rows_per_item;
     bt->path[g] = path;
@@ -1060,10 +1228,20 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       L.gd = bt->gdev.get();
       L.go = gorder.get();
       L.s = s;
+      // path-4 groups advanced this step, with their absolute step index
+      std::vector<int> multi;
+      for (int q = 0; q < nactive; ++q)
+        if (bt->path[ord[q]] == 4) multi.push_back(ord[q]);
+      std::vector<int64_t> sidx(bt->ngroups, 0);
+      for (int g : multi) sidx[g] = bt->done[g] + n;
       launch_stage<0>(L);
+      launch_multi<0>(*bt, multi, sidx.data(), s);
       launch_stage<1>(L);
+      launch_multi<1>(*bt, multi, sidx.data(), s);
       launch_stage<2>(L);
+      launch_multi<2>(*bt, multi, sidx.data(), s);
       launch_stage<3>(L);
+      launch_multi<3>(*bt, multi, sidx.data(), s);
     }
     HIP_LAUNCH_OK();
     for (int g = 0; g < bt->ngroups; ++g) bt->done[g] += todo[g];
@@ -1072,7 +1250,10 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     DevBuf<int> bad(1);
     set_int(bad.get(), 0, s);
     for (int g = 0; g < bt->ngroups; ++g)
-      if (todo[g] > 0) flag_nonfinite(bt->v[g].get(), (bt->M[g] + 1) * bt->ld[g], bad.get(), s);
+      if (todo[g] > 0) {
+        if (bt->path[g] == 4) flag_nonfinite(bt->mv[g].get(), (int64_t)bt->B[g] * (bt->M[g] + 1), bad.get(), s);
+        else flag_nonfinite(bt->v[g].get(), (bt->M[g] + 1) * bt->ld[g], bad.get(), s);
+      }
     int h = 0;
     HIP_OK(hipMemcpyAsync(&h, bad.get(), sizeof(int), hipMemcpyDeviceToHost, s));
     // the step table and group order are freed on return

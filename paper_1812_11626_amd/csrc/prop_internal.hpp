@@ -123,6 +123,23 @@ void prop_build_segments(sun_prop_s& p, hipStream_t s);
 int64_t prop_rev_slots(const sun_prop_s& p);
 void prop_stage_dot(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
                     const double* xdot, const RevDot& rd, int64_t krow, double dt, hipStream_t s);
+// Per-instance coefficients of the time-dependent segments for the
+// multi-instance stage: c_{b,d} = w[b * nt + term[d]] + u[b * nt + term[d]] * wave[widx].
+struct MultiCoef {
+  const double* w = nullptr;
+  const double* u = nullptr;
+  const double* wave = nullptr;
+  int64_t widx = 0;
+  int nt = 0;
+  int term[kMaxRevSeg] = {};
+  int B = 0;          // instances
+  int64_t ldv = 0;    // stride between instance vectors (>= M + 1)
+};
+// One forward RK4 stage (0..3) for B instance vectors (instance-major, stride
+// mc.ldv, entry M = 1) on the segmented sliced layout (layout 2, ndyn =
+// number of segments), ki = 2, 4 or 8 instances per wavefront.
+void prop_stage_multi(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc,
+                      double* xout, const MultiCoef& mc, int ki, double dt, hipStream_t s);
 // Forward stage 0..3 on the segmented sliced layout (layout 2: 2-3
 // time-dependent terms, segment d with coefficient coef[row * ndyn + d]).
 void prop_seg_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,

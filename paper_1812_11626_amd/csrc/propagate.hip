@@ -929,6 +929,175 @@ __global__ __launch_bounds__(256) void k_sell_seg(
 }
 
 // ---------------------------------------------------------------------------
+// Several instances on one segmented sliced layout (the batched form's
+// instance-major path).  KI instance vectors (each M+1 doubles, stride ldv,
+// entry M = 1) are advanced by one RK4 stage with per-instance coefficients
+// of the ND time-dependent segments, c_{b,d} = w[b][term_d] + u[b][term_d] *
+// wave(t); the static segment carries the weights every instance shares.
+// One wavefront takes one slice (or long row) for one chunk of KI instances;
+// the chunks of a slice are consecutive wavefronts, so the slice's matrix
+// data is read from HBM once and served from L2 to the others.  Every
+// instance's row sums are formed exactly as k_sell_seg forms them for one
+// vector (same segments, same order), so each instance gets the bits of a
+// plain propagation with its own coefficients.
+// ---------------------------------------------------------------------------
+template <class T, int U, int ND, int KI>
+__device__ inline void slice_row_segs_multi(const unsigned char* cb, const int* __restrict__ gbase,
+                                            const double* __restrict__ vp, int wd, int lane, const int* b,
+                                            const double* const* xs, double (*a)[KI]) {
+#pragma unroll
+  for (int q = 0; q <= ND; ++q)
+#pragma unroll
+    for (int i = 0; i < KI; ++i) a[q][i] = 0.0;
+  int k = 0;
+  for (; k + U <= wd; k += U) {
+    int ci[U];
+    double cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ci[u] = gbase[k + u] + load_delta<T, false>(cb, (int64_t)(k + u) * kSlice + lane);
+      cv[u] = vp[(int64_t)(k + u) * kSlice];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double xv[KI];
+#pragma unroll
+      for (int i = 0; i < KI; ++i) xv[i] = xs[i][ci[u]];
+#pragma unroll
+      for (int i = 0; i < KI; ++i) {
+        const double pr = cv[u] * xv[i];
+#pragma unroll
+        for (int q = 0; q <= ND; ++q) a[q][i] += (k + u >= b[q] && k + u < b[q + 1]) ? pr : 0.0;
+      }
+    }
+  }
+  for (; k < wd; ++k) {
+    const int c = gbase[k] + load_delta<T, false>(cb, (int64_t)k * kSlice + lane);
+    const double cvk = vp[(int64_t)k * kSlice];
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+      const double pr = cvk * xs[i][c];
+#pragma unroll
+      for (int q = 0; q <= ND; ++q) a[q][i] += (k >= b[q] && k < b[q + 1]) ? pr : 0.0;
+    }
+  }
+}
+
+template <int STAGE, int ND, int KI>
+__global__ __launch_bounds__(256) void k_sell_multi(
+    const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
+    const unsigned char* __restrict__ cb_all, const int* __restrict__ sell_row, const int* __restrict__ sell_len,
+    const int* __restrict__ sell_seg, const double* __restrict__ sval, int64_t nslices, int64_t nshort,
+    const int* __restrict__ long_rows, int64_t nlong, const int* __restrict__ rowptr, const int* __restrict__ seg,
+    const int* __restrict__ col, const double* __restrict__ val, int64_t M, MultiCoef mc, const double* xin,
+    const double* v, double* acc, double* xout, double dt, int xcd_remap) {
+  const int lane = threadIdx.x & 63;
+  int64_t blk = blockIdx.x;
+  if (xcd_remap) {
+    const int64_t q = ((int64_t)gridDim.x + 7) >> 3;
+    blk = (blk & 7) * q + (blk >> 3);
+  }
+  const int64_t gw = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nch = (mc.B + KI - 1) / KI;
+  const int64_t wid = gw / nch;
+  const int ch = (int)(gw % nch);
+  if (wid >= nslices + nlong) return;
+  // this chunk's instances (the last chunk repeats its last instance in the
+  // unused slots, which are computed but not stored)
+  const double* xs[KI];
+  int bi[KI];
+  double cseg[ND][KI];
+  const double ph = mc.wave[mc.widx];
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int bb = min(ch * KI + i, mc.B - 1);
+    bi[i] = bb;
+    xs[i] = xin + (int64_t)bb * mc.ldv;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      cseg[d][i] = mc.w[(int64_t)bb * mc.nt + mc.term[d]] + mc.u[(int64_t)bb * mc.nt + mc.term[d]] * ph;
+  }
+  if (wid < nslices) {
+    const int64_t i = wid * kSlice + lane;
+    const int off = __builtin_amdgcn_readfirstlane(sell_off[wid]);
+    const int wd = (__builtin_amdgcn_readfirstlane(sell_off[wid + 1]) - off) / kSlice;
+    const int coff = __builtin_amdgcn_readfirstlane(sell_coff[wid]);
+    const bool own = i < nshort;
+    const int r = own ? sell_row[i] : 0;
+    const int lens = sell_len[i];
+    const int packed = sell_seg[i];
+    int b[ND + 2];
+    b[0] = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) b[d + 1] = (packed >> (8 * d)) & 255;
+    b[ND + 1] = lens >> 16;
+    const unsigned char* cb = cb_all + (coff & ~63);
+    const int* gbase = gbase_all + off / kSlice;
+    const double* vp = sval + off + lane;
+    double a[ND + 1][KI];
+    switch (coff & 3) {
+      case 0: slice_row_segs_multi<uint8_t, 4, ND, KI>(cb, gbase, vp, wd, lane, b, xs, a); break;
+      case 1: slice_row_segs_multi<uint16_t, 4, ND, KI>(cb, gbase, vp, wd, lane, b, xs, a); break;
+      default: slice_row_segs_multi<uint32_t, 4, ND, KI>(cb, gbase, vp, wd, lane, b, xs, a); break;
+    }
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < KI; ++q) {
+        if (ch * KI + q >= mc.B) break;
+        const int64_t o = (int64_t)bi[q] * mc.ldv;
+        double kk = a[0][q];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) kk += cseg[d][q] * a[d + 1][q];
+        const double vr = v[o + r];
+        const double ar = reads_acc<STAGE>() ? acc[o + r] : 0.0;
+        stage_store<STAGE>(r, kk, vr, ar, acc + o, xout + o, dt);
+      }
+    }
+  } else {
+    const int r = long_rows[wid - nslices];
+    const int e0 = rowptr[r], e1 = rowptr[r + 1];
+    int b[ND + 2];
+    b[0] = e0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) b[d + 1] = seg[(int64_t)d * M + r];
+    b[ND + 1] = e1;
+    double a[ND + 1][KI];
+#pragma unroll
+    for (int q = 0; q <= ND; ++q)
+#pragma unroll
+      for (int i = 0; i < KI; ++i) a[q][i] = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      const double ve = val[e];
+      const int ce = col[e];
+#pragma unroll
+      for (int i = 0; i < KI; ++i) {
+        const double pr = ve * xs[i][ce];
+#pragma unroll
+        for (int q = 0; q <= ND; ++q) a[q][i] += (e >= b[q] && e < b[q + 1]) ? pr : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q <= ND; ++q)
+#pragma unroll
+      for (int i = 0; i < KI; ++i)
+        for (int o = 32; o > 0; o >>= 1) a[q][i] += __shfl_down(a[q][i], o, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < KI; ++q) {
+        if (ch * KI + q >= mc.B) break;
+        const int64_t o = (int64_t)bi[q] * mc.ldv;
+        double kk = a[0][q];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) kk += cseg[d][q] * a[d + 1][q];
+        const double vr = v[o + r];
+        const double ar = reads_acc<STAGE>() ? acc[o + r] : 0.0;
+        stage_store<STAGE>(r, kk, vr, ar, acc + o, xout + o, dt);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Resident path for small systems: one workgroup keeps v, two stage vectors
 // and the accumulator ((M+1) doubles each, entry M = 1) in LDS and runs every
 // RK4 step of a call in one launch, so small N is not bound by four launches
@@ -1280,6 +1449,52 @@ void prop_build_segments(sun_prop_s& p, hipStream_t s) {
 }
 
 int64_t prop_rev_slots(const sun_prop_s& p) { return p.nslices + p.nlong; }
+
+template <int STAGE, int ND, int KI>
+void launch_sell_multi(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                       const MultiCoef& mc, double dt, hipStream_t s) {
+  const int64_t waves = (p.nslices + p.nlong) * ((mc.B + KI - 1) / KI);
+  if (waves == 0) return;
+  unsigned grid = (unsigned)((waves + 3) / 4);
+  if (p.sell_remap) grid = (grid + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_sell_multi<STAGE, ND, KI>), dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
+                     p.sell_base.get(), p.sell_cb.get(), p.sell_row.get(), p.sell_len.get(), p.sell_seg.get(),
+                     p.sell_val.get(), p.nslices, p.nshort, p.long_rows.get(), p.nlong, p.rowptr.get(), p.seg.get(),
+                     p.col.get(), p.val.get(), p.M, mc, xin, vin, acc, xout, dt, p.sell_remap);
+}
+
+template <int STAGE, int ND>
+void launch_sell_multi_ki(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                          const MultiCoef& mc, int ki, double dt, hipStream_t s) {
+  switch (ki) {
+    case 2: launch_sell_multi<STAGE, ND, 2>(p, xin, vin, acc, xout, mc, dt, s); break;
+    case 4: launch_sell_multi<STAGE, ND, 4>(p, xin, vin, acc, xout, mc, dt, s); break;
+    default: launch_sell_multi<STAGE, ND, 8>(p, xin, vin, acc, xout, mc, dt, s); break;
+  }
+}
+
+template <int STAGE>
+void launch_sell_multi_nd(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,
+                          const MultiCoef& mc, int ki, double dt, hipStream_t s) {
+  switch (p.ndyn) {
+    case 1: launch_sell_multi_ki<STAGE, 1>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+    case 2: launch_sell_multi_ki<STAGE, 2>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+    default: launch_sell_multi_ki<STAGE, 3>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+  }
+}
+
+void prop_stage_multi(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc,
+                      double* xout, const MultiCoef& mc, int ki, double dt, hipStream_t s) {
+  SUN_REQUIRE(p.layout == 2 && p.sell_segs == p.ndyn && p.ndyn >= 1 && p.ndyn <= kMaxRevSeg, SUN_EINVAL,
+              "the multi-instance stage needs the segmented sliced layout");
+  switch (stage) {
+    case 0: launch_sell_multi_nd<0>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+    case 1: launch_sell_multi_nd<1>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+    case 2: launch_sell_multi_nd<2>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+    default: launch_sell_multi_nd<3>(p, xin, vin, acc, xout, mc, ki, dt, s); break;
+  }
+  HIP_LAUNCH_OK();
+}
 
 template <int STAGE, bool DOTS>
 void launch_sell_seg(const sun_prop_s& p, const double* xin, const double* vin, double* acc, double* xout,

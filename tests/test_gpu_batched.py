@@ -183,3 +183,54 @@ def test_bifurcation_scan_against_plain_and_oracle(lib):
     rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"]], [q.gamma_eff], rho0,
                      dimer.drive_table(q, steps=steps)[:, None], q.dt, steps)
     assert rel_vec_err(P[7], np.real(np.diag(rho))) <= TOL
+
+
+def test_instance_major_path_against_oracle_and_other_paths(lib):
+    """Path 4 (instance-major state on a segmented sliced layout: H0 merged,
+    the drive and the per-instance rate as segments): every instance of the
+    small groups against the dense oracle (1e-12), the other paths (1e-12;
+    the row sums are grouped differently, so not bitwise), and path 4 with 2,
+    4 and 8 instances per wavefront bitwise equal to each other."""
+    flush("[batched] path 4 vs oracle and the row-major paths")
+    inst = _small_instances()
+    steps = {4: 60, 5: 40}
+    bp, groups = dimer_batch(lib, inst, steps)
+    starts = [torch.as_tensor(np.stack([fock_bloch(N, j % N) for j in range(len(idx))]))
+              for (N, idx, _, _, _) in groups]
+    res = {}
+    for key, (tile, rows, path) in {"p0": (64, 64, 0), "p4k2": (2, 64, 4), "p4k4": (4, 64, 4),
+                                    "p4k8": (8, 64, 4)}.items():
+        for g in range(len(groups)):
+            bp.tune(g, tile, rows, path)
+            bp.set_state(g, starts[g])
+        bp.run(1000)
+        res[key] = [bp.get_state(g).cpu().numpy() for g in range(len(groups))]
+    for g, (N, idx, _, _, st) in enumerate(groups):
+        for j, i in enumerate(idx):
+            want = _oracle_instance(inst[i], st, fock_bloch(N, j % N))
+            assert rel_vec_err(res["p4k4"][g][j], want) <= TOL, (N, j)
+            assert rel_vec_err(res["p4k4"][g][j], res["p0"][g][j]) <= TOL
+    for key in ("p4k2", "p4k8"):
+        for a, b in zip(res[key], res["p4k4"]):
+            assert np.array_equal(a, b)
+
+
+def test_instance_major_path_switch_keeps_state(lib):
+    """Switching a group between the row-major paths and path 4 in the middle
+    of a run moves its state with it: 20 steps on path 0, 20 on path 4, 20 on
+    path 2 equal 60 steps on path 0 (1e-12)."""
+    inst = dimer.batched_instances(count=12, sizes=(21,), periods=1)
+    bp, groups = dimer_batch(lib, inst, steps={21: 60})
+    start = torch.as_tensor(np.stack([fock_bloch(21, 0)] * len(groups[0][1])))
+    bp.tune(0, 64, 64, 0)
+    bp.set_state(0, start)
+    bp.run(60)
+    ref = bp.get_state(0).cpu().numpy()
+    bp.set_state(0, start)
+    bp.run(20)
+    bp.tune(0, 8, 64, 4)
+    bp.run(20)
+    bp.tune(0, 16, 64, 2)
+    bp.run(20)
+    got = bp.get_state(0).cpu().numpy()
+    assert rel_vec_err(got, ref) <= TOL
