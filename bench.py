@@ -50,6 +50,8 @@ def parse():
                     help="run one leg only (for profiling); prints that leg's report")
     ap.add_argument("--scan", action="store_true",
                     help="assembly time and RK4 steps/s of the plain workload over a range of N (one JSON line)")
+    ap.add_argument("--pmc-target", choices=("plain", "batched", "adjoint", "gemm"), default="plain",
+                    help="workload of --pmc-mode")
     ap.add_argument("--pmc-mode", action="store_true",
                     help="short run for rocprofv3 --pmc (stage kernel + calibration copy)")
     return ap.parse_args()
@@ -386,18 +388,12 @@ def batched_report(sb, torch):
             "groups": per_N, "setup_s": setup_s}
 
 
-def adjoint_report(sb, torch, periods=100, N=301, ckpt=None):
-    """Adjoint form at N (301: the adjoint workload over its full horizon of
-    100 periods with a checkpoint every period; 1001: the plain workload):
-    d<n1-n2>_(last period)/d(A, gamma, U) by the discrete adjoint on a
-    PyTorch workspace; time of the gradient over the time of the forward
-    objective (both warmed: layouts built, workspace allocated)."""
+def _adjoint_problem(sb, N, steps, S, ckpt):
+    """AdjointProblem of the dimer (terms H_J, H_U, H1, L; theta = (A, gamma,
+    U)) at N (301: the adjoint workload, otherwise the plain one)."""
     import copy
     from workloads import dimer
     p = dimer.adjoint_config(N) if N == 301 else dimer.plain_config(N)
-    steps = periods * p.steps_per_period
-    S = p.steps_per_period
-    ckpt = S if ckpt is None else ckpt
     ops = dimer.dimer_operators(p)
     basis = sb.build_basis(p.N)
     lind = sb.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"]], [ops["L"]])
@@ -417,6 +413,21 @@ def adjoint_report(sb, torch, periods=100, N=301, ckpt=None):
                     coef=dimer.drive_table(q, steps=steps)[:, None], dstatic=dstatic, dcoef=dcoef)
 
     prob = sb.AdjointProblem(lind, pmap, v0, cobs, p.dt, steps, S, ckpt_every=ckpt)
+    return prob, p
+
+
+def adjoint_report(sb, torch, periods=100, N=301, ckpt=None):
+    """Adjoint form at N (301: the adjoint workload over its full horizon of
+    100 periods with a checkpoint every period; 1001: the plain workload):
+    d<n1-n2>_(last period)/d(A, gamma, U) by the discrete adjoint on a
+    PyTorch workspace; time of the gradient over the time of the forward
+    objective (both warmed: layouts built, workspace allocated)."""
+    from workloads import dimer
+    p0 = dimer.adjoint_config(N) if N == 301 else dimer.plain_config(N)
+    steps = periods * p0.steps_per_period
+    S = p0.steps_per_period
+    ckpt = S if ckpt is None else ckpt
+    prob, p = _adjoint_problem(sb, N, steps, S, ckpt)
     theta = np.array([p.A, p.gamma, p.U])
     adj, coef, dstatic, dcoef = prob._setup(theta)
     full, low = adj.plan(dstatic, steps, ckpt)
@@ -511,26 +522,80 @@ def stationary_report(sb, torch, Ns=(301, 1001)):
     return res
 
 
-def pmc_mode(sb, torch, steps, N=1001):
-    """Short run for hardware-counter collection: the stage kernel on the
-    plain workload (N = 1001 unless --N says otherwise), then a plain 512 MiB
-    device copy (known size) that calibrates the byte counters."""
-    from workloads import dimer
-    p = dimer.plain_config(N)
-    p.steps_per_period = max(p.steps_per_period, dimer.stable_steps_per_period(N, p.E + p.A))
-    ops = dimer.dimer_operators(p)
-    basis = sb.build_basis(N)
-    lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
-    v = _fock_v0(sb, basis, N)
-    eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
-    prop.propagate(v, eps, p.dt, steps)
+def _calibration_copy(torch):
+    """Three plain 512 MiB device copies (known bytes) that calibrate the
+    byte counters of a profiled run."""
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_mode": True, "steps": steps, "copy_bytes_read": a.numel() * 8,
-                      "copy_bytes_written": b.numel() * 8, "layout": prop.layout()}), flush=True)
+    return a.numel() * 8
+
+
+def pmc_mode(sb, torch, steps, N=1001, target="plain"):
+    """Short runs for profiling, each followed by the calibration copy:
+      plain   -- the stage kernel on the plain workload (N = 1001 unless --N
+                 says otherwise), `steps` RK4 steps;
+      batched -- the 512-instance workload with its autotuned tiling (from the
+                 autotuner's cache when a previous run filled it; then no
+                 probe launches run), 3 RK4 steps of every group;
+      adjoint -- the adjoint workload N = 301, 8 steps with a checkpoint every
+                 4 (forward and fused reverse stages);
+      gemm    -- the dense path's product at N = 100 (9,999 x 19,998 by
+                 19,998 x 9,999), once."""
+    from workloads import dimer
+    info = {"pmc_mode": True, "target": target}
+    if target == "plain":
+        p = dimer.plain_config(N)
+        p.steps_per_period = max(p.steps_per_period, dimer.stable_steps_per_period(N, p.E + p.A))
+        ops = dimer.dimer_operators(p)
+        basis = sb.build_basis(N)
+        lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+        v = _fock_v0(sb, basis, N)
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+        prop.propagate(v, eps, p.dt, steps)
+        info.update(steps=steps, layout=prop.layout())
+    elif target == "batched":
+        inst = dimer.batched_instances()
+        byN = {}
+        for i, q in enumerate(inst):
+            byN.setdefault(q.N, []).append(i)
+        specs, starts = [], []
+        for Ng in sorted(byN):
+            idx = byN[Ng]
+            p0 = inst[idx[0]]
+            ops = dimer.dimer_operators(p0)
+            basis = sb.build_basis(Ng)
+            lind = sb.Lindbladian(basis, [ops["H0"], ops["H1"]], [ops["L"]])
+            specs.append(dict(lind=lind, w=np.array([[1.0, inst[i].E, inst[i].gamma_eff] for i in idx]),
+                              u=np.array([[0.0, inst[i].A, 0.0] for i in idx]), wave=dimer.drive_table_dA(p0),
+                              dt=p0.dt, steps=p0.steps))
+            starts.append(_fock_v0(sb, basis, Ng).unsqueeze(0).repeat(len(idx), 1))
+        bp = sb.BatchedPropagator(specs)
+        for g, st in enumerate(starts):
+            bp.set_state(g, st)
+        tuned = sb.autotune_batched(bp, probe_steps=4)
+        for g, st in enumerate(starts):
+            bp.set_state(g, st)
+        bp.run(3)
+        info.update(steps=3, tuning=tuned, groups=[{"N": G["N"], "B": G["B"], **bp.info(g)}
+                                                    for g, G in enumerate(bp.groups)])
+    elif target == "adjoint":
+        prob, p = _adjoint_problem(sb, 301, 8, 4, 4)
+        J, g = prob.value_and_grad(np.array([p.A, p.gamma, p.U]))
+        info.update(steps=8, J=J, grad=list(g))
+    elif target == "gemm":
+        M = 9999
+        g = torch.Generator(device="cuda").manual_seed(7)
+        X = torch.randn((M, 2 * M), dtype=torch.float64, device="cuda", generator=g)
+        Y = torch.randn((2 * M, M), dtype=torch.float64, device="cuda", generator=g)
+        C = torch.empty((M, M), dtype=torch.float64, device="cuda")
+        sb.gemm_f64(X, Y, C, -0.5, 0.0)
+        torch.cuda.synchronize()
+        info.update(shape=[M, M, 2 * M])
+    info["copy_bytes"] = _calibration_copy(torch)
+    print(json.dumps(info), flush=True)
 
 
 def scan_report(sb, torch, Ns=(51, 101, 201, 301, 501, 701, 1001, 1501, 2001), steps=200):
@@ -589,7 +654,7 @@ def main():
 
     sb.require_gpu()
     if args.pmc_mode:
-        pmc_mode(sb, torch, min(args.steps, 20), args.N)
+        pmc_mode(sb, torch, min(args.steps, 20), args.N, args.pmc_target)
         return
     if args.scan:
         print(json.dumps(scan_report(sb, torch)), flush=True)

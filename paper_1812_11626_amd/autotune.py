@@ -4,7 +4,8 @@ For every group it times a few RK4 steps of that group alone for each
 (tile, rows_per_item, path) candidate and keeps the fastest; then it times
 the whole batch with those choices against a few uniform tilings and keeps
 the fastest of these.  Results are cached in
-a JSON file keyed by device name, N, number of instances and number of terms
+a JSON file keyed by device architecture and compute-unit count, N, number
+of instances and number of terms
 (path from $SUN_AUTOTUNE_CACHE, default ~/.cache/sunbloch/autotune.json).
 The tiling never changes the numbers, only the speed.
 """
@@ -57,9 +58,16 @@ def _save(path, data):
         pass
 
 
+def _device_tag() -> str:
+    """Architecture and compute-unit count of device 0 (the marketing name is
+    not used: some profilers report it empty)."""
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "") or "unknown"
+    return f"{arch.split(':')[0]}-{props.multi_processor_count}cu"
+
+
 def _key(G) -> str:
-    name = torch.cuda.get_device_name(0).replace(" ", "_")
-    return f"{name}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4|p4"
+    return f"{_device_tag()}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4|p4"
 
 
 def _candidates(tiles, rows, paths):
