@@ -417,9 +417,18 @@ int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream)
  * with a row of more than 1024 entries falls back to path 1).  path 3 (tile
  * 8, 16 or 32): path 2 with the state rows each block gathers staged in LDS
  * too (blocks also limited to 4096/tile distinct columns; a group where one
- * row exceeds that falls back to path 2).  Defaults 64, 64, 0.  All paths
- * add every term's entries in row order: results do not depend on the
- * tiling or path. */
+ * row exceeds that falls back to path 2).  path 4 (tile 2, 4 or 8
+ * instances per wavefront; rows_per_item unused): the group's state is kept
+ * instance-major on a segmented sliced layout of its generator, the terms
+ * whose coefficients are the same for every instance merged and the others
+ * (1 to 3) kept as segments; SUN_ENOTSUP otherwise.  path 5 (tile 64 or 128;
+ * rows_per_item unused): one wavefront per (row, tile of 64 instances with
+ * one per lane, or 128 with two), the row's pointers, columns and values
+ * read through the scalar cache, each XCD sweeping one eighth of the
+ * group's rows in order with the device's resident wavefronts.  Defaults
+ * 64, 64, 0.  Paths 0-3 and 5 add every term's entries in row order: their
+ * results do not depend on the tiling or path; path 4 groups the row sums
+ * differently and agrees with them to rounding. */
 int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, int32_t path,
                    void* stream);
 int sun_batch_info(sun_batch b, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,

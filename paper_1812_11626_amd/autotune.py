@@ -27,11 +27,15 @@ ROWS = (32, 64, 128)
 # path 3: path 2 with the gathered state rows staged in LDS (tiles 8-32)
 # path 4: instance-major state on a segmented sliced layout, 4 or 8 instances
 # per wavefront (the tile value); rows_per_item does not apply
-PATHS = (0, 2, 3, 4)
+# path 5: one wavefront per (row, tile of 64 or 128 instances), the matrix
+# read through the scalar cache, rows swept in order per XCD; rows_per_item
+# does not apply
+PATHS = (0, 2, 3, 4, 5)
 TILES3 = (8, 16, 32)
 TILES4 = (4, 8)
+TILES5 = (64, 128)
 UNIFORM = ((128, 64, 0), (128, 32, 0), (64, 64, 0), (16, 64, 2), (32, 64, 2), (16, 128, 3), (8, 128, 3),
-           (4, 64, 4), (8, 64, 4))
+           (4, 64, 4), (8, 64, 4), (128, 64, 5), (64, 64, 5))
 
 
 def cache_path() -> str:
@@ -67,7 +71,7 @@ def _device_tag() -> str:
 
 
 def _key(G) -> str:
-    return f"{_device_tag()}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4|p4"
+    return f"{_device_tag()}|N={G['N']}|B={G['B']}|nt={G['nt']}|lds4|p5"
 
 
 def _candidates(tiles, rows, paths):
@@ -75,6 +79,9 @@ def _candidates(tiles, rows, paths):
     for p in paths:
         if p == 4:
             out += [(t, 64, 4) for t in TILES4]
+            continue
+        if p == 5:
+            out += [(t, 64, 5) for t in TILES5]
             continue
         for t in (TILES3 if p == 3 else tiles):
             if p == 2 and t == 128:
@@ -131,7 +138,8 @@ def autotune_batched(bp, tiles=TILES, rows=ROWS, paths=PATHS, probe_steps: int =
         steps = min(probe_steps, max(1, min(G["steps"] for G in bp.groups)))
         cands = [[(chosen[g]["tile"], chosen[g]["rows_per_item"], chosen[g]["path"]) for g in range(len(bp.groups))]]
         cands += [[(t, r, p)] * len(bp.groups) for (t, r, p) in UNIFORM
-                  if (t in TILES3 if p == 3 else (t in TILES4 if p == 4 else t in tiles)) and p in paths]
+                  if (t in TILES3 if p == 3 else (t in TILES4 if p == 4 else (t in TILES5 if p == 5 else t in tiles)))
+                  and p in paths]
         best = None
         for cand in cands:
             try:

@@ -69,6 +69,7 @@ struct GroupDev {
   const int* ucol_ptr;   // path 3: distinct columns of block i are ucol[ucol_ptr[i] .. ucol_ptr[i+1])
   const int* ucol;
   const unsigned short* lidx;   // path 3: position of every stored entry's column in its block's list
+  int p5;                // 1: one wavefront per (row, tile), matrix through the scalar cache (path 5)
 };
 
 }  // namespace
@@ -662,6 +663,161 @@ __global__ __launch_bounds__(256) void k_batch_stage_xlds(const GroupDev* __rest
   }
 }
 
+// Path 5: one wavefront per (row, instance tile), every group in one tile
+// of 64 lanes with VEC consecutive instances per lane (VEC = 2: up to 128
+// instances, so each group's matrix row is read once per stage).  The row's
+// pointers, columns and values are uniform across the wavefront and are read
+// through the scalar cache (constant address space), so each entry costs one
+// 16-byte gather per lane and no vector work to broadcast it.  Ordering:
+// the grid is the number of wavefronts the device keeps resident, each XCD
+// (blockIdx % 8) takes one contiguous eighth of every group's rows, and its
+// wavefronts walk that eighth interleaved (wavefront w takes rows w, w + W,
+// ...), so the rows in flight on an XCD form a narrow moving window and the
+// state rows they gather (neighbouring pairs, a few hundred rows apart) are
+// still in that XCD's L2 when the next rows use them.  Each term's entries
+// are summed in row order and combined exactly as in the other paths, so the
+// results are bitwise the same.  The column and value arrays carry
+// kRowPad padding entries: a round of kRowChunk scalar loads may read past
+// the last row.
+typedef const __attribute__((address_space(4))) int scalar_int;
+typedef const __attribute__((address_space(4))) double scalar_dbl;
+// global (not generic) pointers: generic loads also count against the
+// counter the scalar loads wait on, which would serialise the gathers
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) double gconst_dbl;
+typedef const __attribute__((address_space(1))) dv2 gconst_dbl2;
+typedef __attribute__((address_space(1))) double gdbl;
+typedef __attribute__((address_space(1))) dv2 gdbl2;
+
+constexpr int kRowChunk = 8;
+constexpr int kRowPad = 16;
+
+template <int STAGE, int VEC>
+__global__ __launch_bounds__(64) void k_batch_rows(const GroupDev* __restrict__ groups,
+                                                   const int* __restrict__ gorder, int nactive,
+                                                   const int64_t* __restrict__ step) {
+  extern __shared__ double s_cf[];   // [nt][64 * VEC]: this wavefront's tile coefficients, lane-private
+  const int lane = threadIdx.x;
+  const int x = blockIdx.x & 7;
+  const int64_t W = gridDim.x >> 3;
+  const int64_t w = blockIdx.x >> 3;
+  constexpr int TW = 64 * VEC;
+  for (int q = 0; q < nactive; ++q) {
+    const int g = gorder[q];
+    const GroupDev& G = groups[g];
+    if (!G.p5 || G.vec != VEC) continue;
+    const int64_t lo = (int64_t)G.M * x / 8;
+    const int64_t n = (int64_t)G.M * (x + 1) / 8 - lo;
+    const int nt = G.nt, ld = G.ld, B = G.B;
+    const int64_t k0 = 2 * step[g];
+    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+    const double ph = G.wave[k0 + krow];
+    gconst_dbl* xin = (gconst_dbl*)(STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa)));
+    gdbl* xout = (gdbl*)(STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v)));
+    gconst_dbl* gv = (gconst_dbl*)G.v;
+    gdbl* gacc = (gdbl*)G.acc;
+    scalar_int* rp = (scalar_int*)G.rowptr;
+    scalar_int* sp = (scalar_int*)G.segptr;
+    scalar_int* col = (scalar_int*)G.col;
+    scalar_dbl* val = (scalar_dbl*)G.val;
+    int cur = -1;
+    for (int64_t i = w; i < n * G.tiles; i += W) {
+      const int tb = (int)(i / n);
+      const int64_t r = lo + i % n;
+      if (tb != cur) {
+        for (int a = 0; a < nt; ++a)
+#pragma unroll
+          for (int j = 0; j < VEC; ++j) {
+            const int b = tb * TW + VEC * lane + j;
+            s_cf[a * TW + VEC * lane + j] = b < B ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
+          }
+        cur = tb;
+      }
+      const int b0 = tb * TW + VEC * lane;
+      const int64_t ix = r * ld + b0;
+      const bool own = b0 < B;
+      double vr[VEC], ar[VEC], sum[VEC], y[VEC];
+      if constexpr (VEC == 2) {
+        const dv2 t = own ? *(gconst_dbl2*)(gv + ix) : dv2{0.0, 0.0};
+        const dv2 u = (own && STAGE != 0) ? *(gconst_dbl2*)(gacc + ix) : dv2{0.0, 0.0};
+        vr[0] = t.x; vr[1] = t.y; ar[0] = u.x; ar[1] = u.y;
+      } else {
+        vr[0] = own ? gv[ix] : 0.0;
+        ar[0] = (own && STAGE != 0) ? gacc[ix] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) { sum[j] = 0.0; y[j] = 0.0; }
+      const int e0 = rp[r], e1 = rp[r + 1];
+      int a = 0;
+      int bnd = nt > 1 ? sp[r * nt + 1] : e1;   // end of segment a
+      gconst_dbl* xb = xin + b0;
+      for (int e = e0; e < e1; e += kRowChunk) {
+        int c[kRowChunk];
+        double v[kRowChunk];
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+          c[k] = col[e + k];
+          v[k] = val[e + k];
+        }
+        double xv[kRowChunk][VEC];
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+          if (e + k < e1) {
+            // lanes past the group's last instance issue no gather
+            if constexpr (VEC == 2) {
+              const dv2 t = own ? *(gconst_dbl2*)(xb + (int64_t)c[k] * ld) : dv2{0.0, 0.0};
+              xv[k][0] = t.x;
+              xv[k][1] = t.y;
+            } else {
+              xv[k][0] = own ? xb[(int64_t)c[k] * ld] : 0.0;
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+          if (e + k < e1) {
+            while (e + k >= bnd) {   // close segment a (and any empty ones after it)
+              const double* cf = s_cf + a * TW + VEC * lane;
+#pragma unroll
+              for (int j = 0; j < VEC; ++j) {
+                y[j] += cf[j] * sum[j];
+                sum[j] = 0.0;
+              }
+              ++a;
+              bnd = a + 1 < nt ? sp[r * nt + a + 1] : e1;
+            }
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) sum[j] += v[k] * xv[k][j];
+          }
+        }
+      }
+      for (; a < nt; ++a) {
+        const double* cf = s_cf + a * TW + VEC * lane;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+          y[j] += cf[j] * sum[j];
+          sum[j] = 0.0;
+        }
+      }
+      double o[VEC], an[VEC];
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) o[j] = lds_stage<STAGE>(vr[j], ar[j], y[j], G.dt, an[j]);
+      if constexpr (VEC == 2) {
+        if (own && b0 + 1 < B) {
+          *(gdbl2*)(xout + ix) = dv2{o[0], o[1]};
+          if (STAGE != 3) *(gdbl2*)(gacc + ix) = dv2{an[0], an[1]};
+        } else if (own) {
+          xout[ix] = o[0];
+          if (STAGE != 3) gacc[ix] = an[0];
+        }
+      } else if (own) {
+        xout[ix] = o[0];
+        if (STAGE != 3) gacc[ix] = an[0];
+      }
+    }
+  }
+}
+
 // Row blocks for path 3: at most max_rows rows, kLdsCap entries and ucap
 // distinct columns; with each block's sorted distinct columns and every
 // entry's position in them.  False if a single row does not fit.
@@ -752,6 +908,13 @@ void refresh_items(sun_batch_s& bt) {
     G.ld = bt.ld[g];
     G.row_blocks = (int)((bt.M[g] + G.rows_per_item - 1) / G.rows_per_item);
     G.tiles = (G.B + G.tile * G.vec - 1) / (G.tile * G.vec);
+    G.p5 = bt.path[g] == 5;
+    if (G.p5) {              // one wavefront (64 lanes) per (row, tile)
+      G.vec = bt.tile[g] == 128 ? 2 : 1;
+      G.tile = 64;
+      G.tiles = (G.B + 64 * G.vec - 1) / (64 * G.vec);
+      G.row_blocks = 0;        // no items of the block kernels
+    }
     if (bt.path[g] == 4) {   // advanced by the multi-instance sliced kernel instead
       G.row_blocks = 0;
       G.tiles = 0;
@@ -759,7 +922,7 @@ void refresh_items(sun_batch_s& bt) {
   }
   for (int gi : bt.order) {
     GroupDev& G = bt.ghost[gi];
-    G.nblk = bt.path[gi] == 4 ? 0 : bt.nblk[gi];
+    G.nblk = bt.path[gi] >= 4 ? 0 : bt.nblk[gi];
     G.blk_row = bt.blk_row[gi].get();
     G.item0 = item;
     if (G.nblk == 0) item += (int64_t)G.row_blocks * G.tiles;
@@ -773,7 +936,7 @@ void repartition(sun_batch_s& bt, int g) {
   const int max_rows = std::min(bt.rows_per_item[g], kLdsRows);
   std::vector<int> blk;
   bt.xl[g] = 0;
-  if (bt.path[g] == 4) {
+  if (bt.path[g] >= 4) {
     bt.xu_ptr[g].release();
     bt.xu_col[g].release();
     bt.xu_lidx[g].release();
@@ -920,7 +1083,26 @@ struct StageLaunch {
   int nactive = 0, cf_len = 0;
   int64_t nitems = 0, grid = 1, bgrid = 8, xgrid = 8;
   bool v1 = false, v2 = false, xl = false;
+  bool r1 = false, r2 = false;   // path-5 groups with one / two instances per lane
+  int64_t rgrid[3] = {0, 0, 0};  // path-5 grids (resident wavefronts, a multiple of 8), by VEC
+  int r_nt = 1;                  // most terms of a path-5 group
 };
+
+// Wavefronts of k_batch_rows<*, VEC> the device keeps resident (the least
+// over the four stages), rounded down to a multiple of 8 XCDs.
+template <int VEC>
+int64_t rows_grid(int ncu, size_t lds) {
+  int least = INT32_MAX;
+  const void* ks[4] = {(const void*)k_batch_rows<0, VEC>, (const void*)k_batch_rows<1, VEC>,
+                       (const void*)k_batch_rows<2, VEC>, (const void*)k_batch_rows<3, VEC>};
+  for (const void* k : ks) {
+    int nb = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, lds));
+    least = std::min(least, nb);
+  }
+  SUN_REQUIRE(least >= 1, SUN_ENOTSUP, "path 5 kernel cannot be resident");
+  return std::max<int64_t>(8, (int64_t)least * ncu / 8 * 8);
+}
 
 template <int STAGE>
 void launch_stage(const StageLaunch& L) {
@@ -937,6 +1119,12 @@ void launch_stage(const StageLaunch& L) {
   if (L.xl)
     hipLaunchKernelGGL(k_batch_stage_xlds<STAGE>, dim3((unsigned)L.xgrid), dim3(256), cf_bytes + kXLdsBytes, L.s,
                        L.gd, L.go, L.nactive, L.st, L.cf_len);
+  if (L.r1)
+    hipLaunchKernelGGL((k_batch_rows<STAGE, 1>), dim3((unsigned)L.rgrid[1]), dim3(64),
+                       (size_t)L.r_nt * 64 * sizeof(double), L.s, L.gd, L.go, L.nactive, L.st);
+  if (L.r2)
+    hipLaunchKernelGGL((k_batch_rows<STAGE, 2>), dim3((unsigned)L.rgrid[2]), dim3(64),
+                       (size_t)L.r_nt * 128 * sizeof(double), L.s, L.gd, L.go, L.nactive, L.st);
 }
 
 }  // namespace
@@ -1027,8 +1215,11 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
         SUN_REQUIRE(bt->nnz[g] < (int64_t)INT32_MAX, SUN_ENOTSUP, "group matrix has 2^31 or more nonzeros");
         bt->rowptr[g].alloc(M + 1);
         bt->segptr[g].alloc(M * nt);
-        bt->col[g].alloc(bt->nnz[g] > 0 ? bt->nnz[g] : 1);
-        bt->val[g].alloc(bt->nnz[g] > 0 ? bt->nnz[g] : 1);
+        // kRowPad zero entries after the last one (path 5 reads ahead)
+        bt->col[g].alloc(bt->nnz[g] + kRowPad);
+        bt->val[g].alloc(bt->nnz[g] + kRowPad);
+        HIP_OK(hipMemsetAsync(bt->col[g].get() + bt->nnz[g], 0, kRowPad * sizeof(int), s));
+        HIP_OK(hipMemsetAsync(bt->val[g].get() + bt->nnz[g], 0, kRowPad * sizeof(double), s));
         hipLaunchKernelGGL(k_batch_fuse, dim3(grid_for(M, 128)), dim3(128), 0, s, M, P, t, 1, nullptr, off.get(),
                            bt->segptr[g].get(), bt->col[g].get(), bt->val[g].get());
         HIP_LAUNCH_OK();
@@ -1114,9 +1305,11 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
   return guarded([&] {
     SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
-    SUN_REQUIRE(path >= 0 && path <= 4, SUN_EINVAL, "path must be 0, 1, 2, 3 or 4");
+    SUN_REQUIRE(path >= 0 && path <= 5, SUN_EINVAL, "path must be 0, 1, 2, 3, 4 or 5");
     if (path == 4) {
       SUN_REQUIRE(tile == 2 || tile == 4 || tile == 8, SUN_EINVAL, "path 4 takes 2, 4 or 8 instances per wavefront");
+    } else if (path == 5) {
+      SUN_REQUIRE(tile == 64 || tile == 128, SUN_EINVAL, "path 5 takes tiles of 64 or 128 instances");
     } else {
       SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
                   "tile must be 8, 16, 32, 64 or 128");
@@ -1198,6 +1391,18 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     int dev = 0, ncu = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // path-5 grids: the resident wavefronts for the largest term count of
+    // the groups the call advances
+    int p5_nt = 1;
+    bool p5_vec[3] = {false, false, false};
+    for (int g = 0; g < bt->ngroups; ++g)
+      if (todo[g] > 0 && bt->ghost[g].p5) {
+        p5_nt = std::max(p5_nt, bt->ghost[g].nt);
+        p5_vec[bt->ghost[g].vec] = true;
+      }
+    int64_t p5_grid[3] = {0, 0, 0};
+    if (p5_vec[1]) p5_grid[1] = rows_grid<1>(ncu, (size_t)p5_nt * 64 * sizeof(double));
+    if (p5_vec[2]) p5_grid[2] = rows_grid<2>(ncu, (size_t)p5_nt * 128 * sizeof(double));
     for (int64_t n = 0; n < maxn; ++n) {
       int nactive = 0;
       while (nactive < bt->ngroups && todo[ord[nactive]] > n) ++nactive;
@@ -1209,6 +1414,13 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       int max_nt = 1;
       for (int q = 0; q < nactive; ++q) {
         const GroupDev& G = bt->ghost[ord[q]];
+        if (G.p5) {
+          // the kernel's tile of 64 * vec instances stays inside the padded state rows
+          SUN_REQUIRE(G.tiles * 64 * G.vec <= G.ld && G.nt <= kMaxBTerms, SUN_ENOTSUP,
+                      "internal: path 5 tile exceeds the state rows");
+          (G.vec == 2 ? L.r2 : L.r1) = true;
+          continue;
+        }
         if (G.nblk == 0) continue;
         max_nt = std::max(max_nt, G.nt);
         if (G.xlds) {
@@ -1224,6 +1436,9 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       L.bgrid = std::max<int64_t>(8, (std::min<int64_t>(nlds, (int64_t)ncu * 8) + 7) / 8 * 8);
       L.xgrid = std::max<int64_t>(8, (std::min<int64_t>(nx, (int64_t)ncu * 3) + 7) / 8 * 8);
       L.cf_len = max_nt * kCfStride;
+      L.r_nt = p5_nt;
+      L.rgrid[1] = p5_grid[1];
+      L.rgrid[2] = p5_grid[2];
       L.st = steptab.get() + n * bt->ngroups;
       L.gd = bt->gdev.get();
       L.go = gorder.get();

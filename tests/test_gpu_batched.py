@@ -66,7 +66,7 @@ def test_tiling_does_not_change_results(lib):
     results = []
     for tile, rows, path in ((64, 64, 0), (8, 1, 0), (16, 7, 1), (32, 512, 1), (64, 3, 1), (16, 128, 0),
                              (128, 32, 0), (128, 5, 1), (16, 64, 2), (32, 9, 2), (64, 128, 2), (8, 16, 2),
-                             (8, 4, 3), (16, 64, 3), (32, 128, 3)):
+                             (8, 4, 3), (16, 64, 3), (32, 128, 3), (128, 64, 5), (64, 1, 5)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -93,7 +93,8 @@ def test_lds_and_global_paths_agree_bitwise(lib):
     starts = [torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))) for (N, idx, _, _, _) in groups]
     out = []
     for tile, rows, path in ((64, 64, 0), (16, 128, 0), (32, 16, 1), (64, 8, 1), (128, 64, 0), (128, 8, 0),
-                             (16, 64, 2), (32, 32, 2), (64, 128, 2), (8, 128, 3), (16, 32, 3), (32, 128, 3)):
+                             (16, 64, 2), (32, 32, 2), (64, 128, 2), (8, 128, 3), (16, 32, 3), (32, 128, 3),
+                             (128, 64, 5), (64, 64, 5)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -102,6 +103,40 @@ def test_lds_and_global_paths_agree_bitwise(lib):
     for r in out[1:]:
         for a, b in zip(r, out[0]):
             assert np.array_equal(a, b)
+
+
+def test_row_wavefront_path_multi_tile_bitwise(lib):
+    """Path 5 (one wavefront per row and tile, matrix through the scalar
+    cache) on groups of 300 and 130 instances, i.e. 3 and 2 tiles of 128 and
+    5 and 3 tiles of 64 with ragged last tiles, against path 0: bitwise equal
+    after 16 steps, and the first instances against the dense oracle."""
+    flush("[batched] path 5, several tiles per group, vs path 0")
+    rng = np.random.default_rng(11)
+    inst = []
+    for N, cnt in ((4, 300), (5, 130)):
+        for _ in range(cnt):
+            p = dimer.plain_config(N)
+            p.A = float(rng.uniform(0.5, 3.0))
+            p.gamma = float(rng.uniform(0.05, 0.5))
+            p.steps_per_period = 200 if N == 4 else 300
+            inst.append(p)
+    steps = 16
+    bp, groups = dimer_batch(lib, inst, steps)
+    starts = [torch.as_tensor(np.stack([fock_bloch(N, j % N) for j in range(len(idx))])) for (N, idx, _, _, _) in groups]
+    out = []
+    for tile, rows, path in ((64, 64, 0), (128, 64, 5), (64, 64, 5)):
+        for g in range(len(groups)):
+            bp.tune(g, tile, rows, path)
+            bp.set_state(g, starts[g])
+        bp.run(steps)
+        out.append([bp.get_state(g).cpu().numpy() for g in range(len(groups))])
+    for r in out[1:]:
+        for a, b in zip(r, out[0]):
+            assert np.array_equal(a, b)
+    for g, (N, idx, _, _, st) in enumerate(groups):
+        for j in (0, len(idx) - 1):
+            want = _oracle_instance(inst[idx[j]], st, fock_bloch(N, j % N))
+            assert rel_vec_err(out[1][g][j], want) <= TOL, (N, j)
 
 
 def test_full_workload_sampled_against_plain(lib):
@@ -144,7 +179,7 @@ def test_autotuner_picks_valid_tiling(lib, tmp_path, monkeypatch):
     for g in range(len(groups)):
         info = bp.info(g)
         assert info["tile"] == chosen[g]["tile"] and info["rows_per_item"] == chosen[g]["rows_per_item"]
-        assert chosen[g]["path"] in (0, 2, 3)
+        assert chosen[g]["path"] in (0, 2, 3, 4, 5)
     again = lib.autotune_batched(bp)
     assert all(c["cached"] for c in again.values())
 
