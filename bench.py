@@ -50,7 +50,8 @@ def parse():
                     help="run one leg only (for profiling); prints that leg's report")
     ap.add_argument("--scan", action="store_true",
                     help="assembly time and RK4 steps/s of the plain workload over a range of N (one JSON line)")
-    ap.add_argument("--pmc-target", choices=("plain", "batched", "adjoint", "gemm"), default="plain",
+    ap.add_argument("--pmc-target", choices=("plain", "batched", "batched-paths", "adjoint", "gemm"),
+                    default="plain",
                     help="workload of --pmc-mode")
     ap.add_argument("--pmc-mode", action="store_true",
                     help="short run for rocprofv3 --pmc (stage kernel + calibration copy)")
@@ -540,6 +541,9 @@ def pmc_mode(sb, torch, steps, N=1001, target="plain"):
       batched -- the 512-instance workload with its autotuned tiling (from the
                  autotuner's cache when a previous run filled it; then no
                  probe launches run), 3 RK4 steps of every group;
+      batched-paths -- the N = 301 group of the 512-instance workload alone,
+                 3 RK4 steps on path 0 (128-instance tile, 64-row blocks),
+                 then 3 on path 5 (128-instance tile);
       adjoint -- the adjoint workload N = 301, 8 steps with a checkpoint every
                  4 (forward and fused reverse stages);
       gemm    -- the dense path's product at N = 100 (9,999 x 19,998 by
@@ -556,7 +560,7 @@ def pmc_mode(sb, torch, steps, N=1001, target="plain"):
         eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
         prop.propagate(v, eps, p.dt, steps)
         info.update(steps=steps, layout=prop.layout())
-    elif target == "batched":
+    elif target in ("batched", "batched-paths"):
         inst = dimer.batched_instances()
         byN = {}
         for i, q in enumerate(inst):
@@ -575,6 +579,21 @@ def pmc_mode(sb, torch, steps, N=1001, target="plain"):
         bp = sb.BatchedPropagator(specs)
         for g, st in enumerate(starts):
             bp.set_state(g, st)
+        if target == "batched-paths":
+            g = len(specs) - 1                      # the N = 301 group
+            ms = {}
+            for path in (0, 5):
+                bp.tune(g, 128, 64, path)
+                bp.set_state(g, starts[g])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                bp.run(3, only_group=g)
+                torch.cuda.synchronize()
+                ms[f"path{path}"] = (time.perf_counter() - t0) / 3 * 1e3
+            info.update(steps=3, N=bp.groups[g]["N"], B=bp.groups[g]["B"], ms_per_step_with_sync=ms)
+            info["copy_bytes"] = _calibration_copy(torch)
+            print(json.dumps(info), flush=True)
+            return
         tuned = sb.autotune_batched(bp, probe_steps=4)
         for g, st in enumerate(starts):
             bp.set_state(g, st)

@@ -169,7 +169,7 @@ int sun_expand_lindbladian(sun_basis b, const sun_zcsr* H, int32_t nH,
  * (eq. 10 with dense sections; a K = 2M contraction), then compressed to CSR
  * with the same drop rule.  No per-row limit; device memory about 5 M^2
  * doubles while a dissipator is assembled (4 GB at N = 100); M^2 < 2^33
- * (N < 300, else SUN_ENOTSUP).
+ * (N <= 304, else SUN_ENOTSUP).
  * sun_expand_lindbladian itself switches to this path for a term whose rows
  * exceed its per-row limit.  Synchronises `stream`. */
 int sun_expand_lindbladian_dense(sun_basis b, const sun_zcsr* H, int32_t nH,

@@ -657,7 +657,7 @@ void dense_rows(const sun_basis_s& b, const Expansion& e, const cplx* x, const c
 
 // The dense path holds M x M arrays: limit it to M^2 < 2^33 entries (N < 300).
 void dense_require(int64_t M) {
-  SUN_REQUIRE(M * M < ((int64_t)1 << 33), SUN_ENOTSUP, "dense path limited to M^2 < 2^33 entries (N < 300)");
+  SUN_REQUIRE(M * M < ((int64_t)1 << 33), SUN_ENOTSUP, "dense path limited to M^2 < 2^33 entries (N <= 304)");
 }
 
 void dense_zero(double* a, int64_t n, hipStream_t s) {

@@ -311,8 +311,10 @@ __global__ __launch_bounds__(NT) void k_rk4_stage(
 // each window (stable), and packed 64 rows per slice: entry k of the row in
 // lane l of slice s sits at off[s] + 64 k + l, so one load instruction of a
 // wavefront reads 64 consecutive values.  A slice is as wide as its longest
-// row; shorter rows are padded with (column M, value 0), which multiplies the
-// constant 1 at x[M] and adds nothing.  Each lane keeps the static length of
+// row; a shorter row's padding entries hold value 0 and column delta 0 (so
+// they gather the slice column's base entry, a valid index); the row walk
+// drops their products by selecting on the lane's row length, so they add
+// exactly nothing even where the gathered entry is not finite.  Each lane keeps the static length of
 // its row so that it can split its sum into the static and the dynamic
 // segment.  Longer rows are listed separately and reduced by one wavefront
 // each.
