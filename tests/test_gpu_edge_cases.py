@@ -12,7 +12,7 @@ import scipy.sparse as sp
 import torch
 
 from helpers import flush, rel_matrix_err, rel_vec_err, to_scipy
-from oracle import basis as ob, lindblad as lb
+from oracle import basis as ob, lindblad as lb, o2
 from workloads import dimer, random_ops
 
 pytestmark = pytest.mark.gpu
@@ -128,16 +128,33 @@ def test_banded_random_operators_larger_N(lib):
     assert rel_vec_err(K.cpu().numpy(), lb.k_vector(L)) <= 1e-12
 
 
-def test_dense_operator_beyond_row_capacity_is_refused(lib):
-    """A dense complex L at N = 40 gives product rows beyond the LDS sort
-    capacity; the library must refuse with SUN_ENOTSUP (detected from the
-    per-row counts before anything is filled)."""
+def test_dense_operator_beyond_row_capacity_takes_dense_path(lib):
+    """A dense complex L at N = 40 gives product rows beyond the sparse
+    assembly's LDS sort capacity (detected from the per-row counts before
+    anything is filled); the default assembly then takes the dense path, and
+    R and K equal the C oracle's explicit traces to 1e-12."""
     N = 40
+    flush(f"[edge] dense L beyond the sparse row capacity N={N}")
+    M = N * N - 1
     b = lib.build_basis(N)
     L = random_ops.random_complex_csr(N, 1.0, seed=3)
+    lind = lib.Lindbladian(b, [], [L])
+    rp, c, v, k = lind.export("L", 0)
+    assert rel_matrix_err(to_scipy(rp, c, v, M), o2.q_full("L", L)) <= 1e-12
+    assert rel_vec_err(k.cpu().numpy(), o2.k_vector(L)) <= 1e-12
+
+
+def test_dense_path_size_limit_is_refused(lib):
+    """Past the dense path's index limit (M^2 >= 2^33, N = 305) a dense L is
+    refused with SUN_ENOTSUP before any dense array is allocated."""
+    N = 305
+    flush(f"[edge] dense path limit N={N}")
+    b = lib.build_basis(N)
+    L = random_ops.random_complex_csr(N, 1.0, seed=5)
     with pytest.raises(lib.SunError) as e:
-        lib.Lindbladian(b, [], [L])
+        lib.Lindbladian(b, [], [L], dense=True)
     assert e.value.code == -4
+    assert "dense path" in str(e.value)
 
 
 def test_propagate_argument_checks(lib):
