@@ -26,9 +26,10 @@
  *    Kernels are queued on it.  Entry points that return sizes or counts to
  *    host memory synchronise that stream before returning.
  *  - Memory ownership: buffers passed in stay owned by the caller.  Objects
- *    created by the library (sun_basis, sun_lind, sun_prop, sun_batch) own
- *    their internal device memory (allocated with hipMalloc) until the
- *    matching *_free call.  Objects must be freed before the process ends.
+ *    created by the library (sun_basis, sun_lind, sun_prop, sun_batch,
+ *    sun_adj) own their internal device memory until the matching *_free
+ *    call; it comes from hipMalloc, or from the caller's allocator after
+ *    sun_set_allocator.  Objects must be freed before the process ends.
  *  - Errors: every int-returning call returns SUN_OK (0) or a negative
  *    status; sun_last_error() then returns a message for the calling thread.
  *    On error, outputs are unspecified but no object is leaked.
@@ -60,6 +61,26 @@ enum {
 const char* sun_last_error(void);
 /* Library version, major*10000 + minor*100 + patch. */
 int sun_version(void);
+
+/* Device memory of the library (object layouts, assembly temporaries,
+ * internal work buffers) comes from hipMalloc/hipFree unless the caller
+ * installs its own pair here, e.g. a framework's caching allocator, so that
+ * the framework accounts for it and can reuse it.
+ *   alloc(bytes, stream, ctx) returns device memory of at least `bytes`
+ *     bytes, 256-byte aligned, usable on `stream` (the stream of the call
+ *     that allocates, NULL = the default stream), or NULL on failure (the
+ *     library then returns SUN_ENOMEM);
+ *   release(ptr, ctx) gives it back.  The library synchronises the device
+ *     before calling it (as hipFree does), so no queued kernel still uses
+ *     the memory.
+ * Both NULL restores hipMalloc/hipFree; exactly one NULL is SUN_EINVAL.
+ * Every buffer is released through the pair that allocated it, so objects
+ * created before a change stay valid.  Process-wide; install it before
+ * creating objects, not while other threads call the library.  The
+ * allocation-free entry point never calls either. */
+typedef void* (*sun_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*sun_release_fn)(void* ptr, void* ctx);
+int sun_set_allocator(sun_alloc_fn alloc, sun_release_fn release, void* ctx);
 
 /* ------------------------------------------------------------------------
  * Basis (Sec. II; Sec. IV step 2.2)

@@ -27,5 +27,7 @@ from .api import (  # noqa: F401
     propagate,
     require_gpu,
     SunBlochLoss,
+    use_default_allocator,
+    use_torch_allocator,
 )
 from .autotune import autotune_batched  # noqa: F401

@@ -42,10 +42,15 @@ i64 = C.c_int64
 f64 = C.c_double
 P = C.POINTER
 
+# caller allocator (sun_set_allocator): alloc(bytes, stream, ctx) -> ptr, release(ptr, ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
 # name: (restype, argtypes)
 PROTOS = {
     "sun_last_error": (C.c_char_p, []),
     "sun_version": (C.c_int, []),
+    "sun_set_allocator": (C.c_int, [ALLOC_FN, RELEASE_FN, vp]),
     "sun_build_basis": (C.c_int, [i32, vp, P(vp)]),
     "sun_basis_dims": (C.c_int, [vp, P(i32), P(i64)]),
     "sun_basis_counts": (C.c_int, [vp, vp, P(i64), P(i64)]),

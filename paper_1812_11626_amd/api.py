@@ -148,6 +148,45 @@ class Basis:
         return out if v.dim() == 2 else out[0]
 
 
+_ALLOCATOR = None   # the installed ctypes callbacks (kept alive while installed)
+
+
+def use_torch_allocator():
+    """Route every device allocation of the library (object layouts, assembly
+    temporaries, work buffers) through PyTorch's caching allocator, on the
+    stream of the library call that allocates, so that PyTorch accounts for
+    the memory (torch.cuda.memory_allocated) and can reuse it.  Buffers
+    allocated before the switch are still released by hipFree."""
+    global _ALLOCATOR
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:                           # out of memory: the library returns SUN_ENOMEM
+            return None
+
+    def _release(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    cbs = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+    check(_lib.load().sun_set_allocator(cbs[0], cbs[1], None))
+    _ALLOCATOR = cbs
+
+
+def use_default_allocator():
+    """Back to hipMalloc/hipFree for new allocations (buffers allocated
+    through PyTorch are still released through it)."""
+    global _ALLOCATOR
+    check(_lib.load().sun_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None))
+    # the old callbacks must outlive every buffer they allocated: keep them
+    if _ALLOCATOR is not None:
+        _RETIRED_ALLOCATORS.append(_ALLOCATOR)
+    _ALLOCATOR = None
+
+
+_RETIRED_ALLOCATORS = []
+
+
 def gemm_f64(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
              beta: float = 0.0) -> torch.Tensor:
     """C = alpha A B + beta C on the matrix cores (sun_gemm_f64); float64

@@ -1,4 +1,6 @@
 // Error state, scans and reductions used by the assembly pipeline.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace sun {
@@ -7,6 +9,44 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
+
+thread_local void* t_call_stream = nullptr;
+
+// ---------------------------------------------------------------------------
+// Device allocations (hipMalloc/hipFree or the caller's pair).
+// ---------------------------------------------------------------------------
+static std::mutex g_alloc_mu;
+static AllocPair g_alloc;
+
+void* device_alloc(size_t bytes, AllocPair& used) {
+  {
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    used = g_alloc;
+  }
+  void* p = nullptr;
+  if (!used.alloc) {
+    HIP_OK(hipMalloc(&p, bytes));
+    return p;
+  }
+  p = used.alloc(bytes, t_call_stream, used.ctx);
+  SUN_REQUIRE(p != nullptr, SUN_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  if (reinterpret_cast<uintptr_t>(p) & 255) {
+    used.release(p, used.ctx);
+    SUN_THROW(SUN_EINVAL, "the caller's allocator returned memory that is not 256-byte aligned");
+  }
+  return p;
+}
+
+void device_release(void* p, const AllocPair& used) noexcept {
+  if (!used.release) {
+    (void)hipFree(p);
+    return;
+  }
+  // as hipFree does: nothing queued may still use the memory once the
+  // caller's allocator may hand it out again
+  (void)hipDeviceSynchronize();
+  used.release(p, used.ctx);
+}
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of int64 (block-local scan, recursive scan of block sums,
@@ -226,4 +266,13 @@ size_t lds_limit() {
 }  // namespace sun
 
 extern "C" const char* sun_last_error(void) { return sun::g_last_error.c_str(); }
+
+extern "C" int sun_set_allocator(sun_alloc_fn alloc, sun_release_fn release, void* ctx) {
+  return sun::guarded([&] {
+    SUN_REQUIRE((alloc == nullptr) == (release == nullptr), SUN_EINVAL,
+                "give both the allocation and the release function, or neither");
+    std::lock_guard<std::mutex> lock(sun::g_alloc_mu);
+    sun::g_alloc = sun::AllocPair{alloc, release, alloc ? ctx : nullptr};
+  });
+}
 extern "C" int sun_version(void) { return 100; }

@@ -49,10 +49,15 @@ void clear_error();
 // Check the launch status of the last kernel.
 #define HIP_LAUNCH_OK() HIP_OK(hipGetLastError())
 
+// Stream of the entry point being executed on this thread (reset by
+// guarded, recorded by as_stream); handed to a caller-installed allocator.
+extern thread_local void* t_call_stream;
+
 template <class F>
 int guarded(F&& f) {
   try {
     clear_error();
+    t_call_stream = nullptr;
     f();
     return SUN_OK;
   } catch (const Error& e) {
@@ -67,7 +72,20 @@ int guarded(F&& f) {
   }
 }
 
-inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline hipStream_t as_stream(void* s) {
+  t_call_stream = s;
+  return reinterpret_cast<hipStream_t>(s);
+}
+
+// Device allocations: hipMalloc/hipFree, or the caller's pair installed with
+// sun_set_allocator.  Each buffer remembers the pair that allocated it.
+struct AllocPair {
+  sun_alloc_fn alloc = nullptr;
+  sun_release_fn release = nullptr;
+  void* ctx = nullptr;
+};
+void* device_alloc(size_t bytes, AllocPair& used);          // throws SUN_ENOMEM
+void device_release(void* p, const AllocPair& used) noexcept;
 
 // ---------------------------------------------------------------------------
 // Owning device buffer.
@@ -76,23 +94,24 @@ template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  AllocPair a;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), a(o.a) { o.p = nullptr; o.n = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; a = o.a; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
+    if (count) p = static_cast<T*>(device_alloc(count * sizeof(T), a));
     n = count;
-    if (count) HIP_OK(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) device_release(p, a);
     p = nullptr;
     n = 0;
   }

@@ -98,3 +98,15 @@ def test_header_is_plain_c99(tmp_path):
     r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
                         "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_allocator_hook_arguments_need_no_gpu():
+    """sun_set_allocator checks its arguments on the host: one function of
+    the pair alone is SUN_EINVAL; both NULL (hipMalloc/hipFree) is accepted."""
+    from paper_1812_11626_amd import _lib
+    L = _lib.load()
+    alloc = _lib.ALLOC_FN(lambda n, s, c: None)
+    release = _lib.RELEASE_FN(lambda p, c: None)
+    assert L.sun_set_allocator(alloc, _lib.RELEASE_FN(), None) == _lib.SUN_EINVAL
+    assert L.sun_set_allocator(_lib.ALLOC_FN(), release, None) == _lib.SUN_EINVAL
+    assert L.sun_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None) == _lib.SUN_OK
