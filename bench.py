@@ -488,7 +488,7 @@ def dense_report(sb, torch, N=100):
     torch.cuda.empty_cache()
     prop = lind.propagator([1.0, 0.1], [])
     t0 = time.perf_counter()
-    v, iters, relres = prop.stationary([], tau=5.0)
+    v, iters, relres = prop.stationary([], tau=1.0)
     t_st = time.perf_counter() - t0
     rho = basis.density(v)
     ev = torch.linalg.eigvalsh(rho.cpu())
@@ -505,7 +505,7 @@ def dense_report(sb, torch, N=100):
 
 def stationary_report(sb, torch, Ns=(301, 1001)):
     """Stationary state of the dimer generator at the static drive eps = E:
-    GMRES on the RK4 time-tau map (tau = 5), iterations, time and residual."""
+    GMRES on the RK4 time-tau map (tau = 1), iterations, time and residual."""
     from workloads import dimer
     res = {}
     for N in Ns:
@@ -515,10 +515,10 @@ def stationary_report(sb, torch, Ns=(301, 1001)):
         lind, prop = sb.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        v, iters, relres = prop.stationary([p.E], dt=p.dt, tau=5.0)
+        v, iters, relres = prop.stationary([p.E], dt=p.dt, tau=1.0)
         el = time.perf_counter() - t0
         res[str(N)] = {"iterations": iters, "relres": relres, "seconds": el, "dt": p.dt,
-                       "steps_per_map": int(round(5.0 / p.dt))}
+                       "steps_per_map": int(round(1.0 / p.dt))}
         log(f"stationary N={N}: {iters} iterations, relres {relres:.1e}, {el:.2f} s")
     return res
 

@@ -345,7 +345,7 @@ class Propagator:
         self._guard = (lo, hi) if limit >= 0 else None
         return rho.value
 
-    def stationary(self, coef=(), dt: float = 0.0, tau: float = 5.0, restart: int = 40, max_iter: int = 400,
+    def stationary(self, coef=(), dt: float = 0.0, tau: float = 1.0, restart: int = 80, max_iter: int = 800,
                    tol: float = 1e-10, v0: torch.Tensor | None = None):
         """Stationary state of the generator with the time-dependent
         coefficients frozen at ``coef``: G v = -K by GMRES on the RK4

@@ -47,12 +47,12 @@ def _oracle(p, ops):
     return lb.stationary_bloch(G, K), G, K
 
 
-@pytest.mark.parametrize("N", [4, 51, 101, 301])
-def test_stationary_against_oracle(lib, N):
-    flush(f"[stationary] N={N}")
+@pytest.mark.parametrize("N,tau", [(4, 1.0), (51, 1.0), (101, 1.0), (301, 1.0), (51, 5.0)])
+def test_stationary_against_oracle(lib, N, tau):
+    flush(f"[stationary] N={N} tau={tau}")
     p, ops, basis, lind, prop = _system(lib, N)
-    v, iters, relres = prop.stationary([p.E], tau=5.0)
-    flush(f"[stationary] N={N}: {iters} GMRES iterations, relres {relres:.2e}")
+    v, iters, relres = prop.stationary([p.E], tau=tau)
+    flush(f"[stationary] N={N} tau={tau}: {iters} GMRES iterations, relres {relres:.2e}")
     v = v.cpu().numpy()
     v_o, G, K = _oracle(p, ops)
     assert relres <= 1e-10
