@@ -70,12 +70,6 @@ struct GroupDev {
   const int* ucol;
   const unsigned short* lidx;   // path 3: position of every stored entry's column in its block's list
   int p5;                // 1: one wavefront per (row, tile), matrix through the scalar cache (path 5)
-  int p6;                // 1: row pairs with a merged column list (path 6)
-  int npblk;             // path 6: blocks of pairs [pblk[i], pblk[i+1])
-  const int* pblk;
-  const int* pptr;       // path 6: union entries of pair q are [pptr[q], pptr[q+1])
-  const int* pcol;       // path 6: stored column of each union entry
-  const double* pval;    // path 6: [entry][row of the pair][term] values, 0 where absent
 };
 
 }  // namespace
@@ -101,10 +95,6 @@ struct sun_batch_s {
                             // per lane, 3: as 2 with the gathered state rows staged in LDS
   std::vector<int> xl;      // 1 when the group runs path 3
   std::vector<DevBuf<int>> xu_ptr, xu_col;
-  // path 6: row pairs (2q, 2q+1) with one merged column list each
-  std::vector<DevBuf<int>> pr_ptr, pr_col, pr_blk;
-  std::vector<DevBuf<double>> pr_val;
-  std::vector<int> npblk;
   std::vector<DevBuf<unsigned short>> xu_lidx;
   // path 4: instance-major state ([B][M+1], grouped order, entry M = 1) on a
   // segmented sliced layout of the group's generator (the terms whose
@@ -828,142 +818,6 @@ __global__ __launch_bounds__(64) void k_batch_rows(const GroupDev* __restrict__ 
   }
 }
 
-// Path 6: one wavefront per pair of stored rows (2q, 2q+1) and tile of 128
-// instances (two per lane), over the pair's merged column list: every
-// distinct column is gathered once for both rows and all terms (the rows of
-// an S_p / J_p pair use largely the same columns), and each (row, term) sum
-// takes its products in the original order (entries the row and term do not
-// have contribute an exact 0 while the state is finite), so results are
-// bitwise those of the other paths.  A workgroup stages one block of pairs
-// (columns, values, pair pointers) and the tile's term coefficients in LDS,
-// items numbered tile-major with one eighth of every group per XCD.
-constexpr int kPairTerms = 4;
-constexpr int kPairMax = 64;
-constexpr int kPairCol = 512;
-constexpr int kPairVal = 3072;
-
-template <int STAGE, int NT>
-__device__ inline void pair_rows(const GroupDev& G, int tb, int q0, int np, const int* s_col, const double* s_val,
-                                 const int* s_pp, const double* s_cf) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int ld = G.ld, ld2 = ld / 2;
-  constexpr int nv = 2 * NT;
-  const double* xin = STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
-  double* xout = STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
-  const int b = tb * 128 + 2 * lane;   // instances b and b + 1
-  const bool own0 = b < G.B, own1 = b + 1 < G.B;
-  const double2* xb = reinterpret_cast<const double2*>(xin + b);
-  for (int lp = wv; lp < np; lp += 4) {
-    const int r0 = 2 * (q0 + lp);
-    const int nrow = min(2, G.M - r0);
-    double acc[2][NT][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int a = 0; a < NT; ++a) acc[r][a][0] = acc[r][a][1] = 0.0;
-    auto add = [&](const double* v, double2 xx) {
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int a = 0; a < NT; ++a) {
-          const double w = v[r * NT + a];
-          acc[r][a][0] += w * xx.x;
-          acc[r][a][1] += w * xx.y;
-        }
-    };
-    const int ue = s_pp[lp + 1];
-    int u = s_pp[lp];
-    for (; u + 4 <= ue; u += 4) {
-      double2 xx[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) xx[k] = xb[(int64_t)s_col[u + k] * ld2];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) add(s_val + (u + k) * nv, xx[k]);
-    }
-    for (; u < ue; ++u) add(s_val + u * nv, xb[(int64_t)s_col[u] * ld2]);
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      if (r >= nrow) break;
-      const int64_t ix = (int64_t)(r0 + r) * ld + b;
-      // the row's own state entries, loaded after the gathers (fewer live registers)
-      const double2 vr = own0 ? *reinterpret_cast<const double2*>(G.v + ix) : make_double2(0.0, 0.0);
-      const double2 ar = (own0 && STAGE != 0) ? *reinterpret_cast<const double2*>(G.acc + ix) : make_double2(0.0, 0.0);
-      double y0 = 0.0, y1 = 0.0;
-#pragma unroll
-      for (int a = 0; a < NT; ++a) {
-        const double2 cf = *reinterpret_cast<const double2*>(s_cf + a * kCfStride + 2 * lane);
-        y0 += cf.x * acc[r][a][0];
-        y1 += cf.y * acc[r][a][1];
-      }
-      double a0 = 0.0, a1 = 0.0;
-      const double o0 = lds_stage<STAGE>(vr.x, ar.x, y0, G.dt, a0);
-      const double o1 = lds_stage<STAGE>(vr.y, ar.y, y1, G.dt, a1);
-      if (own0 && own1) {
-        *reinterpret_cast<double2*>(xout + ix) = make_double2(o0, o1);
-        if (STAGE != 3) *reinterpret_cast<double2*>(G.acc + ix) = make_double2(a0, a1);
-      } else if (own0) {
-        xout[ix] = o0;
-        if (STAGE != 3) G.acc[ix] = a0;
-      }
-    }
-  }
-}
-
-template <int STAGE, int NT>
-__global__ __launch_bounds__(256) void k_batch_pairs(const GroupDev* __restrict__ groups,
-                                                     const int* __restrict__ gorder, int nactive,
-                                                     const int64_t* __restrict__ step) {
-  __shared__ int s_col[kPairCol];
-  __shared__ double s_val[kPairVal];
-  __shared__ int s_pp[kPairMax + 1];
-  __shared__ double s_cf[kPairTerms * kCfStride];
-  const int tid = threadIdx.x;
-  const int x = blockIdx.x & 7;
-  const int64_t K = gridDim.x >> 3;
-  // this instantiation takes the path-6 groups with NT terms
-  auto items = [&](const GroupDev& G) -> int64_t { return G.p6 && G.nt == NT ? (int64_t)G.npblk * G.tiles : 0; };
-  int64_t total = 0;
-  for (int q = 0; q < nactive; ++q) {
-    const int64_t n = items(groups[gorder[q]]);
-    total += n * (x + 1) / 8 - n * x / 8;
-  }
-  for (int64_t i = blockIdx.x >> 3; i < total; i += K) {
-    int gi = 0;
-    int64_t j = i, lo = 0;
-    for (;;) {
-      const int64_t n = items(groups[gorder[gi]]);
-      lo = n * x / 8;
-      const int64_t cnt = n * (x + 1) / 8 - lo;
-      if (j < cnt || gi + 1 == nactive) break;
-      j -= cnt;
-      ++gi;
-    }
-    const GroupDev& G = groups[gorder[gi]];
-    const int64_t local = lo + j;
-    const int tb = (int)(local / G.npblk);
-    const int blk = (int)(local % G.npblk);
-    const int q0 = G.pblk[blk], q1 = G.pblk[blk + 1];
-    const int np = q1 - q0;
-    const int u0 = G.pptr[q0];
-    const int nu = G.pptr[q1] - u0;
-    constexpr int nt = NT;
-    const int64_t k0 = 2 * step[gorder[gi]];
-    const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
-    const double ph = G.wave[k0 + krow];
-    __syncthreads();   // the previous item's LDS contents are no longer read
-    for (int i2 = tid; i2 < nu; i2 += 256) s_col[i2] = G.pcol[u0 + i2];
-    for (int i2 = tid; i2 < nu * 2 * nt; i2 += 256) s_val[i2] = G.pval[(int64_t)u0 * 2 * nt + i2];
-    for (int i2 = tid; i2 <= np; i2 += 256) s_pp[i2] = G.pptr[q0 + i2] - u0;
-    for (int i2 = tid; i2 < nt * 128; i2 += 256) {
-      const int a = i2 / 128, bl = i2 % 128;
-      const int b = tb * 128 + bl;
-      s_cf[a * kCfStride + bl] = b < G.B ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
-    }
-    __syncthreads();
-    pair_rows<STAGE, NT>(G, tb, q0, np, s_col, s_val, s_pp, s_cf);
-  }
-}
-
 // Row blocks for path 3: at most max_rows rows, kLdsCap entries and ucap
 // distinct columns; with each block's sorted distinct columns and every
 // entry's position in them.  False if a single row does not fit.
@@ -1061,18 +915,6 @@ void refresh_items(sun_batch_s& bt) {
       G.tiles = (G.B + 64 * G.vec - 1) / (64 * G.vec);
       G.row_blocks = 0;        // no items of the block kernels
     }
-    G.p6 = bt.path[g] == 6;
-    G.npblk = G.p6 ? bt.npblk[g] : 0;
-    G.pblk = G.p6 ? bt.pr_blk[g].get() : nullptr;
-    G.pptr = G.p6 ? bt.pr_ptr[g].get() : nullptr;
-    G.pcol = G.p6 ? bt.pr_col[g].get() : nullptr;
-    G.pval = G.p6 ? bt.pr_val[g].get() : nullptr;
-    if (G.p6) {              // one wavefront per (row pair, tile of 128 instances)
-      G.vec = 2;
-      G.tile = 64;
-      G.tiles = (G.B + 127) / 128;
-      G.row_blocks = 0;
-    }
     if (bt.path[g] == 4) {   // advanced by the multi-instance sliced kernel instead
       G.row_blocks = 0;
       G.tiles = 0;
@@ -1090,114 +932,17 @@ void refresh_items(sun_batch_s& bt) {
 // Per-wavefront and LDS work items of a group (one of the two is zero).
 int64_t wave_items(const GroupDev& G) { return G.nblk > 0 ? 0 : (int64_t)G.row_blocks * G.tiles; }
 
-// Path 6 layout: for every pair of stored rows (2q, 2q+1; the last row alone
-// when M is odd) one list of the distinct columns the two rows use in any
-// term, in the order of the grouped column index (the order every term
-// segment keeps its entries in), each with 2 * nt values [row][term], 0 where
-// that row and term have no entry at the column.  A (row, term) sum over the
-// list therefore adds that term's products in the original order, plus exact
-// zeros.  Pairs are cut into blocks of at most kPairMax pairs, kPairCol
-// entries and kPairVal values (the kernel's LDS tables).
-struct PairLayout {
-  std::vector<int> ptr, col, blk;
-  std::vector<double> val;
-};
-
-PairLayout make_pairs(const sun_batch_s& bt, int g) {
-  const int M = (int)bt.M[g], nt = bt.nt[g];
-  const int64_t P = bt.P[g], nnz = bt.nnz[g];
-  SUN_REQUIRE(nt <= kPairTerms, SUN_ENOTSUP, "path 6 takes at most 4 terms per group");
-  std::vector<int> rp(M + 1), sg((size_t)M * nt), col(nnz);
-  std::vector<double> val(nnz);
-  HIP_OK(hipMemcpy(rp.data(), bt.rowptr[g].get(), (M + 1) * sizeof(int), hipMemcpyDeviceToHost));
-  HIP_OK(hipMemcpy(sg.data(), bt.segptr[g].get(), sg.size() * sizeof(int), hipMemcpyDeviceToHost));
-  if (nnz > 0) {
-    HIP_OK(hipMemcpy(col.data(), bt.col[g].get(), nnz * sizeof(int), hipMemcpyDeviceToHost));
-    HIP_OK(hipMemcpy(val.data(), bt.val[g].get(), nnz * sizeof(double), hipMemcpyDeviceToHost));
-  }
-  // grouped index of a stored column (S_p at 2p, J_p at 2p+1, D and M unchanged)
-  auto grouped = [&](int c) -> int64_t { return c < 2 * P ? ((c & 1) ? P + c / 2 : c / 2) : c; };
-  const int npairs = (M + 1) / 2;
-  PairLayout out;
-  std::vector<int>& ptr = out.ptr;
-  std::vector<int>& ucol = out.col;
-  std::vector<double>& uval = out.val;
-  ptr.assign(npairs + 1, 0);
-  struct Ent { int64_t key; int c, slot; double v; };
-  std::vector<Ent> ents;
-  for (int q = 0; q < npairs; ++q) {
-    ents.clear();
-    for (int r = 0; r < 2 && 2 * q + r < M; ++r) {
-      const int row = 2 * q + r;
-      for (int a = 0; a < nt; ++a) {
-        const int e0 = sg[(size_t)row * nt + a], e1 = a + 1 < nt ? sg[(size_t)row * nt + a + 1] : rp[row + 1];
-        for (int e = e0; e < e1; ++e) ents.push_back(Ent{grouped(col[e]), col[e], r * nt + a, val[e]});
-      }
-    }
-    std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.key < y.key; });
-    for (size_t i = 0; i < ents.size();) {
-      size_t j = i;
-      ucol.push_back(ents[i].c);
-      const size_t base = uval.size();
-      uval.resize(base + 2 * nt, 0.0);
-      // (a row's term never repeats a column: its segment is a sorted CSR row)
-      for (; j < ents.size() && ents[j].key == ents[i].key; ++j) uval[base + ents[j].slot] = ents[j].v;
-      i = j;
-    }
-    SUN_REQUIRE(ucol.size() < (size_t)INT32_MAX, SUN_ENOTSUP, "path 6 layout has 2^31 or more entries");
-    ptr[q + 1] = (int)ucol.size();
-  }
-  // blocks of pairs within the kernel's LDS tables
-  std::vector<int>& blk = out.blk;
-  blk.assign(1, 0);
-  for (int q0 = 0; q0 < npairs;) {
-    int q1 = q0;
-    while (q1 < npairs && q1 - q0 < kPairMax && ptr[q1 + 1] - ptr[q0] <= kPairCol &&
-           (int64_t)(ptr[q1 + 1] - ptr[q0]) * 2 * nt <= kPairVal)
-      ++q1;
-    SUN_REQUIRE(q1 > q0, SUN_ENOTSUP, "path 6: a row pair has more distinct columns than the LDS tables hold");
-    blk.push_back(q1);
-    q0 = q1;
-  }
-  return out;
-}
-
-void install_pairs(sun_batch_s& bt, int g, const PairLayout& pl) {
-  const std::vector<int>& ptr = pl.ptr;
-  const std::vector<int>& ucol = pl.col;
-  const std::vector<double>& uval = pl.val;
-  const std::vector<int>& blk = pl.blk;
-  bt.pr_ptr[g].alloc(ptr.size());
-  bt.pr_col[g].alloc(std::max<size_t>(1, ucol.size()));
-  bt.pr_val[g].alloc(std::max<size_t>(1, uval.size()));
-  bt.pr_blk[g].alloc(blk.size());
-  HIP_OK(hipMemcpy(bt.pr_ptr[g].get(), ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
-  if (!ucol.empty()) {
-    HIP_OK(hipMemcpy(bt.pr_col[g].get(), ucol.data(), ucol.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(bt.pr_val[g].get(), uval.data(), uval.size() * sizeof(double), hipMemcpyHostToDevice));
-  }
-  HIP_OK(hipMemcpy(bt.pr_blk[g].get(), blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice));
-  bt.npblk[g] = (int)blk.size() - 1;
-}
-
 void repartition(sun_batch_s& bt, int g) {
   const int max_rows = std::min(bt.rows_per_item[g], kLdsRows);
   std::vector<int> blk;
   bt.xl[g] = 0;
-  if (bt.path[g] != 6) {
-    bt.pr_ptr[g].release();
-    bt.pr_col[g].release();
-    bt.pr_blk[g].release();
-    bt.pr_val[g].release();
-    bt.npblk[g] = 0;
-  }
   if (bt.path[g] >= 4) {
     bt.xu_ptr[g].release();
     bt.xu_col[g].release();
     bt.xu_lidx[g].release();
     bt.nblk[g] = 0;
     bt.blk_row[g].release();
-    return;                   // path 6: sun_batch_tune installs the pair layout
+    return;
   }
   if (bt.path[g] == 3) {
     std::vector<int> hcol(bt.nnz[g]);
@@ -1339,8 +1084,6 @@ struct StageLaunch {
   int64_t nitems = 0, grid = 1, bgrid = 8, xgrid = 8;
   bool v1 = false, v2 = false, xl = false;
   bool r1 = false, r2 = false;   // path-5 groups with one / two instances per lane
-  bool pr[kPairTerms + 1] = {};  // path-6 groups, by term count
-  int64_t pgrid = 8;             // path-6 grid
   int64_t rgrid[3] = {0, 0, 0};  // path-5 grids (resident wavefronts, a multiple of 8), by VEC
   int r_nt = 1;                  // most terms of a path-5 group
 };
@@ -1376,10 +1119,6 @@ void launch_stage(const StageLaunch& L) {
   if (L.xl)
     hipLaunchKernelGGL(k_batch_stage_xlds<STAGE>, dim3((unsigned)L.xgrid), dim3(256), cf_bytes + kXLdsBytes, L.s,
                        L.gd, L.go, L.nactive, L.st, L.cf_len);
-  if (L.pr[1]) hipLaunchKernelGGL((k_batch_pairs<STAGE, 1>), dim3((unsigned)L.pgrid), dim3(256), 0, L.s, L.gd, L.go, L.nactive, L.st);
-  if (L.pr[2]) hipLaunchKernelGGL((k_batch_pairs<STAGE, 2>), dim3((unsigned)L.pgrid), dim3(256), 0, L.s, L.gd, L.go, L.nactive, L.st);
-  if (L.pr[3]) hipLaunchKernelGGL((k_batch_pairs<STAGE, 3>), dim3((unsigned)L.pgrid), dim3(256), 0, L.s, L.gd, L.go, L.nactive, L.st);
-  if (L.pr[4]) hipLaunchKernelGGL((k_batch_pairs<STAGE, 4>), dim3((unsigned)L.pgrid), dim3(256), 0, L.s, L.gd, L.go, L.nactive, L.st);
   if (L.r1)
     hipLaunchKernelGGL((k_batch_rows<STAGE, 1>), dim3((unsigned)L.rgrid[1]), dim3(64),
                        (size_t)L.r_nt * 64 * sizeof(double), L.s, L.gd, L.go, L.nactive, L.st);
@@ -1431,11 +1170,6 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->path.assign(ngroups, 0);
       bt->xl.assign(ngroups, 0);
       bt->xu_ptr.resize(ngroups);
-      bt->pr_ptr.resize(ngroups);
-      bt->pr_col.resize(ngroups);
-      bt->pr_blk.resize(ngroups);
-      bt->pr_val.resize(ngroups);
-      bt->npblk.assign(ngroups, 0);
       bt->xu_col.resize(ngroups);
       bt->xu_lidx.resize(ngroups);
       bt->mprop.assign(ngroups, nullptr);
@@ -1571,14 +1305,11 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
   return guarded([&] {
     SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
-    SUN_REQUIRE(path >= 0 && path <= 6, SUN_EINVAL, "path must be 0 to 6");
+    SUN_REQUIRE(path >= 0 && path <= 5, SUN_EINVAL, "path must be 0, 1, 2, 3, 4 or 5");
     if (path == 4) {
       SUN_REQUIRE(tile == 2 || tile == 4 || tile == 8, SUN_EINVAL, "path 4 takes 2, 4 or 8 instances per wavefront");
     } else if (path == 5) {
       SUN_REQUIRE(tile == 64 || tile == 128, SUN_EINVAL, "path 5 takes tiles of 64 or 128 instances");
-    } else if (path == 6) {
-      SUN_REQUIRE(tile == 128, SUN_EINVAL, "path 6 takes tiles of 128 instances");
-      SUN_REQUIRE(bt->nt[g] <= kPairTerms, SUN_ENOTSUP, "path 6 takes at most 4 terms per group");
     } else {
       SUN_REQUIRE(tile == 8 || tile == 16 || tile == 32 || tile == 64 || tile == 128, SUN_EINVAL,
                   "tile must be 8, 16, 32, 64 or 128");
@@ -1588,9 +1319,6 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
     hipStream_t s = as_stream(stream);
     HIP_OK(hipStreamSynchronize(s));
     if (path == 4) setup_multi(*bt, g, s);
-    // path 6: the pair layout is built (and may be refused) before anything changes
-    PairLayout pairs;
-    if (path == 6) pairs = make_pairs(*bt, g);
     // the state moves with the layout
     const int old = bt->path[g];
     const int M = (int)bt->M[g];
@@ -1609,7 +1337,6 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
     bt->rows_per_item[g] = rows_per_item;
     bt->path[g] = path;
     repartition(*bt, g);
-    if (path == 6) install_pairs(*bt, g, pairs);
     refresh_items(*bt);
     upload(*bt, s);
   });
@@ -1683,17 +1410,10 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       L.nactive = nactive;
       L.nitems = items_upto[nactive];
       L.grid = std::max<int64_t>(1, std::min<int64_t>((L.nitems + 3) / 4, (int64_t)ncu * 8));
-      int64_t nlds = 0, nx = 0, npr = 0;
+      int64_t nlds = 0, nx = 0;
       int max_nt = 1;
       for (int q = 0; q < nactive; ++q) {
         const GroupDev& G = bt->ghost[ord[q]];
-        if (G.p6) {
-          SUN_REQUIRE(G.tiles * 128 <= G.ld && G.nt >= 1 && G.nt <= kPairTerms && G.npblk > 0, SUN_ENOTSUP,
-                      "internal: path 6 layout does not fit the group");
-          L.pr[G.nt] = true;
-          npr += (int64_t)G.npblk * G.tiles;
-          continue;
-        }
         if (G.p5) {
           // the kernel's tile of 64 * vec instances stays inside the padded state rows
           SUN_REQUIRE(G.tiles * 64 * G.vec <= G.ld && G.nt <= kMaxBTerms, SUN_ENOTSUP,
@@ -1716,7 +1436,6 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       L.bgrid = std::max<int64_t>(8, (std::min<int64_t>(nlds, (int64_t)ncu * 8) + 7) / 8 * 8);
       L.xgrid = std::max<int64_t>(8, (std::min<int64_t>(nx, (int64_t)ncu * 3) + 7) / 8 * 8);
       L.cf_len = max_nt * kCfStride;
-      L.pgrid = std::max<int64_t>(8, (std::min<int64_t>(npr, (int64_t)ncu * 8) + 7) / 8 * 8);
       L.r_nt = p5_nt;
       L.rgrid[1] = p5_grid[1];
       L.rgrid[2] = p5_grid[2];

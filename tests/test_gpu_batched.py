@@ -66,7 +66,7 @@ def test_tiling_does_not_change_results(lib):
     results = []
     for tile, rows, path in ((64, 64, 0), (8, 1, 0), (16, 7, 1), (32, 512, 1), (64, 3, 1), (16, 128, 0),
                              (128, 32, 0), (128, 5, 1), (16, 64, 2), (32, 9, 2), (64, 128, 2), (8, 16, 2),
-                             (8, 4, 3), (16, 64, 3), (32, 128, 3), (128, 64, 5), (64, 1, 5), (128, 64, 6)):
+                             (8, 4, 3), (16, 64, 3), (32, 128, 3), (128, 64, 5), (64, 1, 5)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -94,7 +94,7 @@ def test_lds_and_global_paths_agree_bitwise(lib):
     out = []
     for tile, rows, path in ((64, 64, 0), (16, 128, 0), (32, 16, 1), (64, 8, 1), (128, 64, 0), (128, 8, 0),
                              (16, 64, 2), (32, 32, 2), (64, 128, 2), (8, 128, 3), (16, 32, 3), (32, 128, 3),
-                             (128, 64, 5), (64, 64, 5), (128, 64, 6)):
+                             (128, 64, 5), (64, 64, 5)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -107,11 +107,9 @@ def test_lds_and_global_paths_agree_bitwise(lib):
 
 def test_row_wavefront_path_multi_tile_bitwise(lib):
     """Path 5 (one wavefront per row and tile, matrix through the scalar
-    cache) and path 6 (row pairs with a merged column list) on groups of 300
-    and 130 instances, i.e. 3 and 2 tiles of 128 and 5 and 3 tiles of 64
-    with ragged last tiles, against path 0: bitwise equal after 16 steps, and
-    the first instances against the dense oracle (N = 5 has an odd M, so its
-    last pair holds one row)."""
+    cache) on groups of 300 and 130 instances, i.e. 3 and 2 tiles of 128 and
+    5 and 3 tiles of 64 with ragged last tiles, against path 0: bitwise equal
+    after 16 steps, and the first instances against the dense oracle."""
     flush("[batched] path 5, several tiles per group, vs path 0")
     rng = np.random.default_rng(11)
     inst = []
@@ -126,7 +124,7 @@ def test_row_wavefront_path_multi_tile_bitwise(lib):
     bp, groups = dimer_batch(lib, inst, steps)
     starts = [torch.as_tensor(np.stack([fock_bloch(N, j % N) for j in range(len(idx))])) for (N, idx, _, _, _) in groups]
     out = []
-    for tile, rows, path in ((64, 64, 0), (128, 64, 5), (64, 64, 5), (128, 64, 6)):
+    for tile, rows, path in ((64, 64, 0), (128, 64, 5), (64, 64, 5)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
