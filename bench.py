@@ -76,6 +76,7 @@ def union_nnz(lind, torch):
 
 STAGE_SOURCE = "paper_1812_11626_amd/csrc/propagate.hip"
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_rk4_sell_dimer-plain-N1001_counters.md")
+BATCHED_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_batch_stage_lds_dimer-batched-512_counters.md")
 
 
 def stage_source_hash() -> str:
@@ -92,16 +93,32 @@ def stage_source_hash() -> str:
     return h.hexdigest()
 
 
+def _summary_fields(path):
+    """The `- key: `value`` lines of a committed profile summary."""
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    return fields
+
+
+def batched_profiled_traffic():
+    """(bytes beyond L2 per batched stage launch, the tiling it was taken
+    with) from the committed counter summary, or (None, None)."""
+    try:
+        fields = _summary_fields(BATCHED_COUNTER_SUMMARY)
+        return float(fields["bytes_beyond_l2_per_launch"]), fields["tiling"]
+    except (OSError, KeyError, ValueError):
+        return None, None
+
+
 def measured_traffic():
     """HBM bytes per stage launch from the committed counter summary, if it
     was taken on the current stage-kernel source (else None)."""
     try:
-        fields = {}
-        with open(COUNTER_SUMMARY) as fh:
-            for line in fh:
-                if ":" in line and line.startswith("- "):
-                    k, v = line[2:].split(":", 1)
-                    fields[k.strip()] = v.strip().strip("`")
+        fields = _summary_fields(COUNTER_SUMMARY)
         if fields.get("source_sha256") != stage_source_hash():
             return None
         return float(fields["hbm_bytes_per_launch"])
@@ -352,10 +369,15 @@ def batched_report(sb, torch):
     # plus 20 bytes per state row and instance (gather, base, accumulator and
     # output streams: 80 M per instance-step)
     alg_bytes = 0
+    launch_bytes = 0          # one stage launch with every group active
     for g, (N, idx, basis, lind, p0) in enumerate(meta):
         info = bp.info(g)
         M = info["M"]
         alg_bytes += p0.steps * 4 * (12 * info["nnz"] + 4 * (M + 1)) + p0.steps * len(idx) * 80 * M
+        launch_bytes += 12 * info["nnz"] + 4 * (M + 1) + 20 * M * len(idx)
+    tiling = ",".join(f"{tuned[g]['tile']}/{tuned[g]['rows_per_item']}/{tuned[g]['path']}" for g in range(len(meta)))
+    prof_bytes, prof_tiling = batched_profiled_traffic()
+    traffic = prof_bytes if prof_tiling == tiling else None
     # sequential plain solves: per-step time of one plain instance per N
     seq_time = 0.0
     per_N = {}
@@ -385,7 +407,13 @@ def batched_report(sb, torch):
             "sequential_plain_instance_steps_per_s": seq_rate, "sequential_plain_20_periods_s_est": seq_time,
             "speedup_vs_sequential_plain": batched_rate / seq_rate,
             "roofline": {"bound": "hbm", "algorithmic_bytes": alg_bytes, "achieved": alg_bytes / el / 1e9,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg_bytes / el / 1e9 / HBM_PEAK_GBS},
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg_bytes / el / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": launch_bytes, "tiling": tiling,
+                         "traffic": traffic,
+                         "profiled_traffic": {"bytes_beyond_l2_per_launch": prof_bytes, "tiling": prof_tiling},
+                         "traffic_note": "bytes beyond L2 per stage launch with every group active, from the "
+                                         "committed counter summary; null when this run's autotuned tiling "
+                                         "differs from the profiled one (profiled_traffic gives it anyway)"},
             "groups": per_N, "setup_s": setup_s}
 
 
