@@ -107,6 +107,30 @@ def test_N301_benchmark_configuration(lib):
         assert abs(fd - g[i]) <= 1e-7 * abs(g[i]) + 1e-11, (i, fd, g[i])
 
 
+def test_N301_ten_periods_central_differences(lib):
+    """The adjoint workload at N = 301 over 10 of its 100 periods (40,960
+    steps, a checkpoint every period as the benchmark runs it, so the
+    backward sweep recomputes 9 intervals from their checkpoints), J over the
+    last period: dJ/d(A, gamma, U) against central differences of the GPU's
+    own forward objective to 1e-7 (a property of the exact discrete gradient
+    at any horizon; the oracle's gradient is pinned at 256 steps above)."""
+    flush("[adjoint] N=301 ten periods vs central differences")
+    p = dimer.adjoint_config(301)
+    S = p.steps_per_period
+    steps = 10 * S
+    prob, _, _ = dimer_adjoint_problem(lib, p, steps, S, ckpt_every=S)
+    J, g = prob.value_and_grad(THETA.copy())
+    assert np.isfinite(J) and np.all(np.isfinite(g))
+    assert abs(J - prob.value(THETA.copy())) <= 1e-12 * abs(J)
+    h = 1e-6
+    for i in range(3):
+        tp, tm = THETA.copy(), THETA.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (prob.value(tp) - prob.value(tm)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * abs(g[i]) + 1e-11, (i, fd, g[i])
+
+
 def test_N1001_plain_workload_gradient(lib):
     """The plain N = 1001 workload (M = 1,002,000) on the adjoint path the
     benchmark times there (fused reverse stages, several checkpoint intervals

@@ -171,6 +171,31 @@ def test_full_workload_sampled_against_plain(lib):
         assert rel_vec_err(got[len(idx) // 2], lb.bloch_vector_sparse(rho)) <= TOL, N
 
 
+def test_N51_group_full_horizon_against_plain(lib):
+    """The N = 51 group of the 512-instance workload (104 instances) over its
+    full horizon of 20 periods (25,600 steps) with the two-instances-per-lane
+    LDS kernel the autotuner picks for it: the first, middle and last
+    instances against plain single-instance GPU propagation of the same
+    drive, 1e-12 relative at the end."""
+    flush("[batched] N=51 group, 20 periods vs plain")
+    inst = [p for p in dimer.batched_instances() if p.N == 51]
+    steps = inst[0].steps
+    assert steps == 20 * inst[0].steps_per_period
+    bp, groups = dimer_batch(lib, inst, steps)
+    N, idx, lind, dt, st = groups[0]
+    bp.tune(0, 32, 32, 2)
+    bp.set_state(0, torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))))
+    bp.run(steps)
+    got = bp.get_state(0).cpu().numpy()
+    for j in (0, len(idx) // 2, len(idx) - 1):
+        p = inst[idx[j]]
+        prop = lind.propagator([1.0, 0.0, p.gamma_eff], [1])
+        v = torch.as_tensor(fock_bloch(N, 0)).cuda()
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+        prop.propagate(v, eps, dt, steps)
+        assert rel_vec_err(got[j], v.cpu().numpy()) <= TOL, j
+
+
 def test_autotuner_picks_valid_tiling(lib, tmp_path, monkeypatch):
     monkeypatch.setenv("SUN_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     inst = _small_instances()
