@@ -222,13 +222,15 @@ def small_configs_report(sb, torch, steps=2000):
         torch.cuda.synchronize()
         t_asm = time.perf_counter() - t0
         v = _fock_v0(sb, basis, N)
-        eps = torch.as_tensor(dimer.drive_table(p, steps=steps + 50)).cuda().contiguous()
-        prop.propagate(v, eps, p.dt, 50)
+        # warm-up of 128 steps: builds the layouts and, where used, captures
+        # the 64-step graph, so that the timed call only replays
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps + 128)).cuda().contiguous()
+        prop.propagate(v, eps, p.dt, 128)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        prop.propagate(v, eps[100:], p.dt, steps)
+        prop.propagate(v, eps[256:], p.dt, steps)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -387,7 +389,7 @@ def batched_report(sb, torch):
         v = _fock_v0(sb, basis, N)
         nst = 200
         eps = torch.as_tensor(dimer.drive_table(p, steps=nst)).cuda().contiguous()
-        prop.propagate(v, eps, p.dt, 20)
+        prop.propagate(v, eps, p.dt, 128)            # warm-up, including the graph capture where used
         torch.cuda.synchronize()
         ta = time.perf_counter()
         prop.propagate(v, eps, p.dt, nst)
@@ -664,13 +666,13 @@ def scan_report(sb, torch, Ns=(51, 101, 201, 301, 501, 701, 1001, 1501, 2001), s
         t_asm = time.perf_counter() - t0
         M = N * N - 1
         v = _fock_v0(sb, basis, N)
-        eps = torch.as_tensor(dimer.drive_table(p, steps=steps + 40)).cuda().contiguous()
-        prop.propagate(v, eps, p.dt, 20)
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps + 128)).cuda().contiguous()
+        prop.propagate(v, eps, p.dt, 128)            # warm-up, including the graph capture where used
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        prop.propagate(v, eps[40:], p.dt, steps)
+        prop.propagate(v, eps[256:], p.dt, steps)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)

@@ -385,6 +385,17 @@ int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t mi
  * off (sun_prop_tune and sun_prop_tune_sliced also do); on = 1 where it
  * does not apply returns SUN_ENOTSUP. */
 int sun_prop_tune_resident(sun_prop p, int32_t on);
+/* HIP-graph replay in sun_propagate.  Where a stage launch is dominated by
+ * launch latency (M <= 160,000, e.g. the dimer up to N = 400), sun_propagate
+ * captures 64 RK4 steps (256 stage launches on the propagator's own
+ * vectors) into a graph once per layout and step size and replays it, after
+ * copying the chunk's 129 coefficient rows into a fixed device buffer; the
+ * remaining steps are launched directly.  Results are bitwise those of
+ * direct launches.  mode 0: never; 1: where M <= 160,000 (default); 2:
+ * always (64 or more steps).  A re-layout (sun_prop_tune*) or a new dt
+ * recaptures.  The graph is launched on the call's stream; the capture uses
+ * a stream of the propagator's own (default priority). */
+int sun_prop_use_graphs(sun_prop p, int32_t mode);
 /* Current layout, number of stored matrix entries (with padding), rows on
  * the long-row path, and bytes of matrix data plus per-row metadata one
  * stage launch streams (sliced layout: excluding the long rows' entries). */

@@ -78,6 +78,7 @@ PROTOS = {
     "sun_debug_inject_failure": (C.c_int, [i32]),
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),
+    "sun_prop_use_graphs": (C.c_int, [vp, i32]),
     "sun_prop_tune_resident": (C.c_int, [vp, i32]),
     "sun_prop_layout": (C.c_int, [vp, P(i32), P(i64), P(i64), P(i64)]),
     "sun_prop_free": (None, [vp]),

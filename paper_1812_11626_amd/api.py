@@ -309,6 +309,11 @@ class Propagator:
         check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes), flags,
                                              _stream()))
 
+    def use_graphs(self, mode: int = 1):
+        """HIP-graph replay of 64-step chunks in propagate: 0 never, 1 where
+        M <= 160,000 (default), 2 always."""
+        check(self._lib.sun_prop_use_graphs(self.handle, int(mode)))
+
     def tune_resident(self, on: bool = True):
         """Run all steps of a call in one single-workgroup launch (small systems)."""
         check(self._lib.sun_prop_tune_resident(self.handle, int(bool(on))))

@@ -43,6 +43,20 @@ struct sun_prop_s {
   DevBuf<int> bad;           // [1] set by the finite check, reset after it is read
   double dt_max = 0.0;       // > 0: stability guard, larger dt is refused (SUN_EUNSTABLE)
   double rho_guard = 0.0;    // |lambda|max estimate behind dt_max
+  // HIP-graph replay of chunks of sun_propagate steps, for generators small
+  // enough that a stage launch is dominated by launch latency
+  int graph_mode = 1;        // 0: never, 1: when M <= kGraphMaxRows (default), 2: always
+  int layout_gen = 0;        // bumped by every re-layout; a captured graph is valid for one generation
+  int graph_gen = -1;        // generation, and step size, the current graph was captured with
+  double graph_dt = 0.0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  DevBuf<double> gcoef;      // the coefficient rows of the chunk being replayed
+  sun_prop_s() = default;
+  sun_prop_s(const sun_prop_s&) = delete;
+  sun_prop_s& operator=(const sun_prop_s&) = delete;
+  ~sun_prop_s();
 };
 
 namespace sun {

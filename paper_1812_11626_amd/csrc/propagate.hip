@@ -1444,6 +1444,7 @@ void prop_dot(const sun_prop_s* const* ps, const int* term, const int* slot, con
 void prop_build_segments(sun_prop_s& p, hipStream_t s) {
   SUN_REQUIRE(p.ndyn >= 1 && p.ndyn <= kMaxRevSeg, SUN_ENOTSUP, "1 to 3 segments for the fused reverse stages");
   p.usable = 0;
+  ++p.layout_gen;
   p.long_len = std::min(p.long_len, 255);   // segment starts are stored in 8 bits
   p.sell_segs = p.ndyn;
   build_sell(p, s);
@@ -1665,6 +1666,7 @@ extern "C" int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int
                 "block_nnz must be a power of two in [128, 8192]");
     SUN_REQUIRE(threads == 64 || threads == 128 || threads == 256, SUN_EINVAL, "threads must be 64, 128 or 256");
     p->usable = 0;
+    ++p->layout_gen;
     p->block_nnz = block_nnz;
     p->threads = threads;
     p->xcd_remap = xcd_remap ? 1 : 0;
@@ -1699,6 +1701,7 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     p->sell_nt = (flags & 2) ? 1 : 0;
     p->sell_unroll = u ? u : 8;
     p->usable = 0;
+    ++p->layout_gen;
     p->resident = 0;
     p->layout = p->ndyn <= 1 ? 1 : 2;
     p->sell_segs = p->ndyn <= 1 ? 0 : p->ndyn;
@@ -1761,7 +1764,77 @@ void require_finite(const sun_prop_s& p, hipStream_t s, int64_t steps) {
                                  " RK4 steps (NaN or Inf in v; it is returned as computed)");
 }
 
+// HIP-graph replay: a chunk of kGraphSteps RK4 steps (4 launches each) on the
+// propagator's own vectors is captured once per layout and step size, with
+// the stage kernels reading their coefficient rows from a fixed buffer; each
+// replay first copies the chunk's 2 kGraphSteps + 1 rows of the caller's
+// table there (stream-ordered after the previous replay).  No memset is
+// recorded.  Used where a stage is launch-bound (M <= kGraphMaxRows).
+constexpr int64_t kGraphSteps = 64;
+constexpr int64_t kGraphMaxRows = 160000;
+
+void reset_graph(sun_prop_s& p) {
+  if (p.gexec) (void)hipGraphExecDestroy(p.gexec);
+  if (p.graph) (void)hipGraphDestroy(p.graph);
+  p.gexec = nullptr;
+  p.graph = nullptr;
+  p.graph_gen = -1;
+}
+
+bool graph_wanted(const sun_prop_s& p, int64_t steps) {
+  return p.graph_mode != 0 && !p.resident && steps >= kGraphSteps && (p.graph_mode == 2 || p.M <= kGraphMaxRows);
+}
+
+void ensure_graph(sun_prop_s& p, double dt) {
+  if (p.gexec && p.graph_gen == p.layout_gen && p.graph_dt == dt) return;
+  reset_graph(p);
+  if (!p.cap_stream) HIP_OK(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+  const double* cf = nullptr;
+  if (p.ndyn > 0) {
+    const size_t need = (size_t)(2 * kGraphSteps + 1) * p.ndyn;
+    if (p.gcoef.n < need) p.gcoef.alloc(need);
+    cf = p.gcoef.get();
+  }
+  double* va = p.vaug.get();
+  double* xa = p.xa.get();
+  double* xb = p.xb.get();
+  HIP_OK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    for (int64_t j = 0; j < kGraphSteps; ++j) {
+      launch_stage<0>(p, va, xa, cf, 2 * j, dt, p.cap_stream);
+      launch_stage<1>(p, xa, xb, cf, 2 * j + 1, dt, p.cap_stream);
+      launch_stage<2>(p, xb, xa, cf, 2 * j + 1, dt, p.cap_stream);
+      launch_stage<3>(p, xa, va, cf, 2 * j + 2, dt, p.cap_stream);
+    }
+    HIP_LAUNCH_OK();
+  } catch (...) {
+    (void)hipStreamEndCapture(p.cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIP_OK(hipStreamEndCapture(p.cap_stream, &g));
+  p.graph = g;
+  HIP_OK(hipGraphInstantiate(&p.gexec, g, nullptr, nullptr, 0));
+  p.graph_gen = p.layout_gen;
+  p.graph_dt = dt;
+}
+
 }  // namespace
+
+sun_prop_s::~sun_prop_s() {
+  reset_graph(*this);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}
+
+extern "C" int sun_prop_use_graphs(sun_prop p, int32_t mode) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr, SUN_EINVAL, "propagator is NULL");
+    SUN_REQUIRE(mode >= 0 && mode <= 2, SUN_EINVAL, "mode must be 0, 1 or 2");
+    p->graph_mode = mode;
+    if (mode == 0) reset_graph(*p);
+  });
+}
 
 extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double dt, int64_t steps, void* stream) {
   return guarded([&] {
@@ -1786,7 +1859,18 @@ extern "C" int sun_propagate(sun_prop p, double* v, const double* coef, double d
     double* va = p->vaug.get();
     double* xa = p->xa.get();
     double* xb = p->xb.get();
-    for (int64_t n = 0; n < steps; ++n) {
+    int64_t n0 = 0;
+    if (graph_wanted(*p, steps)) {
+      ensure_graph(*p, dt);
+      const size_t rows = (size_t)(2 * kGraphSteps + 1) * p->ndyn;
+      for (; n0 + kGraphSteps <= steps; n0 += kGraphSteps) {
+        if (p->ndyn > 0)
+          HIP_OK(hipMemcpyAsync(p->gcoef.get(), coef + (size_t)2 * n0 * p->ndyn, rows * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipGraphLaunch(p->gexec, s));
+      }
+    }
+    for (int64_t n = n0; n < steps; ++n) {
       launch_stage<0>(*p, va, xa, coef, 2 * n, dt, s);
       launch_stage<1>(*p, xa, xb, coef, 2 * n + 1, dt, s);
       launch_stage<2>(*p, xb, xa, coef, 2 * n + 1, dt, s);

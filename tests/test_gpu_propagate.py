@@ -476,3 +476,76 @@ def test_segmented_layout_two_and_three_dynamic_terms(lib):
             rho = pr.rk4_rho(ops["H0"], [ops["H1"]], [ops["L"], L2], [p.gamma_eff, 0.0], rho0, eps[:, None], p.dt, steps,
                              rates=np.stack([np.full_like(t, p.gamma_eff), g2], axis=1))
             assert rel_vec_err(a.cpu().numpy(), lb.bloch_vector_sparse(rho)) <= TOL
+
+
+def _graph_cases(lib):
+    """(name, propagator, coefficient table (2*steps+1 rows), dt, steps) for
+    the stream layout (N = 51), the sliced layout (N = 101) and the segmented
+    layout (N = 101, two time-dependent terms)."""
+    out = []
+    steps = 200                      # three 64-step chunks and 8 direct steps
+    for N in (51, 101):
+        p = dimer.plain_config(N)
+        ops = dimer.dimer_operators(p)
+        b = lib.build_basis(N)
+        lind, prop = lib.expand_lindbladian(b, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
+        eps = torch.as_tensor(dimer.drive_table(p, steps=3 * steps)).cuda().contiguous()
+        out.append((f"N{N}-{prop.layout()['layout']}", prop, eps, p.dt, steps, N))
+    N = 101
+    p = dimer.plain_config(N)
+    ops = dimer.dimer_operators(p)
+    s = np.sqrt((np.arange(N - 1) + 1.0) * (N - 1.0 - np.arange(N - 1)))
+    L2 = dimer.ZCSR.from_diagonals(N, {-1: s})
+    t = np.arange(2 * 3 * steps + 1) * 0.5 * p.dt
+    table = np.stack([dimer.drive_table_square(p, steps=3 * steps), 0.3 * p.gamma_eff * (1.0 + 0.5 * np.sin(2.0 * t))],
+                     axis=1)
+    b = lib.build_basis(N)
+    lind = lib.Lindbladian(b, [ops["HJ"].scaled(-p.J), ops["HU"], ops["H1"]], [ops["L"], L2])
+    prop = lind.propagator([1.0, p.U_eff, 0.0, p.gamma_eff, 0.0], [2, 4])
+    out.append(("N101-segmented", prop, torch.as_tensor(table).cuda().contiguous(), p.dt, steps, N))
+    return out
+
+
+def test_graph_replay_equals_direct_launches(lib):
+    """sun_propagate with HIP-graph replay of 64-step chunks (the default at
+    these sizes) against direct launches, bitwise, on three layouts: three
+    consecutive calls over successive parts of the coefficient table (every
+    replay refreshes the chunk's coefficient rows), with eager PyTorch work
+    and synchronisations between the calls; then a different dt (recapture)
+    and a re-layout (recapture)."""
+    for name, prop, coef, dt, steps, N in _graph_cases(lib):
+        flush(f"[propagate] graph replay {name}")
+        nd = coef.shape[1] if coef.dim() == 2 else 1
+        v0 = torch.as_tensor(_fock_v0(N)).cuda()
+        ref, got = [], []
+        for mode, out in ((0, ref), (1, got)):
+            prop.use_graphs(mode)
+            v = v0.clone()
+            for k in range(3):
+                part = coef[2 * k * steps: 2 * (k + 1) * steps + 1].contiguous()
+                prop.propagate(v, part, dt, steps)
+                out.append(v.clone())
+                junk = torch.randn(4096, device="cuda").sum()        # eager work between replays
+                torch.cuda.synchronize()
+                assert torch.isfinite(junk)
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), name
+        part = coef[: 2 * steps + 1].contiguous()
+        outs = []
+        for mode in (0, 1):
+            prop.use_graphs(mode)
+            v = v0.clone()
+            prop.propagate(v, part, 0.5 * dt, steps)               # new step size: recaptured
+            outs.append(v)
+        assert torch.equal(outs[0], outs[1]), name
+        prop.use_graphs(1)
+        if name.startswith("N101-sliced"):
+            prop.tune_sliced(sigma=2048)                            # re-layout: recaptured
+            outs = []
+            for mode in (1, 0):
+                prop.use_graphs(mode)
+                v = v0.clone()
+                prop.propagate(v, part, dt, steps)
+                outs.append(v)
+            assert torch.equal(outs[0], outs[1]), name
+            assert rel_vec_err(outs[0].cpu().numpy(), ref[0].cpu().numpy()) <= 1e-14
