@@ -396,6 +396,12 @@ int sun_prop_tune_resident(sun_prop p, int32_t on);
  * recaptures.  The graph is launched on the call's stream; the capture uses
  * a stream of the propagator's own (default priority). */
 int sun_prop_use_graphs(sun_prop p, int32_t mode);
+/* Device memory an object holds (layouts, state and work buffers), in bytes
+ * (host size_t).  Host-side bookkeeping; no device work.  With
+ * sun_set_allocator installed, this is the memory those objects took from the
+ * caller's allocator. */
+int sun_prop_device_bytes(sun_prop p, size_t* bytes);
+int sun_lind_device_bytes(sun_lind l, size_t* bytes);
 /* Current layout, number of stored matrix entries (with padding), rows on
  * the long-row path, and bytes of matrix data plus per-row metadata one
  * stage launch streams (sliced layout: excluding the long rows' entries). */
@@ -465,6 +471,8 @@ int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, 
                    void* stream);
 int sun_batch_info(sun_batch b, int32_t g, int64_t* M, int64_t* nnz, int32_t* tile,
                    int32_t* rows_per_item);
+/* Device memory the batch holds (every group's layout and states), bytes. */
+int sun_batch_device_bytes(sun_batch b, size_t* bytes);
 void sun_batch_free(sun_batch b);
 /* The batched form in one call: sun_batch_create with these arguments,
  * states loaded from V[g] (device double[B[g]][M_g], one Bloch vector per

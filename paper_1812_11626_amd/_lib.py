@@ -79,6 +79,9 @@ PROTOS = {
     "sun_prop_tune": (C.c_int, [vp, i32, i32, i32, vp]),
     "sun_prop_tune_sliced": (C.c_int, [vp, i32, i32, i32, i32, vp]),
     "sun_prop_use_graphs": (C.c_int, [vp, i32]),
+    "sun_prop_device_bytes": (C.c_int, [vp, P(C.c_size_t)]),
+    "sun_lind_device_bytes": (C.c_int, [vp, P(C.c_size_t)]),
+    "sun_batch_device_bytes": (C.c_int, [vp, P(C.c_size_t)]),
     "sun_prop_tune_resident": (C.c_int, [vp, i32]),
     "sun_prop_layout": (C.c_int, [vp, P(i32), P(i64), P(i64), P(i64)]),
     "sun_prop_free": (None, [vp]),

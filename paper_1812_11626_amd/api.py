@@ -234,6 +234,12 @@ class Lindbladian:
             self._lib.sun_lind_free(self.handle)
             self.handle = None
 
+    def device_bytes(self) -> int:
+        """Device memory the assembled terms hold."""
+        b = C.c_size_t()
+        check(self._lib.sun_lind_device_bytes(self.handle, C.byref(b)))
+        return int(b.value)
+
     def nnz(self, which: str, index: int) -> int:
         w = SUN_TERM_H if which == "H" else SUN_TERM_L
         n = C.c_int64()
@@ -308,6 +314,12 @@ class Propagator:
             ((int(unroll) & 0xFF) << 16)
         check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes), flags,
                                              _stream()))
+
+    def device_bytes(self) -> int:
+        """Device memory this propagator holds."""
+        b = C.c_size_t()
+        check(self._lib.sun_prop_device_bytes(self.handle, C.byref(b)))
+        return int(b.value)
 
     def use_graphs(self, mode: int = 1):
         """HIP-graph replay of 64-step chunks in propagate: 0 never, 1 where
@@ -516,6 +528,12 @@ class BatchedPropagator:
         segmented sliced layout (tile = 2, 4 or 8 instances per wavefront;
         needs 1 to 3 terms whose coefficients differ between instances)"""
         check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), int(path), _stream()))
+
+    def device_bytes(self) -> int:
+        """Device memory the batch holds (every group's layout and states)."""
+        b = C.c_size_t()
+        check(self._lib.sun_batch_device_bytes(self.handle, C.byref(b)))
+        return int(b.value)
 
     def info(self, g: int):
         M, nnz, tile, rows = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()

@@ -844,4 +844,15 @@ extern "C" int sun_lind_export(sun_lind l, int32_t which, int32_t index, int32_t
   });
 }
 
+extern "C" int sun_lind_device_bytes(sun_lind l, size_t* bytes) {
+  return guarded([&] {
+    SUN_REQUIRE(l != nullptr && bytes != nullptr, SUN_EINVAL, "NULL argument");
+    size_t b = 0;
+    for (const std::vector<DevCSR>* v : {&l->QH, &l->R})
+      for (const DevCSR& m : *v) b += m.rowptr.bytes() + m.col.bytes() + m.val.bytes();
+    for (const DevBuf<double>& k : l->K) b += k.bytes();
+    *bytes = b;
+  });
+}
+
 extern "C" void sun_lind_free(sun_lind l) { delete l; }

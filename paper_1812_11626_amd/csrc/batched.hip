@@ -1477,6 +1477,24 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
   });
 }
 
+extern "C" int sun_batch_device_bytes(sun_batch bt, size_t* bytes) {
+  return guarded([&] {
+    SUN_REQUIRE(bt != nullptr && bytes != nullptr, SUN_EINVAL, "NULL argument");
+    size_t b = bt->gdev.bytes();
+    for (int g = 0; g < bt->ngroups; ++g) {
+      for (const DevBuf<int>* x : {&bt->rowptr[g], &bt->segptr[g], &bt->col[g], &bt->blk_row[g], &bt->xu_ptr[g],
+                                   &bt->xu_col[g]})
+        b += x->bytes();
+      for (const DevBuf<double>* x : {&bt->val[g], &bt->v[g], &bt->xa[g], &bt->xb[g], &bt->acc[g], &bt->mv[g],
+                                      &bt->mxa[g], &bt->mxb[g], &bt->macc[g]})
+        b += x->bytes();
+      b += bt->xu_lidx[g].bytes();
+      if (bt->mprop[g]) b += prop_device_bytes(*bt->mprop[g]);
+    }
+    *bytes = b;
+  });
+}
+
 extern "C" void sun_batch_free(sun_batch bt) { delete bt; }
 
 extern "C" int sun_propagate_batched(const sun_lind* lind, int32_t ngroups, const int32_t* B, const double* const* w,

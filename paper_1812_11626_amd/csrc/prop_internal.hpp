@@ -63,6 +63,8 @@ namespace sun {
 
 // Refuse a propagator whose layout is not in a launchable state.
 void prop_require_usable(const sun_prop_s& p);
+// Device memory the propagator holds (bytes).
+size_t prop_device_bytes(const sun_prop_s& p);
 // Queue the finite check of x[0..n) (sets p.bad[0]); read and reset it with
 // prop_finite_result, which synchronises the stream.  Both are no-ops when
 // the propagator's check is off.

@@ -1827,6 +1827,27 @@ sun_prop_s::~sun_prop_s() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
+namespace sun {
+
+size_t prop_device_bytes(const sun_prop_s& p) {
+  size_t b = 0;
+  for (const DevBuf<int>* x : {&p.rowptr, &p.col, &p.seg, &p.blk_row, &p.sell_row, &p.sell_len, &p.sell_off,
+                               &p.sell_coff, &p.sell_base, &p.long_rows, &p.sell_seg, &p.bad})
+    b += x->bytes();
+  for (const DevBuf<double>* x : {&p.val, &p.vaug, &p.xa, &p.xb, &p.acc, &p.sell_val, &p.rec_part, &p.gcoef})
+    b += x->bytes();
+  return b + p.sell_cb.bytes();
+}
+
+}  // namespace sun
+
+extern "C" int sun_prop_device_bytes(sun_prop p, size_t* bytes) {
+  return guarded([&] {
+    SUN_REQUIRE(p != nullptr && bytes != nullptr, SUN_EINVAL, "NULL argument");
+    *bytes = prop_device_bytes(*p);
+  });
+}
+
 extern "C" int sun_prop_use_graphs(sun_prop p, int32_t mode) {
   return guarded([&] {
     SUN_REQUIRE(p != nullptr, SUN_EINVAL, "propagator is NULL");
