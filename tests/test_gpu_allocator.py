@@ -47,12 +47,19 @@ def _run_all(lib):
     return out
 
 
+def _requested() -> int:
+    """Bytes requested from PyTorch's caching allocator and not yet freed,
+    before its rounding (memory_allocated() counts whole blocks, which
+    depend on what the cache already holds)."""
+    return torch.cuda.memory_stats()["requested_bytes.all.current"]
+
+
 def test_torch_allocator_matches_hipmalloc(lib):
     flush("[allocator] hipMalloc run")
     ref = _run_all(lib)
     gc.collect()
     torch.cuda.synchronize()
-    base = torch.cuda.memory_allocated()
+    base = _requested()
     lib.use_torch_allocator()
     try:
         flush("[allocator] PyTorch caching allocator run")
@@ -61,17 +68,17 @@ def test_torch_allocator_matches_hipmalloc(lib):
         basis = lib.build_basis(p.N)
         lind, prop = lib.expand_lindbladian(basis, ops["H0"], ops["H1"], [(ops["L"], p.gamma_eff)])
         torch.cuda.synchronize()
-        held = torch.cuda.memory_allocated() - base
-        # the N = 301 terms and propagator layouts (> 40 MB) are now PyTorch's,
-        # and the objects' own memory queries account for all of it but the
-        # basis tables and PyTorch's rounding of each block (512 B)
+        held = _requested() - base
+        # the N = 301 terms and propagator layouts (> 40 MB) are now PyTorch's;
+        # the objects' own memory queries account for every byte of it but
+        # the basis tables (pair indices j and k, P ints each, and N doubles)
         assert held > 40e6, held
         own = lind.device_bytes() + prop.device_bytes()
-        assert own <= held <= own + 1e6, (own, held)
+        assert held == own + 2 * basis.P * 4 + basis.N * 8, (own, held)
         del lind, prop, basis
         gc.collect()
         torch.cuda.synchronize()
-        assert torch.cuda.memory_allocated() - base < 1e6
+        assert _requested() == base
         got = _run_all(lib)
     finally:
         lib.use_default_allocator()
