@@ -148,7 +148,8 @@ def cpu_baseline(p, ops):
     R and K by explicit traces, then its CSR RK4 on the same N = 1001 workload
     on every host core (2000 steps after one warm-up step) and on one thread
     (200 steps); the N = 51 workload over its full 100,000 steps on every core
-    (and 10,000 steps on one thread)."""
+    (and 10,000 steps on one thread); and the dense tier at N = 4 over its
+    full 2,000 steps on one core."""
     from oracle import o2
     from workloads import dimer
     ncpu, model = _host_info()
@@ -189,6 +190,22 @@ def cpu_baseline(p, ops):
     terms51, t_asm51 = assemble(q51, ops51, threads)
     r51_mc, el51_mc = rate(terms51, q51, 51, q51.steps, threads)
     r51_1, el51_1 = rate(terms51, q51, 51, 10000, 1)
+    # the dense tier at N = 4 (numpy on one core): the terms by explicit
+    # traces of dense generators, then the full 10-period horizon
+    from oracle import basis as ob, lindblad as lb, propagate as pr
+    q4 = dimer.plain_config(4)
+    ops4 = dimer.dimer_operators(q4)
+    t0 = time.perf_counter()
+    F4 = ob.generators(4)
+    G0 = lb.q_hamiltonian(F4, ops4["H0"].to_dense()) + q4.gamma_eff * lb.q_dissipator(F4, ops4["L"].to_dense())
+    G1 = lb.q_hamiltonian(F4, ops4["H1"].to_dense())
+    K4 = q4.gamma_eff * lb.k_dissipator(F4, ops4["L"].to_dense())
+    t_asm4 = time.perf_counter() - t0
+    eps4 = dimer.drive_table(q4, steps=q4.steps)
+    t0 = time.perf_counter()
+    v4 = pr.rk4_bloch(G0, [G1], K4, fock(4), eps4[:, None], q4.dt, q4.steps)
+    el4 = time.perf_counter() - t0
+    assert np.all(np.isfinite(v4))
     return {"value": r_mc, "unit": "RK4 steps/s", "cores": threads, "kind": "oracle",
             "sample": f"2000 RK4 steps ({el_mc:.1f} s) of the N={p.N} dimer by the oracle's C/OpenMP CSR RK4 on "
                       f"{threads} threads after one warm-up step, on Q_H0 + gamma R, Q_H1 and K assembled by the "
@@ -196,7 +213,9 @@ def cpu_baseline(p, ops):
             "single_thread_steps_per_s": r_1, "single_thread_sample": f"200 steps, {el_1:.1f} s",
             "assembly_s": t_asm, "host_cpus": ncpu, "host_model": model,
             "N51": {"steps_per_s": r51_mc, "cores": threads, "full_100_periods_s": el51_mc,
-                    "single_thread_steps_per_s": r51_1, "assembly_s": t_asm51}}
+                    "single_thread_steps_per_s": r51_1, "assembly_s": t_asm51},
+            "N4_dense": {"steps_per_s": q4.steps / el4, "cores": 1, "steps": q4.steps, "assembly_s": t_asm4,
+                         "sample": "the dense tier (numpy): explicit-trace terms, full 10 periods"}}
 
 
 def _fock_v0(sb, basis, N, i=0):
