@@ -342,6 +342,7 @@ __device__ inline void lds_rows(const GroupDev& G, int64_t k0, int tb, int r0, i
   const int b = tb * T + bl;
   const double* xb = xin + b;
   (void)ph;
+  if (b >= G.B) return;   // a lane past the last instance gathers nothing (the tile's padding)
   for (int lr = lg; lr < nr; lr += ngrp) {
     const int ee = s_rp[lr + 1];
     // the row's own state entries are loaded before its gathers
@@ -397,6 +398,7 @@ __device__ inline void lds_rows_vec2(const GroupDev& G, int64_t k0, int tb, int 
   (void)ph;
   const double2* xb = reinterpret_cast<const double2*>(xin + b);
   const int ld2 = ld / 2;
+  if (b >= G.B) return;   // a lane past the last instance gathers nothing (the tile's padding)
   for (int lr = lg; lr < nr; lr += ngrp) {
     const int ee = s_rp[lr + 1];
     const int64_t ix = (int64_t)(r0 + lr) * ld + b;
