@@ -320,7 +320,7 @@ def bifurcation_report(sb, torch, N=101, count=128):
     v0 = _fock_v0(sb, basis, N)
     start = v0.unsqueeze(0).repeat(count, 1)
     bp.set_state(0, start)
-    tuned = sb.autotune_batched(bp, probe_steps=4, log=log)
+    tuned = sb.autotune_batched(bp, probe_steps=8, log=log)
     bp.set_state(0, start)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -372,7 +372,7 @@ def batched_report(sb, torch):
         starts.append(v0.unsqueeze(0).repeat(len(idx), 1))
         bp.set_state(g, starts[-1])
     setup_s = time.perf_counter() - t0
-    tuned = sb.autotune_batched(bp, probe_steps=4, log=log)
+    tuned = sb.autotune_batched(bp, probe_steps=8, log=log)
     for g in range(len(meta)):
         bp.set_state(g, starts[g])          # from t = 0 after the tuning probes
     total = sum(len(idx) * p0.steps for (_, idx, _, _, p0) in meta)
@@ -647,7 +647,7 @@ def pmc_mode(sb, torch, steps, N=1001, target="plain"):
             info["copy_bytes"] = _calibration_copy(torch)
             print(json.dumps(info), flush=True)
             return
-        tuned = sb.autotune_batched(bp, probe_steps=4)
+        tuned = sb.autotune_batched(bp, probe_steps=8)
         for g, st in enumerate(starts):
             bp.set_state(g, st)
         bp.run(3)

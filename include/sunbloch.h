@@ -463,8 +463,15 @@ int sun_batch_run(sun_batch b, int64_t nsteps, int32_t only_group, void* stream)
  * rows_per_item unused): one wavefront per (row, tile of 64 instances with
  * one per lane, or 128 with two), the row's pointers, columns and values
  * read through the scalar cache, each XCD sweeping one eighth of the
- * group's rows in order with the device's resident wavefronts.  Defaults
- * 64, 64, 0.  Paths 0-3 and 5 add every term's entries in row order: their
+ * group's rows in order with the device's resident wavefronts.  path 7
+ * (tile 64; rows_per_item 1 to 32 is the most rows per block): persistent
+ * workgroups (two per CU) walk (tile, block) items whose blocks are taken
+ * along 4 x 4 tiles of the (j, k) pair grid with at most 127 distinct
+ * columns; each block's state rows, matrix data and coefficients are
+ * staged in LDS while the previous block is summed from LDS; rows with more
+ * distinct columns are summed from global memory by a few workgroups of
+ * their own; SUN_ENOTSUP when a group's state reaches 2 GiB.  Defaults
+ * 64, 64, 0.  Paths 0-3, 5 and 7 add every term's entries in row order: their
  * results do not depend on the tiling or path; path 4 groups the row sums
  * differently and agrees with them to rounding. */
 int sun_batch_tune(sun_batch b, int32_t g, int32_t tile, int32_t rows_per_item, int32_t path,

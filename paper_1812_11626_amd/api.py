@@ -526,7 +526,10 @@ class BatchedPropagator:
         width, 3 = path 2 with the gathered state rows staged in LDS as well
         (tiles 8, 16, 32). 4 = instance-major state on a
         segmented sliced layout (tile = 2, 4 or 8 instances per wavefront;
-        needs 1 to 3 terms whose coefficients differ between instances)"""
+        needs 1 to 3 terms whose coefficients differ between instances),
+        5 = one wavefront per (row, tile of 64 or 128), 7 = persistent
+        workgroups with each block's gathered state rows staged in LDS
+        while the previous block is summed (tile 64, rows_per_item <= 32)"""
         check(self._lib.sun_batch_tune(self.handle, int(g), int(tile), int(rows_per_item), int(path), _stream()))
 
     def device_bytes(self) -> int:

@@ -33,8 +33,12 @@
 // numbered tile-major and each XCD taking one eighth of every group;
 // k_batch_stage_xlds also stages the block's distinct gathered state rows;
 // k_batch_stage (rows of more than 1024 entries) reads the matrix from
-// global memory, one wavefront per item.
+// global memory, one wavefront per item; k_batch_rows takes one wavefront
+// per (row, tile) with the matrix read through the scalar cache;
+// k_batch_pipe keeps two persistent workgroups per CU that stage the next
+// block's gathered state rows while summing the current one from LDS.
 #include <algorithm>
+#include <cstring>
 #include <memory>
 #include <vector>
 
@@ -70,6 +74,13 @@ struct GroupDev {
   const int* ucol;
   const unsigned short* lidx;   // path 3: position of every stored entry's column in its block's list
   int p5;                // 1: one wavefront per (row, tile), matrix through the scalar cache (path 5)
+  int p7;                // 1: persistent pipelined staging (path 7)
+  int p7_nblk;           // path 7: blocks
+  const int4* p7_meta;   // path 7, per block: {blob offset and length in 16-byte units, rows, entries}
+  const int* p7_ucol;    // path 7, per block kP7Slots columns, slot s at (s % 16) * 8 + s / 16
+  const uint4* p7_blob;  // path 7: the blocks' matrix data
+  int p7_nlong;          // path 7: rows summed straight from global memory
+  const int* p7_long;
 };
 
 }  // namespace
@@ -102,6 +113,10 @@ struct sun_batch_s {
   std::vector<sun_prop> mprop;
   std::vector<std::vector<int>> mterm;   // the segment terms
   std::vector<DevBuf<double>> mv, mxa, mxb, macc;
+  // path 7: block data (meta as 4 ints per block), slot columns, blobs, long rows
+  std::vector<DevBuf<int>> p7_meta, p7_ucol, p7_long;
+  std::vector<DevBuf<uint4>> p7_blob;
+  std::vector<int> p7_nblk, p7_nlong;
   ~sun_batch_s() {
     for (sun_prop q : mprop)
       if (q) sun_prop_free(q);
@@ -820,6 +835,380 @@ __global__ __launch_bounds__(64) void k_batch_rows(const GroupDev* __restrict__ 
   }
 }
 
+// Path 7: persistent, software-pipelined staging.  The grid holds two
+// workgroups of 512 threads per CU, each walking its own list of items
+// (tile of 64 instances, block of rows).  A block is a set of rows taken
+// along a walk of the (j, k) pair grid in 4 x 4 tiles (S_p and J_p
+// together, the diagonal generators last), so that its rows gather a
+// compact neighbourhood of state rows: at most kP7Slots distinct columns,
+// staged in LDS as 64-instance slices of 512 bytes, beside the block's
+// matrix data (row list, segment ends, 16-bit slot indices, values; at most
+// kP7Blob bytes) and the tile's term coefficients.  While the rows of one
+// item are summed from LDS, the loads of the next item's staged data are in
+// flight into registers -- the same number of 16-byte loads from every
+// thread for every item, at clamped addresses where a block needs fewer, so
+// that every wait the compiler places is a fixed count -- together with the
+// column list of the item after it; at the end of the item the registers
+// are written to LDS.  Each state row a block gathers is read from the
+// memory system once per block instead of once per stored entry.  Rows with
+// more distinct columns than slots are summed afterwards by one wavefront
+// each straight from global memory.  Every row adds its terms in entry
+// order exactly like the other paths, so the results are bitwise the same.
+constexpr int kP7Slots = 128;
+constexpr int kP7Rows = 32;
+constexpr int kP7Blob = 8192;
+constexpr int kP7Threads = 512;
+constexpr int kP7Tile = 64;
+constexpr int kP7SegOff = 4 * kP7Rows;   // bytes: int32 rows[kP7Rows], then u16 segment ends [kP7Rows][nt]
+static_assert(kP7Slots == 16 * 8 && kP7Threads == 16 * 32, "staging map: 16 half-wavefronts x 8 loads");
+static_assert(kP7Blob == 16 * kP7Threads, "one 16-byte blob load per thread");
+static_assert(kP7Rows == 4 * (kP7Threads / 64), "four passes of one row per wavefront");
+
+// Each (row, term) segment of a block is padded to an even number of
+// entries, and each row's last segment to a multiple of kP7Round entries,
+// with entries (kP7Zero, 0.0): slot kP7Zero is never loaded and holds
+// zeros, and adding 0 * 0 to a running sum changes no bit of it (the sum
+// starts at +0 and round-to-nearest never produces -0 from it), so the row
+// walk reads whole rounds of pairs (one 4-byte read of two slot indices,
+// one 16-byte read of two values) with the results bitwise unchanged.
+constexpr int kP7Round = 8;
+static_assert(kP7Round % 2 == 0, "rounds of whole pairs");
+constexpr int kP7Zero = kP7Slots - 1;
+static_assert(kP7Zero == 7 * 16 + 15, "the zero slot is load 7 of half-wavefront 15");
+__host__ __device__ inline int p7_lidx_off(int nt) { return kP7SegOff + 2 * kP7Rows * nt; }
+__host__ __device__ inline int p7_val_off(int nt, int ne) { return (p7_lidx_off(nt) + 2 * ne + 15) & ~15; }
+
+// The path-7 groups of one launch, in launch order (kernel argument, so the
+// item walk runs on scalar registers only).
+constexpr int kP7MaxGroups = 16;
+constexpr int kP7LongWgs = 4;       // workgroups per XCD for the long rows, when there are any
+struct P7Plan {
+  int ng;
+  int klong;              // workgroups per XCD given to the long rows (0: none)
+  int g[kP7MaxGroups];
+  int nblk[kP7MaxGroups];
+  int tiles[kP7MaxGroups];
+};
+
+struct P7Loc {
+  int g, tb, blk;
+};
+
+// Item i of XCD x's share: each group of the plan contributes the x-th
+// eighth of its (tile, block) items, numbered tile-major.
+__device__ inline bool p7_locate(const P7Plan& plan, int x, int64_t i, P7Loc& L) {
+  for (int q = 0; q < plan.ng; ++q) {
+    const int64_t n = (int64_t)plan.nblk[q] * plan.tiles[q];
+    const int64_t lo = n * x / 8, cnt = n * (x + 1) / 8 - lo;
+    if (i < cnt) {
+      const int64_t local = lo + i;
+      L.g = plan.g[q];
+      L.tb = (int)(local / plan.nblk[q]);
+      L.blk = (int)(local % plan.nblk[q]);
+      return true;
+    }
+    i -= cnt;
+  }
+  return false;
+}
+
+template <int STAGE>
+__device__ inline const double* stage_in(const GroupDev& G) {
+  return STAGE == 0 ? G.v : (STAGE == 1 ? G.xa : (STAGE == 2 ? G.xb : G.xa));
+}
+template <int STAGE>
+__device__ inline double* stage_out(const GroupDev& G) {
+  return STAGE == 0 ? G.xa : (STAGE == 1 ? G.xb : (STAGE == 2 ? G.xa : G.v));
+}
+
+// Every global access of the pipelined kernel goes through global-address-
+// space pointers: generic (flat) accesses would also count against the
+// counter that LDS reads wait on, so every LDS wait of the row walk would
+// wait for the staging loads in flight as well.
+typedef unsigned uv4 __attribute__((ext_vector_type(4)));
+typedef int iv4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) uv4 g_uv4;
+typedef const __attribute__((address_space(1))) iv4 g_iv4;
+typedef const __attribute__((address_space(1))) int g_int;
+
+// Buffer resource over `bytes` bytes at p (raw, stride 0).  A load at a
+// byte offset past the end returns zeros and touches no memory, which is how
+// the lanes of a tile past its group's last instance skip their loads
+// without a branch (so every wait count stays fixed).
+constexpr int kP7Off = 0x7ffffff0;   // out-of-range offset
+__device__ inline __amdgpu_buffer_rsrc_t p7_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double p7_load_d(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// The value of x, opaque to the optimizer: keeps a per-lane choice of
+// offset a plain select instead of letting it split the load that uses it
+// into two branches (which would cost a branch and a full wait per load).
+__device__ inline int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+__device__ inline double readlane_d(double v, int l) {
+  const long long bits = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)bits, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kP7Threads, 4) void k_batch_pipe(const GroupDev* __restrict__ groups, P7Plan plan,
+                                                              const int64_t* __restrict__ step) {
+  __shared__ uv4 s_x[kP7Slots * 32];                // slot s: 64 instances of state row ucol[s]
+  __shared__ uv4 s_blob[kP7Blob / 16];
+  __shared__ double s_cf[kMaxBTerms * kP7Tile];     // c_a(t) of the tile's instances, [a][instance]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int hw = tid >> 5, l32 = tid & 31;          // staging: half-wavefront hw loads slots hw + 16 k
+  const int x = blockIdx.x & 7;
+  // The last plan.klong workgroups of every XCD take the long rows; the
+  // others share the blocks.
+  const int64_t K = (gridDim.x >> 3) - plan.klong;
+  const int64_t kk = blockIdx.x >> 3;
+  const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
+
+  uv4 px0, px1, px2, px3, px4, px5, px6, px7, pb;   // named, so they stay in registers
+  double pw, pu;
+  iv4 cu0, cu1;
+  auto issue_cols = [&](const P7Loc& L) {
+    g_iv4* q = (g_iv4*)(groups[L.g].p7_ucol + (int64_t)L.blk * kP7Slots + hw * 8);
+    cu0 = q[0];
+    cu1 = q[1];
+  };
+  auto issue_stage = [&](const P7Loc& L) {
+    const GroupDev& G = groups[L.g];
+    const __amdgpu_buffer_rsrc_t rx = p7_rsrc(stage_in<STAGE>(G), (int64_t)(G.M + 1) * G.ld * 8);
+    const int inst = L.tb * kP7Tile + 2 * l32;      // this lane's two instances
+    const int rowb = G.ld * 8;                      // bytes per state row
+    const bool live = inst < G.B;
+    const int o = inst * 8;
+    // unused slots and the zero slot carry column -1: loaded as zeros, no traffic
+#define P7_SLOT(c) __builtin_amdgcn_raw_buffer_load_b128(rx, opaque(live && (c) >= 0 ? (c) * rowb + o : kP7Off), 0, 0)
+    px0 = P7_SLOT(cu0.x);
+    px1 = P7_SLOT(cu0.y);
+    px2 = P7_SLOT(cu0.z);
+    px3 = P7_SLOT(cu0.w);
+    px4 = P7_SLOT(cu1.x);
+    px5 = P7_SLOT(cu1.y);
+    px6 = P7_SLOT(cu1.z);
+    px7 = P7_SLOT(cu1.w);
+#undef P7_SLOT
+    // block metadata through the scalar cache (uniform, read-only)
+    scalar_int* pm = (scalar_int*)G.p7_meta + 4 * (int64_t)L.blk;
+    const int m0 = pm[0], m1 = pm[1];
+    pb = ((g_uv4*)G.p7_blob)[m0 + (tid < m1 ? tid : 0)];
+    const int a = tid >> 6, b = L.tb * kP7Tile + lane;
+    const int idx = (a < G.nt && b < G.B) ? b * G.nt + a : 0;
+    pw = ((gconst_dbl*)G.w)[idx];
+    pu = ((gconst_dbl*)G.u)[idx];
+  };
+  auto write_stage = [&](const P7Loc& L) {
+    uv4* sx = s_x + hw * 32 + l32;     // slot hw + 16 k
+    sx[0 * 512] = px0;
+    sx[1 * 512] = px1;
+    sx[2 * 512] = px2;
+    sx[3 * 512] = px3;
+    sx[4 * 512] = px4;
+    sx[5 * 512] = px5;
+    sx[6 * 512] = px6;
+    sx[7 * 512] = hw == 15 ? uv4{0u, 0u, 0u, 0u} : px7;   // slot 7 * 16 + 15 = kP7Zero holds zeros
+    s_blob[tid] = pb;
+    const GroupDev& G = groups[L.g];
+    const double ph = G.wave[2 * step[L.g] + krow];   // uniform: a scalar load
+    const int a = tid >> 6, b = L.tb * kP7Tile + lane;
+    if (a < G.nt) s_cf[tid] = b < G.B ? pw + pu * ph : 0.0;
+  };
+
+  // Rows with more distinct columns than slots: one wavefront per (row,
+  // tile), straight from global memory.  Each lane holds one of 64
+  // consecutive entries of the row (column and value), and the wavefront
+  // gathers 32 entries' state at a time before adding them in entry
+  // order, so the chain of dependent loads is one round trip per 32
+  // entries.  They go to workgroups of their own (a few per XCD, with no
+  // blocks), so that their latency overlaps the pipelines of the others
+  // instead of delaying them; the tile's term coefficients go to this
+  // wavefront's own area of the staging buffer, which these workgroups do
+  // not otherwise use.
+  if (kk >= K) {
+  double* s_cw = reinterpret_cast<double*>(s_x) + wv * (kMaxBTerms * kP7Tile);
+  const int64_t wid = (((kk - K) * 8 + x) * (kP7Threads / 64)) + wv;
+  const int64_t nw = (int64_t)plan.klong * 8 * (kP7Threads / 64);
+  for (int q = 0; q < plan.ng; ++q) {
+    const int g = plan.g[q];
+    const GroupDev& G = groups[g];
+    if (G.p7_nlong == 0) continue;
+    const int nt = G.nt, ld = G.ld;
+    const double ph = G.wave[2 * step[g] + krow];
+    gconst_dbl* xin = (gconst_dbl*)stage_in<STAGE>(G);
+    gdbl* xout = (gdbl*)stage_out<STAGE>(G);
+    gconst_dbl* gv = (gconst_dbl*)G.v;
+    gdbl* gacc = (gdbl*)G.acc;
+    gconst_dbl* gval = (gconst_dbl*)G.val;
+    g_int* gcol = (g_int*)G.col;
+    for (int64_t it = wid; it < (int64_t)G.p7_nlong * G.tiles; it += nw) {
+      const int r = G.p7_long[it / G.tiles];
+      const int tb = (int)(it % G.tiles);
+      const int b = tb * kP7Tile + lane;         // lanes past the last instance read padding, store nothing
+      const bool own = b < G.B;
+      for (int a = 0; a < nt; ++a)
+        s_cw[a * kP7Tile + lane] = own ? G.w[(int64_t)b * nt + a] + G.u[(int64_t)b * nt + a] * ph : 0.0;
+      const int64_t ix = (int64_t)r * ld + b;
+      const double vr = gv[ix];
+      const double ar = STAGE != 0 ? ((gconst_dbl*)gacc)[ix] : 0.0;
+      const int e0 = G.rowptr[r], e_end = G.rowptr[r + 1];
+      int a = 0;
+      int s1 = nt > 1 ? G.segptr[(int64_t)r * nt + 1] : e_end;   // end of term a
+      double ysum = 0.0, sacc = 0.0;
+      for (int cb = e0; cb < e_end; cb += 64) {
+        const int n = min(64, e_end - cb);
+        const int mc = gcol[cb + (lane < n ? lane : 0)];
+        const double mv = gval[cb + (lane < n ? lane : 0)];
+        for (int k = 0; k < n; k += 32) {
+          double xs[32];
+#pragma unroll
+          for (int j = 0; j < 32; ++j)
+            xs[j] = xin[(int64_t)__builtin_amdgcn_readlane(mc, min(k + j, n - 1)) * ld + b];
+#pragma unroll
+          for (int j = 0; j < 32; ++j) {
+            if (k + j < n) {
+              const int e = cb + k + j;
+              while (e == s1) {                    // term a ends before entry e
+                ysum += s_cw[a * kP7Tile + lane] * sacc;
+                sacc = 0.0;
+                ++a;
+                s1 = (a + 1 < nt) ? G.segptr[(int64_t)r * nt + a + 1] : e_end;
+              }
+              sacc += readlane_d(mv, k + j) * xs[j];
+            }
+          }
+        }
+      }
+      for (; a < nt; ++a) {                          // the last term, and empty terms after it
+        ysum += s_cw[a * kP7Tile + lane] * sacc;
+        sacc = 0.0;
+      }
+      if (own) {
+        double an = 0.0;
+        xout[ix] = lds_stage<STAGE>(vr, ar, ysum, G.dt, an);
+        if (STAGE != 3) gacc[ix] = an;
+      }
+    }
+  }
+  return;
+  }
+
+  P7Loc cur, nxt, nn;
+  int64_t i = kk;
+  if (p7_locate(plan, x, i, cur)) {
+    issue_cols(cur);
+    issue_stage(cur);
+    write_stage(cur);
+    bool has_nxt = p7_locate(plan, x, i + K, nxt);
+    issue_cols(has_nxt ? nxt : cur);
+    i += 2 * K;
+    __syncthreads();
+    for (;;) {
+      // LDS holds item `cur`; cu0/cu1 hold (or are loading) the columns of `nxt`
+      const GroupDev& G = groups[cur.g];
+      scalar_int* pm = (scalar_int*)G.p7_meta + 4 * (int64_t)cur.blk;
+      const int nr = pm[2], ne = pm[3], nt = G.nt, ld = G.ld;
+      const int* s_rows = reinterpret_cast<const int*>(s_blob);
+      const unsigned short* s_seg = reinterpret_cast<const unsigned short*>(
+          reinterpret_cast<const char*>(s_blob) + kP7SegOff);
+      const unsigned short* s_lx = reinterpret_cast<const unsigned short*>(
+          reinterpret_cast<const char*>(s_blob) + p7_lidx_off(nt));
+      const double* s_val = reinterpret_cast<const double*>(reinterpret_cast<const char*>(s_blob) +
+                                                            p7_val_off(nt, ne));
+      const double* sx = reinterpret_cast<const double*>(s_x);
+      const int b = cur.tb * kP7Tile + lane;
+      const bool own = b < G.B;
+      gdbl* gacc = (gdbl*)G.acc;
+      gdbl* xout = (gdbl*)stage_out<STAGE>(G);
+      // this item's own state entries (rows past the block's last are padded
+      // with its first row; the row is the same for the whole wavefront)
+      const __amdgpu_buffer_rsrc_t rv = p7_rsrc(G.v, (int64_t)(G.M + 1) * ld * 8);
+      const __amdgpu_buffer_rsrc_t ra = p7_rsrc(G.acc, (int64_t)G.M * ld * 8);
+      double vr[4], ar[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int row = __builtin_amdgcn_readfirstlane(s_rows[p * 8 + wv]);
+        const int off = opaque(own ? (row * ld + b) * 8 : kP7Off);
+        vr[p] = p7_load_d(rv, off);
+        ar[p] = STAGE != 0 ? p7_load_d(ra, off) : 0.0;
+      }
+      // the next item's staged data, and the columns of the one after it
+      const bool has_nn = p7_locate(plan, x, i, nn);
+      issue_stage(has_nxt ? nxt : cur);
+      issue_cols(has_nn ? nn : cur);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int lr = p * 8 + wv;
+        if (lr < nr && own) {
+          // one walk over the row in rounds of kP7Round entries across its
+          // terms; term a is closed (ysum += c_a * sum) after the pair that
+          // ends it, empty terms where they stand, the last term at the end
+          const int rs = lr > 0 ? s_seg[lr * nt - 1] : 0;
+          const int re = s_seg[lr * nt + nt - 1];
+          const unsigned* l2 = reinterpret_cast<const unsigned*>(s_lx);   // two slot indices per word
+          const double2* v2 = reinterpret_cast<const double2*>(s_val);
+          double ysum = 0.0, sacc = 0.0;
+          int a = 0, s1 = s_seg[lr * nt];
+          while (a < nt - 1 && s1 == rs) {
+            ysum += s_cf[a * kP7Tile + lane] * sacc;
+            sacc = 0.0;
+            s1 = s_seg[lr * nt + ++a];
+          }
+          for (int e = rs; e < re; e += kP7Round) {
+            unsigned l[kP7Round / 2];
+            double2 v[kP7Round / 2];
+            double xv[kP7Round];
+#pragma unroll
+            for (int q = 0; q < kP7Round / 2; ++q) {
+              l[q] = l2[(e >> 1) + q];
+              v[q] = v2[(e >> 1) + q];
+            }
+#pragma unroll
+            for (int q = 0; q < kP7Round / 2; ++q) {
+              xv[2 * q] = sx[(l[q] & 0xffff) * kP7Tile + lane];
+              xv[2 * q + 1] = sx[(l[q] >> 16) * kP7Tile + lane];
+            }
+#pragma unroll
+            for (int q = 0; q < kP7Round / 2; ++q) {
+              sacc += v[q].x * xv[2 * q];
+              sacc += v[q].y * xv[2 * q + 1];
+              while (a < nt - 1 && e + 2 * q + 2 == s1) {
+                ysum += s_cf[a * kP7Tile + lane] * sacc;
+                sacc = 0.0;
+                s1 = s_seg[lr * nt + ++a];
+              }
+            }
+          }
+          for (; a < nt; ++a) {
+            ysum += s_cf[a * kP7Tile + lane] * sacc;
+            sacc = 0.0;
+          }
+          const int64_t ix = (int64_t)__builtin_amdgcn_readfirstlane(s_rows[lr]) * ld + b;
+          double an = 0.0;
+          xout[ix] = lds_stage<STAGE>(vr[p], ar[p], ysum, G.dt, an);
+          if (STAGE != 3) gacc[ix] = an;
+        }
+      }
+      if (!has_nxt) break;
+      __syncthreads();   // every wavefront is done with this item's LDS
+      write_stage(nxt);
+      __syncthreads();
+      cur = nxt;
+      nxt = nn;
+      has_nxt = has_nn;
+      i += K;
+    }
+  }
+}
+
 // Row blocks for path 3: at most max_rows rows, kLdsCap entries and ucap
 // distinct columns; with each block's sorted distinct columns and every
 // entry's position in them.  False if a single row does not fit.
@@ -876,6 +1265,139 @@ bool xlds_partition(const std::vector<int>& rp, const std::vector<int>& col, int
   return true;
 }
 
+// Path 7 blocks.  Rows are taken along the pair grid in 4 x 4 tiles of
+// (j, k) (stored rows 2p and 2p + 1 of pair p = (j, k), j < k), then the
+// diagonal generators in order; consecutive rows join a block while it
+// keeps at most max_rows rows, kP7Slots distinct columns and kP7Blob bytes
+// of matrix data.  A row that alone exceeds a limit goes to the long list.
+struct P7Part {
+  std::vector<int> meta;        // 4 ints per block
+  std::vector<int> ucol;        // kP7Slots per block, slot s at (s % 16) * 8 + s / 16
+  std::vector<uint4> blob;
+  std::vector<int> longrows;
+};
+
+void p7_partition(int N, int64_t M, int nt, const std::vector<int>& rp, const std::vector<int>& seg,
+                  const std::vector<int>& col, const std::vector<double>& val, int max_rows, P7Part& out) {
+  const int64_t P = (int64_t)N * (N - 1) / 2;
+  std::vector<int> seq;
+  seq.reserve(M);
+  constexpr int T = 4;
+  for (int tj = 0; tj < N; tj += T)
+    for (int tk = tj; tk < N; tk += T)
+      for (int j = tj; j < std::min(tj + T, N); ++j)
+        for (int k = std::max(tk, j + 1); k < std::min(tk + T, N); ++k) {
+          const int64_t p = (int64_t)j * (2 * N - j - 1) / 2 + k - j - 1;
+          seq.push_back((int)(2 * p));
+          seq.push_back((int)(2 * p + 1));
+        }
+  for (int64_t r = 2 * P; r < M; ++r) seq.push_back((int)r);
+  SUN_REQUIRE((int64_t)seq.size() == M, SUN_EDEVICE, "internal: path 7 row walk does not cover the rows");
+  // ne counts padded entries: a row of term lengths n_a takes sum ceil2(n_a), rounded up to kP7Round
+  auto fits = [&](int rows, int used, int ne) {
+    return rows <= max_rows && used <= kP7Slots - 1 && p7_val_off(nt, ne) + 8 * ne <= kP7Blob;
+  };
+  auto padded_len = [&](int r) {
+    int n = 0;
+    for (int a = 0; a < nt; ++a) {
+      const int s1 = a + 1 < nt ? seg[(int64_t)r * nt + a + 1] : rp[r + 1];
+      n += (s1 - seg[(int64_t)r * nt + a] + 1) & ~1;
+    }
+    return (n + kP7Round - 1) / kP7Round * kP7Round;
+  };
+  std::vector<int> mark(M + 1, -1), seen(M + 1, -1);
+  std::vector<std::vector<int>> blocks;
+  std::vector<int> cur;
+  int used = 0, ne = 0, stamp = 0, nb = 0;
+  auto fresh_of = [&](int r) {
+    int fresh = 0;
+    ++stamp;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int c = col[e];
+      if (mark[c] != nb && seen[c] != stamp) { seen[c] = stamp; ++fresh; }
+    }
+    return fresh;
+  };
+  auto close = [&] {
+    if (!cur.empty()) { blocks.push_back(cur); ++nb; }
+    cur.clear();
+    used = 0;
+    ne = 0;
+  };
+  for (int r : seq) {
+    const int len = padded_len(r);
+    int fresh = fresh_of(r);
+    if (!fits((int)cur.size() + 1, used + fresh, ne + len)) {
+      close();
+      fresh = fresh_of(r);
+      if (!fits(1, fresh, len)) {           // the row alone exceeds a block
+        out.longrows.push_back(r);
+        continue;
+      }
+    }
+    for (int e = rp[r]; e < rp[r + 1]; ++e) mark[col[e]] = nb;
+    cur.push_back(r);
+    used += fresh;
+    ne += len;
+  }
+  close();
+  out.meta.clear();
+  out.ucol.assign(blocks.size() * kP7Slots, 0);
+  out.blob.clear();
+  std::vector<int> u;
+  std::vector<unsigned char> bytes;
+  for (size_t bi = 0; bi < blocks.size(); ++bi) {
+    const std::vector<int>& rows = blocks[bi];
+    u.clear();
+    int nent = 0;
+    for (int r : rows) {
+      u.insert(u.end(), col.begin() + rp[r], col.begin() + rp[r + 1]);
+      nent += padded_len(r);
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    SUN_REQUIRE((int)u.size() <= kP7Slots - 1 && (int)rows.size() <= kP7Rows &&
+                    p7_val_off(nt, nent) + 8 * nent <= kP7Blob,
+                SUN_EDEVICE, "internal: path 7 block exceeds its limits");
+    for (int s = 0; s < kP7Slots; ++s)   // unused slots and the zero slot: -1
+      out.ucol[bi * kP7Slots + (s % 16) * 8 + s / 16] = s < (int)u.size() ? u[s] : -1;
+    const int nbytes = p7_val_off(nt, nent) + 8 * nent;
+    const int n16 = (nbytes + 15) / 16;
+    bytes.assign((size_t)n16 * 16, 0);
+    int* brow = reinterpret_cast<int*>(bytes.data());
+    unsigned short* bseg = reinterpret_cast<unsigned short*>(bytes.data() + kP7SegOff);
+    unsigned short* blx = reinterpret_cast<unsigned short*>(bytes.data() + p7_lidx_off(nt));
+    double* bval = reinterpret_cast<double*>(bytes.data() + p7_val_off(nt, nent));
+    int w = 0;
+    for (int lr = 0; lr < kP7Rows; ++lr) brow[lr] = rows[lr < (int)rows.size() ? lr : 0];
+    for (int lr = 0; lr < (int)rows.size(); ++lr) {
+      const int r = rows[lr];
+      for (int a = 0; a < nt; ++a) {
+        const int s1 = a + 1 < nt ? seg[(int64_t)r * nt + a + 1] : rp[r + 1];
+        for (int e = seg[(int64_t)r * nt + a]; e < s1; ++e) {
+          blx[w] = (unsigned short)(std::lower_bound(u.begin(), u.end(), col[e]) - u.begin());
+          bval[w] = val[e];
+          ++w;
+        }
+        // pad the segment to a multiple of two, the row's last one to a multiple of kP7Round
+        for (; (w & 1) || (a == nt - 1 && w % kP7Round); ++w) {
+          blx[w] = (unsigned short)kP7Zero;
+          bval[w] = 0.0;
+        }
+        bseg[lr * nt + a] = (unsigned short)w;
+      }
+    }
+    out.meta.push_back((int)out.blob.size());
+    out.meta.push_back(n16);
+    out.meta.push_back((int)rows.size());
+    out.meta.push_back(nent);
+    const size_t at = out.blob.size();
+    out.blob.resize(at + n16);
+    std::memcpy(out.blob.data() + at, bytes.data(), (size_t)n16 * 16);
+    SUN_REQUIRE(out.blob.size() < (size_t)INT32_MAX, SUN_ENOTSUP, "path 7 block data exceeds 2^31 16-byte units");
+  }
+}
+
 // Row blocks of at most max_rows rows and kLdsCap entries; empty if a single
 // row has more than kLdsCap entries (the group then takes the per-wavefront
 // path).
@@ -921,6 +1443,19 @@ void refresh_items(sun_batch_s& bt) {
       G.row_blocks = 0;
       G.tiles = 0;
     }
+    G.p7 = bt.path[g] == 7;
+    G.p7_nblk = bt.p7_nblk[g];
+    G.p7_meta = reinterpret_cast<const int4*>(bt.p7_meta[g].get());
+    G.p7_ucol = bt.p7_ucol[g].get();
+    G.p7_blob = bt.p7_blob[g].get();
+    G.p7_nlong = bt.p7_nlong[g];
+    G.p7_long = bt.p7_long[g].get();
+    if (G.p7) {              // tiles of 64 instances, one per lane; no items of the other kernels
+      G.vec = 1;
+      G.tile = kP7Tile;
+      G.tiles = (G.B + kP7Tile - 1) / kP7Tile;
+      G.row_blocks = 0;
+    }
   }
   for (int gi : bt.order) {
     GroupDev& G = bt.ghost[gi];
@@ -938,12 +1473,48 @@ void repartition(sun_batch_s& bt, int g) {
   const int max_rows = std::min(bt.rows_per_item[g], kLdsRows);
   std::vector<int> blk;
   bt.xl[g] = 0;
+  bt.p7_meta[g].release();
+  bt.p7_ucol[g].release();
+  bt.p7_blob[g].release();
+  bt.p7_long[g].release();
+  bt.p7_nblk[g] = 0;
+  bt.p7_nlong[g] = 0;
   if (bt.path[g] >= 4) {
     bt.xu_ptr[g].release();
     bt.xu_col[g].release();
     bt.xu_lidx[g].release();
     bt.nblk[g] = 0;
     bt.blk_row[g].release();
+    if (bt.path[g] == 7) {
+      const int64_t M = bt.M[g];
+      const int nt = bt.nt[g];
+      std::vector<int> hseg((size_t)M * nt), hcol(bt.nnz[g]);
+      std::vector<double> hval(bt.nnz[g]);
+      if (M > 0)
+        HIP_OK(hipMemcpy(hseg.data(), bt.segptr[g].get(), hseg.size() * sizeof(int), hipMemcpyDeviceToHost));
+      if (bt.nnz[g] > 0) {
+        HIP_OK(hipMemcpy(hcol.data(), bt.col[g].get(), hcol.size() * sizeof(int), hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(hval.data(), bt.val[g].get(), hval.size() * sizeof(double), hipMemcpyDeviceToHost));
+      }
+      P7Part pp;
+      p7_partition(bt.lind[g]->basis->N, M, nt, bt.h_rowptr[g], hseg, hcol, hval,
+                   std::min(bt.rows_per_item[g], kP7Rows), pp);
+      const int nb = (int)(pp.meta.size() / 4);
+      bt.p7_meta[g].alloc(std::max<size_t>(4, pp.meta.size()));
+      bt.p7_ucol[g].alloc(std::max<size_t>(1, pp.ucol.size()));
+      bt.p7_blob[g].alloc(std::max<size_t>(1, pp.blob.size()));
+      bt.p7_long[g].alloc(std::max<size_t>(1, pp.longrows.size()));
+      if (nb > 0) {
+        HIP_OK(hipMemcpy(bt.p7_meta[g].get(), pp.meta.data(), pp.meta.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(bt.p7_ucol[g].get(), pp.ucol.data(), pp.ucol.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(bt.p7_blob[g].get(), pp.blob.data(), pp.blob.size() * sizeof(uint4), hipMemcpyHostToDevice));
+      }
+      if (!pp.longrows.empty())
+        HIP_OK(hipMemcpy(bt.p7_long[g].get(), pp.longrows.data(), pp.longrows.size() * sizeof(int),
+                         hipMemcpyHostToDevice));
+      bt.p7_nblk[g] = nb;
+      bt.p7_nlong[g] = (int)pp.longrows.size();
+    }
     return;
   }
   if (bt.path[g] == 3) {
@@ -1088,6 +1659,8 @@ struct StageLaunch {
   bool r1 = false, r2 = false;   // path-5 groups with one / two instances per lane
   int64_t rgrid[3] = {0, 0, 0};  // path-5 grids (resident wavefronts, a multiple of 8), by VEC
   int r_nt = 1;                  // most terms of a path-5 group
+  std::vector<P7Plan> p7;        // path-7 groups, at most kP7MaxGroups per launch
+  int64_t pgrid = 8;             // path-7 grid (two workgroups per CU, a multiple of 8)
 };
 
 // Wavefronts of k_batch_rows<*, VEC> the device keeps resident (the least
@@ -1127,6 +1700,8 @@ void launch_stage(const StageLaunch& L) {
   if (L.r2)
     hipLaunchKernelGGL((k_batch_rows<STAGE, 2>), dim3((unsigned)L.rgrid[2]), dim3(64),
                        (size_t)L.r_nt * 128 * sizeof(double), L.s, L.gd, L.go, L.nactive, L.st);
+  for (const P7Plan& plan : L.p7)
+    hipLaunchKernelGGL(k_batch_pipe<STAGE>, dim3((unsigned)L.pgrid), dim3(kP7Threads), 0, L.s, L.gd, plan, L.st);
 }
 
 }  // namespace
@@ -1180,6 +1755,12 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->mxa.resize(ngroups);
       bt->mxb.resize(ngroups);
       bt->macc.resize(ngroups);
+      bt->p7_meta.resize(ngroups);
+      bt->p7_ucol.resize(ngroups);
+      bt->p7_blob.resize(ngroups);
+      bt->p7_long.resize(ngroups);
+      bt->p7_nblk.assign(ngroups, 0);
+      bt->p7_nlong.assign(ngroups, 0);
       for (int g = 0; g < ngroups; ++g) {
         const sun_lind_s* l = lind[g];
         SUN_REQUIRE(l != nullptr, SUN_EINVAL, "group system is NULL");
@@ -1307,8 +1888,13 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
   return guarded([&] {
     SUN_REQUIRE(bt != nullptr, SUN_EINVAL, "batch is NULL");
     SUN_REQUIRE(g >= 0 && g < bt->ngroups, SUN_EINVAL, "group index out of range");
-    SUN_REQUIRE(path >= 0 && path <= 5, SUN_EINVAL, "path must be 0, 1, 2, 3, 4 or 5");
-    if (path == 4) {
+    SUN_REQUIRE(path >= 0 && path <= 7 && path != 6, SUN_EINVAL, "path must be 0, 1, 2, 3, 4, 5 or 7");
+    if (path == 7) {
+      SUN_REQUIRE(tile == kP7Tile, SUN_EINVAL, "path 7 takes tiles of 64 instances");
+      SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= kP7Rows, SUN_EINVAL, "path 7 takes 1 to 32 rows per block");
+      SUN_REQUIRE((bt->M[g] + 1) * (int64_t)bt->ld[g] * 8 < (int64_t)kP7Off, SUN_ENOTSUP,
+                  "path 7 needs a group state below 2 GiB (32-bit buffer offsets)");
+    } else if (path == 4) {
       SUN_REQUIRE(tile == 2 || tile == 4 || tile == 8, SUN_EINVAL, "path 4 takes 2, 4 or 8 instances per wavefront");
     } else if (path == 5) {
       SUN_REQUIRE(tile == 64 || tile == 128, SUN_EINVAL, "path 5 takes tiles of 64 or 128 instances");
@@ -1423,6 +2009,19 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
           (G.vec == 2 ? L.r2 : L.r1) = true;
           continue;
         }
+        if (G.p7) {
+          // every 64-instance tile stays inside the padded state rows
+          SUN_REQUIRE(G.tiles * kP7Tile <= G.ld && G.nt <= kMaxBTerms, SUN_ENOTSUP,
+                      "internal: path 7 tile exceeds the state rows");
+          if (L.p7.empty() || L.p7.back().ng == kP7MaxGroups) L.p7.push_back(P7Plan{});
+          P7Plan& pl = L.p7.back();
+          if (G.p7_nlong > 0) pl.klong = kP7LongWgs;
+          pl.g[pl.ng] = ord[q];
+          pl.nblk[pl.ng] = G.p7_nblk;
+          pl.tiles[pl.ng] = G.tiles;
+          ++pl.ng;
+          continue;
+        }
         if (G.nblk == 0) continue;
         max_nt = std::max(max_nt, G.nt);
         if (G.xlds) {
@@ -1439,6 +2038,9 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       L.xgrid = std::max<int64_t>(8, (std::min<int64_t>(nx, (int64_t)ncu * 3) + 7) / 8 * 8);
       L.cf_len = max_nt * kCfStride;
       L.r_nt = p5_nt;
+      L.pgrid = std::max<int64_t>(16, (int64_t)ncu * 2 / 8 * 8);
+      for (P7Plan& pl : L.p7)   // at least one workgroup per XCD keeps the blocks
+        pl.klong = std::min<int>(pl.klong, (int)(L.pgrid / 8) - 1);
       L.rgrid[1] = p5_grid[1];
       L.rgrid[2] = p5_grid[2];
       L.st = steptab.get() + n * bt->ngroups;
@@ -1491,6 +2093,7 @@ extern "C" int sun_batch_device_bytes(sun_batch bt, size_t* bytes) {
                                       &bt->mxa[g], &bt->mxb[g], &bt->macc[g]})
         b += x->bytes();
       b += bt->xu_lidx[g].bytes();
+      b += bt->p7_meta[g].bytes() + bt->p7_ucol[g].bytes() + bt->p7_blob[g].bytes() + bt->p7_long[g].bytes();
       if (bt->mprop[g]) b += prop_device_bytes(*bt->mprop[g]);
     }
     *bytes = b;

@@ -66,7 +66,8 @@ def test_tiling_does_not_change_results(lib):
     results = []
     for tile, rows, path in ((64, 64, 0), (8, 1, 0), (16, 7, 1), (32, 512, 1), (64, 3, 1), (16, 128, 0),
                              (128, 32, 0), (128, 5, 1), (16, 64, 2), (32, 9, 2), (64, 128, 2), (8, 16, 2),
-                             (8, 4, 3), (16, 64, 3), (32, 128, 3), (128, 64, 5), (64, 1, 5)):
+                             (8, 4, 3), (16, 64, 3), (32, 128, 3), (128, 64, 5), (64, 1, 5), (64, 32, 7),
+                             (64, 1, 7), (64, 7, 7)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -94,7 +95,7 @@ def test_lds_and_global_paths_agree_bitwise(lib):
     out = []
     for tile, rows, path in ((64, 64, 0), (16, 128, 0), (32, 16, 1), (64, 8, 1), (128, 64, 0), (128, 8, 0),
                              (16, 64, 2), (32, 32, 2), (64, 128, 2), (8, 128, 3), (16, 32, 3), (32, 128, 3),
-                             (128, 64, 5), (64, 64, 5)):
+                             (128, 64, 5), (64, 64, 5), (64, 32, 7), (64, 16, 7)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -107,9 +108,10 @@ def test_lds_and_global_paths_agree_bitwise(lib):
 
 def test_row_wavefront_path_multi_tile_bitwise(lib):
     """Path 5 (one wavefront per row and tile, matrix through the scalar
-    cache) on groups of 300 and 130 instances, i.e. 3 and 2 tiles of 128 and
-    5 and 3 tiles of 64 with ragged last tiles, against path 0: bitwise equal
-    after 16 steps, and the first instances against the dense oracle."""
+    cache) and path 7 (pipelined staging, tiles of 64) on groups of 300 and
+    130 instances, i.e. 3 and 2 tiles of 128 and 5 and 3 tiles of 64 with
+    ragged last tiles, against path 0: bitwise equal after 16 steps, and the
+    first instances against the dense oracle."""
     flush("[batched] path 5, several tiles per group, vs path 0")
     rng = np.random.default_rng(11)
     inst = []
@@ -124,7 +126,7 @@ def test_row_wavefront_path_multi_tile_bitwise(lib):
     bp, groups = dimer_batch(lib, inst, steps)
     starts = [torch.as_tensor(np.stack([fock_bloch(N, j % N) for j in range(len(idx))])) for (N, idx, _, _, _) in groups]
     out = []
-    for tile, rows, path in ((64, 64, 0), (128, 64, 5), (64, 64, 5)):
+    for tile, rows, path in ((64, 64, 0), (128, 64, 5), (64, 64, 5), (64, 32, 7)):
         for g in range(len(groups)):
             bp.tune(g, tile, rows, path)
             bp.set_state(g, starts[g])
@@ -137,6 +139,40 @@ def test_row_wavefront_path_multi_tile_bitwise(lib):
         for j in (0, len(idx) - 1):
             want = _oracle_instance(inst[idx[j]], st, fock_bloch(N, j % N))
             assert rel_vec_err(out[1][g][j], want) <= TOL, (N, j)
+
+
+def test_pipelined_path_large_groups_bitwise(lib):
+    """Path 7 (persistent pipelined staging) on the N = 151, 201 and 301
+    groups of the 512-instance workload -- two tiles of 64 instances, the
+    last one ragged; at N >= 201 some rows have more distinct columns than a
+    block's 128 slots and take the long-row walk -- alone and mixed with
+    path 0 in the same launches: bitwise equal to path 0 after 8 steps, and
+    the last instance of each group against plain single-instance GPU
+    propagation (1e-12)."""
+    flush("[batched] path 7 on the large groups vs path 0")
+    inst = [p for p in dimer.batched_instances() if p.N in (151, 201, 301)]
+    steps = 8
+    bp, groups = dimer_batch(lib, inst, steps)
+    starts = [torch.as_tensor(np.stack([fock_bloch(N, j % 3) for j in range(len(idx))]))
+              for (N, idx, _, _, _) in groups]
+    out = []
+    for cfg in ([(64, 64, 0)] * 3, [(64, 32, 7)] * 3, [(64, 32, 7), (128, 64, 0), (64, 16, 7)]):
+        for g, (tile, rows, path) in enumerate(cfg):
+            bp.tune(g, tile, rows, path)
+            bp.set_state(g, starts[g])
+        bp.run(steps)
+        out.append([bp.get_state(g).cpu().numpy() for g in range(len(groups))])
+    for r in out[1:]:
+        for a, b in zip(r, out[0]):
+            assert np.array_equal(a, b)
+    for g, (N, idx, lind, dt, st) in enumerate(groups):
+        j = len(idx) - 1
+        p = inst[idx[j]]
+        prop = lind.propagator([1.0, 0.0, p.gamma_eff], [1])
+        v = torch.as_tensor(fock_bloch(N, j % 3)).cuda()
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+        prop.propagate(v, eps, dt, steps)
+        assert rel_vec_err(out[1][g][j], v.cpu().numpy()) <= TOL, (N, j)
 
 
 def test_full_workload_sampled_against_plain(lib):
@@ -204,7 +240,7 @@ def test_autotuner_picks_valid_tiling(lib, tmp_path, monkeypatch):
     for g in range(len(groups)):
         info = bp.info(g)
         assert info["tile"] == chosen[g]["tile"] and info["rows_per_item"] == chosen[g]["rows_per_item"]
-        assert chosen[g]["path"] in (0, 2, 3, 4, 5)
+        assert chosen[g]["path"] in (0, 2, 3, 4, 5, 7)
     again = lib.autotune_batched(bp)
     assert all(c["cached"] for c in again.values())
 
