@@ -76,7 +76,7 @@ def union_nnz(lind, torch):
 
 STAGE_SOURCE = "paper_1812_11626_amd/csrc/propagate.hip"
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_rk4_sell_dimer-plain-N1001_counters.md")
-BATCHED_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_batch_stage_lds_dimer-batched-512_counters.md")
+BATCHED_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "k_batch_pipe_dimer-batched-512_counters.md")
 
 
 def stage_source_hash() -> str:
