@@ -390,12 +390,17 @@ def batched_report(sb, torch):
     # plus 20 bytes per state row and instance (gather, base, accumulator and
     # output streams: 80 M per instance-step)
     alg_bytes = 0
+    stage_bytes = 0
     launch_bytes = 0          # one stage launch with every group active
     for g, (N, idx, basis, lind, p0) in enumerate(meta):
         info = bp.info(g)
         M = info["M"]
         alg_bytes += p0.steps * 4 * (12 * info["nnz"] + 4 * (M + 1)) + p0.steps * len(idx) * 80 * M
         launch_bytes += 12 * info["nnz"] + 4 * (M + 1) + 20 * M * len(idx)
+        # the state streams a four-launch classical RK4 step cannot avoid (the
+        # gathered input counted once): 24 + 40 + 40 + 32 = 136 B per state row
+        # and instance per step
+        stage_bytes += p0.steps * 4 * (12 * info["nnz"] + 4 * (M + 1)) + p0.steps * len(idx) * 136 * M
     tiling = ",".join(f"{tuned[g]['tile']}/{tuned[g]['rows_per_item']}/{tuned[g]['path']}" for g in range(len(meta)))
     prof_bytes, prof_tiling = batched_profiled_traffic()
     traffic = prof_bytes if prof_tiling == tiling else None
@@ -430,6 +435,8 @@ def batched_report(sb, torch):
             "roofline": {"bound": "hbm", "algorithmic_bytes": alg_bytes, "achieved": alg_bytes / el / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg_bytes / el / 1e9 / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_launch": launch_bytes, "tiling": tiling,
+                         "rk4_stream_bytes": stage_bytes,
+                         "rk4_stream_frac": stage_bytes / el / 1e9 / HBM_PEAK_GBS,
                          "traffic": traffic,
                          "profiled_traffic": {"bytes_beyond_l2_per_launch": prof_bytes, "tiling": prof_tiling},
                          "traffic_note": "bytes beyond L2 per stage launch with every group active, from the "
