@@ -332,11 +332,14 @@ int sun_propagate_profile(sun_prop p, double* v, const double* coef, double dt,
                           int64_t steps, void* stream, double* stage_ms,
                           int64_t* launches);
 /* For tests of the error paths: site 1 makes the next layout build (by
- * sun_prop_tune, sun_prop_tune_sliced or the adjoint's first run) fail with
- * SUN_ENOMEM after it has rewritten part of the propagator, as a device
- * allocation failure there would; site 0 clears a pending injection.  A
- * propagator left incomplete that way refuses every launching call with
- * SUN_EINVAL until a layout is selected again. */
+ * sun_prop_tune, sun_prop_tune_sliced, the adjoint's first run or
+ * sun_batch_tune to path 7) fail with SUN_ENOMEM after it has rewritten part
+ * of the propagator or group, as a device allocation failure there would;
+ * site 0 clears a pending injection.  A propagator left incomplete that way
+ * refuses every launching call with SUN_EINVAL until a layout is selected
+ * again; a batch group left incomplete (by this or any failure inside
+ * sun_batch_tune) makes sun_batch_run refuse with SUN_EINVAL until the group
+ * is tuned again. */
 int sun_debug_inject_failure(int32_t site);
 /* Layout facts for measurement: nnz of the fused matrix (static + dynamic
  * segments + folded free vector), number of work units per stage launch

@@ -117,6 +117,9 @@ struct sun_batch_s {
   std::vector<DevBuf<int>> p7_meta, p7_ucol, p7_long;
   std::vector<DevBuf<uint4>> p7_blob;
   std::vector<int> p7_nblk, p7_nlong;
+  // 0 after a re-tiling of the group failed part-way: sun_batch_run refuses
+  // to advance it (its layout is incomplete) until it is tuned again
+  std::vector<int> usable;
   ~sun_batch_s() {
     for (sun_prop q : mprop)
       if (q) sun_prop_free(q);
@@ -1496,6 +1499,7 @@ void repartition(sun_batch_s& bt, int g) {
         HIP_OK(hipMemcpy(hcol.data(), bt.col[g].get(), hcol.size() * sizeof(int), hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(hval.data(), bt.val[g].get(), hval.size() * sizeof(double), hipMemcpyDeviceToHost));
       }
+      layout_failure_point();   // the old layout is gone from here on
       P7Part pp;
       p7_partition(bt.lind[g]->basis->N, M, nt, bt.h_rowptr[g], hseg, hcol, hval,
                    std::min(bt.rows_per_item[g], kP7Rows), pp);
@@ -1761,6 +1765,7 @@ extern "C" int sun_batch_create(const sun_lind* lind, int32_t ngroups, const int
       bt->p7_long.resize(ngroups);
       bt->p7_nblk.assign(ngroups, 0);
       bt->p7_nlong.assign(ngroups, 0);
+      bt->usable.assign(ngroups, 1);
       for (int g = 0; g < ngroups; ++g) {
         const sun_lind_s* l = lind[g];
         SUN_REQUIRE(l != nullptr, SUN_EINVAL, "group system is NULL");
@@ -1924,7 +1929,9 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
     bt->tile[g] = tile;
     bt->rows_per_item[g] = rows_per_item;
     bt->path[g] = path;
+    bt->usable[g] = 0;          // until the new layout is complete
     repartition(*bt, g);
+    bt->usable[g] = 1;
     refresh_items(*bt);
     upload(*bt, s);
   });
@@ -1952,6 +1959,9 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
     std::vector<int64_t> todo(bt->ngroups, 0);
     for (int g = 0; g < bt->ngroups; ++g)
       if (only_group < 0 || only_group == g) todo[g] = std::min(nsteps, bt->steps[g] - bt->done[g]);
+    for (int g = 0; g < bt->ngroups; ++g)
+      SUN_REQUIRE(todo[g] <= 0 || bt->usable[g], SUN_EINVAL,
+                  "group " + std::to_string(g) + " has an incomplete layout after a failed sun_batch_tune; tune it again");
     std::vector<int> ord(bt->ngroups);
     for (int g = 0; g < bt->ngroups; ++g) ord[g] = g;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return todo[a] > todo[b]; });

@@ -160,5 +160,8 @@ void prop_stage_multi(const sun_prop_s& p, int stage, const double* xin, const d
 // time-dependent terms, segment d with coefficient coef[row * ndyn + d]).
 void prop_seg_stage(const sun_prop_s& p, int stage, const double* xin, const double* vin, double* acc, double* xout,
                     const double* coef, int64_t row, double dt, hipStream_t s);
+// Throws SUN_ENOMEM once after sun_debug_inject_failure(1) (tests of the
+// error paths of the layout builds).
+void layout_failure_point();
 
 }  // namespace sun

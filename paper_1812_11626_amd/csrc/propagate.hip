@@ -1357,6 +1357,10 @@ void launch_stage(const sun_prop_s& p, const double* xin, double* xout, const do
 
 namespace sun {
 
+// The failure-injection point of the layout builds, for the batched form's
+// re-tiling as well.
+void layout_failure_point() { maybe_inject_layout_failure(); }
+
 void prop_require_usable(const sun_prop_s& p) {
   SUN_REQUIRE(p.usable, SUN_EINVAL,
               "propagator layout is incomplete after a failed re-layout; select a layout again (sun_prop_tune*)");

@@ -175,6 +175,46 @@ def test_pipelined_path_large_groups_bitwise(lib):
         assert rel_vec_err(out[1][g][j], v.cpu().numpy()) <= TOL, (N, j)
 
 
+def test_pipelined_path_dense_generator_long_rows(lib):
+    """Path 7 on a group where most rows have more distinct columns than a
+    block's 127 slots (random dense H0, H1 and L at N = 12, M = 143), with
+    70 instances (two tiles of 64, the second ragged): bitwise equal to
+    path 0 after 6 steps, and two instances against the dense oracle's RK4
+    on their own generators (1e-12)."""
+    flush("[batched] path 7, dense random generator (long rows)")
+    from workloads import random_ops
+    N, B, steps, dt = 12, 70, 6, 0.01
+    H0 = random_ops.random_hermitian_csr(N, 1.0, seed=901)
+    H1 = random_ops.random_hermitian_csr(N, 0.5, seed=902)
+    L = random_ops.random_complex_csr(N, 1.0, seed=903)
+    basis = lib.build_basis(N)
+    lind = lib.Lindbladian(basis, [H0, H1], [L])
+    rng = np.random.default_rng(9)
+    A = rng.uniform(0.5, 1.5, B)
+    g = rng.uniform(0.05, 0.3, B)
+    wave = np.cos(0.5 * dt * np.arange(2 * steps + 1))
+    w = np.stack([np.ones(B), np.full(B, 0.3), g], axis=1)
+    u = np.stack([np.zeros(B), A, np.zeros(B)], axis=1)
+    bp = lib.BatchedPropagator([dict(lind=lind, w=w, u=u, wave=wave, dt=dt, steps=steps)])
+    start = torch.as_tensor(np.stack([fock_bloch(N, j % N) for j in range(B)]))
+    out = []
+    for tile, rows, path in ((64, 64, 0), (64, 32, 7), (64, 8, 7)):
+        bp.tune(0, tile, rows, path)
+        bp.set_state(0, start)
+        bp.run(steps)
+        out.append(bp.get_state(0).cpu().numpy())
+    assert np.array_equal(out[1], out[0]) and np.array_equal(out[2], out[0])
+    F = ob.generators(N)
+    QH0 = lb.q_hamiltonian(F, H0.to_dense())
+    QH1 = lb.q_hamiltonian(F, H1.to_dense())
+    RL = lb.q_dissipator(F, L.to_dense())
+    KL = lb.k_dissipator(F, L.to_dense())
+    for j in (0, B - 1):
+        want = pr.rk4_bloch(QH0 + g[j] * RL, [QH1], g[j] * KL, fock_bloch(N, j % N),
+                            (0.3 + A[j] * wave)[:, None], dt, steps)
+        assert rel_vec_err(out[1][j], want) <= TOL, j
+
+
 def test_full_workload_sampled_against_plain(lib):
     """The 512-instance workload (N in {51,...,301}), 24 steps, in the
     launch configuration the benchmark times (autotuned tiles): 3 sampled

@@ -139,6 +139,38 @@ def test_failed_relayout_leaves_propagator_refusing(lib):
     lib._lib.check(L.sun_debug_inject_failure(0))
 
 
+def test_failed_batch_retiling_refuses_group(lib):
+    """An allocation failure injected in the middle of a batch group's
+    re-tiling (to path 7): the call reports it, sun_batch_run then refuses
+    to advance the group (no kernel reads its half-built layout), and tuning
+    it again restores bitwise the same results."""
+    flush("[boundary] injected batch re-tiling failure N=51")
+    from helpers import dimer_batch, fock_bloch
+    L = lib._lib.load()
+    inst = [p for p in dimer.batched_instances() if p.N == 51][:10]
+    steps = 8
+    bp, groups = dimer_batch(lib, inst, steps)
+    start = torch.as_tensor(np.stack([fock_bloch(51, 0)] * len(inst)))
+    bp.tune(0, 64, 32, 7)
+    bp.set_state(0, start)
+    bp.run(steps)
+    ref = bp.get_state(0)
+    lib._lib.check(L.sun_debug_inject_failure(1))
+    with pytest.raises(lib.SunError) as e:
+        bp.tune(0, 64, 16, 7)
+    assert _code(e) == lib._lib.SUN_ENOMEM
+    bp.set_state(0, start)
+    with pytest.raises(lib.SunError) as e:
+        bp.run(steps)
+    assert _code(e) == lib._lib.SUN_EINVAL
+    assert torch.equal(bp.get_state(0), start.cuda())
+    bp.tune(0, 64, 32, 7)
+    bp.set_state(0, start)
+    bp.run(steps)
+    assert torch.equal(bp.get_state(0), ref)
+    lib._lib.check(L.sun_debug_inject_failure(0))
+
+
 def test_adjoint_plan_execute_workspace(lib):
     """sun_adjoint_execute on a PyTorch workspace sized by sun_adjoint_plan
     equals sun_adjoint_run bitwise, with the stage inputs kept (full
