@@ -4,12 +4,14 @@
 // R = -(1/2) Re(B^T A) = -(1/2) [Re B^T | -Im B^T] [Re A ; Im A], a dense
 // contraction of M x 2M by 2M x M (Sec. II eq. 10 with dense sections).
 //
-// Tiling: a workgroup of eight wavefronts (one per CU: 208 registers per
-// lane, 104 KiB of LDS) computes a 256 x 128 tile of C, each wavefront a
-// 64 x 64 block as 4 x 4 blocks of 16 x 16 with v_mfma_f64_16x16x4f64 (a
-// 16 x 4 by 4 x 16 product per instruction, 4 accumulators per lane).  K
-// advances in panels of 16: the A panel (256 x 16) and the B panel
-// (16 x 128) are staged in LDS k-major (A transposed on the way in), each
+// Tiling: a workgroup of four wavefronts (two workgroups per CU: 214
+// registers per lane, 72 KiB of LDS each, so one workgroup's barrier and
+// panel writes overlap the other's products) computes a 128 x 128 tile of
+// C, each wavefront a 64 x 64 block as 4 x 4 blocks of 16 x 16 with
+// v_mfma_f64_16x16x4f64 (a 16 x 4 by 4 x 16 product per instruction, 4
+// accumulators per lane).  K advances in panels of 16: the A panel
+// (128 x 16) and the B panel (16 x 128) are staged in LDS k-major (A
+// transposed on the way in), each
 // row padded to 16 mod 32 doubles so that the four k-rows one fragment read
 // touches fall on disjoint banks; the LDS panels are double-buffered and the
 // next panel is fetched into registers (16-byte loads in the interior)
@@ -26,8 +28,8 @@ using namespace sun;
 
 namespace {
 
-constexpr int kBM = 256, kBN = 128, kBK = 16;
-constexpr int kWavesM = 4, kWavesN = 2;
+constexpr int kBM = 128, kBN = 128, kBK = 16;
+constexpr int kWavesM = 2, kWavesN = 2;
 constexpr int kThreads = 64 * kWavesM * kWavesN;
 constexpr int kGroupM = 8;
 constexpr int kPadA = 16, kPadB = 16;        // (kBM + kPadA) and (kBN + kPadB) are 16 mod 32
@@ -35,7 +37,7 @@ static_assert((kBM + kPadA) % 32 == 16 && (kBN + kPadB) % 32 == 16, "bank-disjoi
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kThreads) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
+__global__ __launch_bounds__(kThreads, 2) void k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha,
                                                        const double* __restrict__ A, int64_t lda,
                                                        const double* __restrict__ B, int64_t ldb, double beta,
                                                        double* __restrict__ C, int64_t ldc) {
