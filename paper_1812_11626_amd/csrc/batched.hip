@@ -934,13 +934,17 @@ typedef const __attribute__((address_space(1))) uv4 g_uv4;
 typedef const __attribute__((address_space(1))) iv4 g_iv4;
 typedef const __attribute__((address_space(1))) int g_int;
 
-// Buffer resource over `bytes` bytes at p (raw, stride 0).  A load at a
-// byte offset past the end returns zeros and touches no memory, which is how
-// the lanes of a tile past its group's last instance skip their loads
-// without a branch (so every wait count stays fixed).
+// Buffer resource over `bytes` bytes at p: raw addressing (stride 0, so
+// the range check compares the byte offset with `bytes`), and in the last
+// descriptor word the 32-bit data format that untyped dword loads use on
+// CDNA.  A load at a byte offset past the end returns zeros and touches no
+// memory, which is how the lanes of a tile past its group's last instance
+// (and unused slots) skip their loads without a branch, so every wait count
+// stays fixed.
 constexpr int kP7Off = 0x7ffffff0;   // out-of-range offset
+constexpr int kRawDwordFormat = 0x00020000;
 __device__ inline __amdgpu_buffer_rsrc_t p7_rsrc(const void* p, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRawDwordFormat);
 }
 __device__ inline double p7_load_d(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
