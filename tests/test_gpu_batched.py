@@ -249,8 +249,8 @@ def test_full_workload_sampled_against_plain(lib):
 
 def test_N51_group_full_horizon_against_plain(lib):
     """The N = 51 group of the 512-instance workload (104 instances) over its
-    full horizon of 20 periods (25,600 steps) with the two-instances-per-lane
-    LDS kernel the autotuner picks for it: the first, middle and last
+    full horizon of 20 periods (25,600 steps) on path 7, the autotuner's
+    choice for it, and on path 2 (bitwise equal): the first, middle and last
     instances against plain single-instance GPU propagation of the same
     drive, 1e-12 relative at the end."""
     flush("[batched] N=51 group, 20 periods vs plain")
@@ -259,7 +259,37 @@ def test_N51_group_full_horizon_against_plain(lib):
     assert steps == 20 * inst[0].steps_per_period
     bp, groups = dimer_batch(lib, inst, steps)
     N, idx, lind, dt, st = groups[0]
+    start = torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx)))
     bp.tune(0, 32, 32, 2)
+    bp.set_state(0, start)
+    bp.run(steps)
+    got2 = bp.get_state(0).cpu().numpy()
+    bp.tune(0, 64, 32, 7)
+    bp.set_state(0, start)
+    bp.run(steps)
+    got = bp.get_state(0).cpu().numpy()
+    assert np.array_equal(got, got2)
+    for j in (0, len(idx) // 2, len(idx) - 1):
+        p = inst[idx[j]]
+        prop = lind.propagator([1.0, 0.0, p.gamma_eff], [1])
+        v = torch.as_tensor(fock_bloch(N, 0)).cuda()
+        eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
+        prop.propagate(v, eps, dt, steps)
+        assert rel_vec_err(got[j], v.cpu().numpy()) <= TOL, j
+
+
+def test_N301_group_one_period_on_pipelined_path_against_plain(lib):
+    """The N = 301 group of the 512-instance workload (109 instances: two
+    tiles of 64, the second ragged; 186 rows on the long-row walk) over one
+    full drive period (6,400 steps) on path 7: the first, middle and last
+    instances against plain single-instance GPU propagation of the same
+    drive, 1e-12 relative at the end."""
+    flush("[batched] N=301 group, one period on path 7 vs plain")
+    inst = [p for p in dimer.batched_instances() if p.N == 301]
+    steps = inst[0].steps_per_period
+    bp, groups = dimer_batch(lib, inst, steps)
+    N, idx, lind, dt, st = groups[0]
+    bp.tune(0, 64, 32, 7)
     bp.set_state(0, torch.as_tensor(np.stack([fock_bloch(N, 0)] * len(idx))))
     bp.run(steps)
     got = bp.get_state(0).cpu().numpy()
