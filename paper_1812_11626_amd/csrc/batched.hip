@@ -843,20 +843,22 @@ __global__ __launch_bounds__(64) void k_batch_rows(const GroupDev* __restrict__ 
 // (tile of 64 instances, block of rows).  A block is a set of rows taken
 // along a walk of the (j, k) pair grid in 4 x 4 tiles (S_p and J_p
 // together, the diagonal generators last), so that its rows gather a
-// compact neighbourhood of state rows: at most kP7Slots distinct columns,
-// staged in LDS as 64-instance slices of 512 bytes, beside the block's
-// matrix data (row list, segment ends, 16-bit slot indices, values; at most
-// kP7Blob bytes) and the tile's term coefficients.  While the rows of one
-// item are summed from LDS, the loads of the next item's staged data are in
-// flight into registers -- the same number of 16-byte loads from every
-// thread for every item, at clamped addresses where a block needs fewer, so
-// that every wait the compiler places is a fixed count -- together with the
-// column list of the item after it; at the end of the item the registers
-// are written to LDS.  Each state row a block gathers is read from the
-// memory system once per block instead of once per stored entry.  Rows with
-// more distinct columns than slots are summed afterwards by one wavefront
-// each straight from global memory.  Every row adds its terms in entry
-// order exactly like the other paths, so the results are bitwise the same.
+// compact neighbourhood of state rows: at most kP7Slots - 1 distinct
+// columns, staged in LDS as 64-instance slices of 512 bytes, beside the
+// block's matrix data (row list, segment ends, 16-bit slot indices, values;
+// at most kP7Blob bytes) and the tile's term coefficients.  While the rows
+// of one item are summed from LDS, the loads of the next item's staged data
+// are in flight into registers -- the same number of 16-byte loads from
+// every thread for every item, at out-of-range buffer offsets (zeros, no
+// traffic) where a block or a tile needs fewer, so that every wait the
+// compiler places is a fixed count -- together with the column list of the
+// item after it; at the end of the item the registers are written to LDS.
+// Each state row a block gathers is read from the memory system once per
+// block instead of once per stored entry.  Rows with more distinct columns
+// than slots are summed straight from global memory, one wavefront per row
+// and tile, by a few workgroups per XCD that take no blocks.  Every row adds
+// its terms in entry order exactly like the other paths, so the results
+// are bitwise the same.
 constexpr int kP7Slots = 128;
 constexpr int kP7Rows = 32;
 constexpr int kP7Blob = 8192;
