@@ -77,7 +77,7 @@ struct GroupDev {
   int p7;                // 1: persistent pipelined staging (path 7)
   int p7_nblk;           // path 7: blocks
   const int4* p7_meta;   // path 7, per block: {blob offset and length in 16-byte units, rows, entries}
-  const int* p7_ucol;    // path 7, per block kP7Slots columns, slot s at (s % 16) * 8 + s / 16
+  const int* p7_ucol;    // path 7, per block kP7Slots columns, slot s at (s % kP7Half) * 8 + s / kP7Half
   const uint4* p7_blob;  // path 7: the blocks' matrix data
   int p7_nlong;          // path 7: rows summed straight from global memory
   const int* p7_long;
@@ -859,15 +859,16 @@ __global__ __launch_bounds__(64) void k_batch_rows(const GroupDev* __restrict__ 
 // and tile, by a few workgroups per XCD that take no blocks.  Every row adds
 // its terms in entry order exactly like the other paths, so the results
 // are bitwise the same.
-constexpr int kP7Slots = 128;
-constexpr int kP7Rows = 32;
-constexpr int kP7Blob = 8192;
-constexpr int kP7Threads = 512;
+constexpr int kP7Threads = 512;                 // 256 (four per CU, 16-row blocks): 1.23 against 1.04 ms per step
+constexpr int kP7Waves = kP7Threads / 64;
+constexpr int kP7Half = kP7Threads / 32;        // half-wavefronts: each stages one slot per load
+constexpr int kP7Slots = 8 * kP7Half;           // eight 16-byte loads per thread
+constexpr int kP7Rows = 4 * kP7Waves;           // four passes of one row per wavefront
+constexpr int kP7Blob = 16 * kP7Threads;        // one 16-byte blob load per thread
 constexpr int kP7Tile = 64;
 constexpr int kP7SegOff = 4 * kP7Rows;   // bytes: int32 rows[kP7Rows], then u16 segment ends [kP7Rows][nt]
-static_assert(kP7Slots == 16 * 8 && kP7Threads == 16 * 32, "staging map: 16 half-wavefronts x 8 loads");
-static_assert(kP7Blob == 16 * kP7Threads, "one 16-byte blob load per thread");
-static_assert(kP7Rows == 4 * (kP7Threads / 64), "four passes of one row per wavefront");
+constexpr int kP7CfPer = (kMaxBTerms + kP7Waves - 1) / kP7Waves;   // coefficients staged per thread
+static_assert(kP7CfPer == 1 || kP7CfPer == 2, "one or two coefficients per thread");
 
 // Each (row, term) segment of a block is padded to an even number of
 // entries, and each row's last segment to a multiple of kP7Round entries,
@@ -879,14 +880,14 @@ static_assert(kP7Rows == 4 * (kP7Threads / 64), "four passes of one row per wave
 constexpr int kP7Round = 8;
 static_assert(kP7Round % 2 == 0, "rounds of whole pairs");
 constexpr int kP7Zero = kP7Slots - 1;
-static_assert(kP7Zero == 7 * 16 + 15, "the zero slot is load 7 of half-wavefront 15");
+static_assert(kP7Zero == 7 * kP7Half + kP7Half - 1, "the zero slot is load 7 of the last half-wavefront");
 __host__ __device__ inline int p7_lidx_off(int nt) { return kP7SegOff + 2 * kP7Rows * nt; }
 __host__ __device__ inline int p7_val_off(int nt, int ne) { return (p7_lidx_off(nt) + 2 * ne + 15) & ~15; }
 
 // The path-7 groups of one launch, in launch order (kernel argument, so the
 // item walk runs on scalar registers only).
 constexpr int kP7MaxGroups = 16;
-constexpr int kP7LongWgs = 4;       // workgroups per XCD for the long rows, when there are any
+constexpr int kP7LongWgs = 32 / kP7Waves;   // workgroups per XCD for the long rows, when there are any
 struct P7Plan {
   int ng;
   int klong;              // workgroups per XCD given to the long rows (0: none)
@@ -972,7 +973,7 @@ __global__ __launch_bounds__(kP7Threads, 4) void k_batch_pipe(const GroupDev* __
   __shared__ uv4 s_blob[kP7Blob / 16];
   __shared__ double s_cf[kMaxBTerms * kP7Tile];     // c_a(t) of the tile's instances, [a][instance]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int hw = tid >> 5, l32 = tid & 31;          // staging: half-wavefront hw loads slots hw + 16 k
+  const int hw = tid >> 5, l32 = tid & 31;          // staging: half-wavefront hw loads slots hw + kP7Half k
   const int x = blockIdx.x & 7;
   // The last plan.klong workgroups of every XCD take the long rows; the
   // others share the blocks.
@@ -981,7 +982,7 @@ __global__ __launch_bounds__(kP7Threads, 4) void k_batch_pipe(const GroupDev* __
   const int krow = STAGE == 0 ? 0 : (STAGE == 3 ? 2 : 1);
 
   uv4 px0, px1, px2, px3, px4, px5, px6, px7, pb;   // named, so they stay in registers
-  double pw, pu;
+  double pw, pu, pw2 = 0.0, pu2 = 0.0;               // coefficient a = wv (and wv + kP7Waves)
   iv4 cu0, cu1;
   auto issue_cols = [&](const P7Loc& L) {
     g_iv4* q = (g_iv4*)(groups[L.g].p7_ucol + (int64_t)L.blk * kP7Slots + hw * 8);
@@ -1010,26 +1011,35 @@ __global__ __launch_bounds__(kP7Threads, 4) void k_batch_pipe(const GroupDev* __
     scalar_int* pm = (scalar_int*)G.p7_meta + 4 * (int64_t)L.blk;
     const int m0 = pm[0], m1 = pm[1];
     pb = ((g_uv4*)G.p7_blob)[m0 + (tid < m1 ? tid : 0)];
-    const int a = tid >> 6, b = L.tb * kP7Tile + lane;
+    const int a = wv, b = L.tb * kP7Tile + lane;
     const int idx = (a < G.nt && b < G.B) ? b * G.nt + a : 0;
     pw = ((gconst_dbl*)G.w)[idx];
     pu = ((gconst_dbl*)G.u)[idx];
+    if constexpr (kP7CfPer == 2) {
+      const int a2 = wv + kP7Waves;
+      const int idx2 = (a2 < G.nt && b < G.B) ? b * G.nt + a2 : 0;
+      pw2 = ((gconst_dbl*)G.w)[idx2];
+      pu2 = ((gconst_dbl*)G.u)[idx2];
+    }
   };
   auto write_stage = [&](const P7Loc& L) {
-    uv4* sx = s_x + hw * 32 + l32;     // slot hw + 16 k
-    sx[0 * 512] = px0;
-    sx[1 * 512] = px1;
-    sx[2 * 512] = px2;
-    sx[3 * 512] = px3;
-    sx[4 * 512] = px4;
-    sx[5 * 512] = px5;
-    sx[6 * 512] = px6;
-    sx[7 * 512] = hw == 15 ? uv4{0u, 0u, 0u, 0u} : px7;   // slot 7 * 16 + 15 = kP7Zero holds zeros
+    constexpr int SK = kP7Half * 32;   // uv4 units between slot hw + kP7Half k and the next k
+    uv4* sx = s_x + hw * 32 + l32;     // slot hw + kP7Half k
+    sx[0 * SK] = px0;
+    sx[1 * SK] = px1;
+    sx[2 * SK] = px2;
+    sx[3 * SK] = px3;
+    sx[4 * SK] = px4;
+    sx[5 * SK] = px5;
+    sx[6 * SK] = px6;
+    sx[7 * SK] = hw == kP7Half - 1 ? uv4{0u, 0u, 0u, 0u} : px7;   // slot kP7Zero holds zeros
     s_blob[tid] = pb;
     const GroupDev& G = groups[L.g];
     const double ph = G.wave[2 * step[L.g] + krow];   // uniform: a scalar load
-    const int a = tid >> 6, b = L.tb * kP7Tile + lane;
-    if (a < G.nt) s_cf[tid] = b < G.B ? pw + pu * ph : 0.0;
+    const int a = wv, b = L.tb * kP7Tile + lane;
+    if (a < G.nt) s_cf[a * kP7Tile + lane] = b < G.B ? pw + pu * ph : 0.0;
+    if constexpr (kP7CfPer == 2)
+      if (a + kP7Waves < G.nt) s_cf[(a + kP7Waves) * kP7Tile + lane] = b < G.B ? pw2 + pu2 * ph : 0.0;
   };
 
   // Rows with more distinct columns than slots: one wavefront per (row,
@@ -1144,7 +1154,7 @@ __global__ __launch_bounds__(kP7Threads, 4) void k_batch_pipe(const GroupDev* __
       double vr[4], ar[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const int row = __builtin_amdgcn_readfirstlane(s_rows[p * 8 + wv]);
+        const int row = __builtin_amdgcn_readfirstlane(s_rows[p * kP7Waves + wv]);
         const int off = opaque(own ? (row * ld + b) * 8 : kP7Off);
         vr[p] = p7_load_d(rv, off);
         ar[p] = STAGE != 0 ? p7_load_d(ra, off) : 0.0;
@@ -1155,7 +1165,7 @@ __global__ __launch_bounds__(kP7Threads, 4) void k_batch_pipe(const GroupDev* __
       issue_cols(has_nn ? nn : cur);
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const int lr = p * 8 + wv;
+        const int lr = p * kP7Waves + wv;
         if (lr < nr && own) {
           // one walk over the row in rounds of kP7Round entries across its
           // terms; term a is closed (ysum += c_a * sum) after the pair that
@@ -1281,7 +1291,7 @@ bool xlds_partition(const std::vector<int>& rp, const std::vector<int>& col, int
 // of matrix data.  A row that alone exceeds a limit goes to the long list.
 struct P7Part {
   std::vector<int> meta;        // 4 ints per block
-  std::vector<int> ucol;        // kP7Slots per block, slot s at (s % 16) * 8 + s / 16
+  std::vector<int> ucol;        // kP7Slots per block, slot s at (s % kP7Half) * 8 + s / kP7Half
   std::vector<uint4> blob;
   std::vector<int> longrows;
 };
@@ -1369,7 +1379,7 @@ void p7_partition(int N, int64_t M, int nt, const std::vector<int>& rp, const st
                     p7_val_off(nt, nent) + 8 * nent <= kP7Blob,
                 SUN_EDEVICE, "internal: path 7 block exceeds its limits");
     for (int s = 0; s < kP7Slots; ++s)   // unused slots and the zero slot: -1
-      out.ucol[bi * kP7Slots + (s % 16) * 8 + s / 16] = s < (int)u.size() ? u[s] : -1;
+      out.ucol[bi * kP7Slots + (s % kP7Half) * 8 + s / kP7Half] = s < (int)u.size() ? u[s] : -1;
     const int nbytes = p7_val_off(nt, nent) + 8 * nent;
     const int n16 = (nbytes + 15) / 16;
     bytes.assign((size_t)n16 * 16, 0);
@@ -1670,7 +1680,7 @@ struct StageLaunch {
   int64_t rgrid[3] = {0, 0, 0};  // path-5 grids (resident wavefronts, a multiple of 8), by VEC
   int r_nt = 1;                  // most terms of a path-5 group
   std::vector<P7Plan> p7;        // path-7 groups, at most kP7MaxGroups per launch
-  int64_t pgrid = 8;             // path-7 grid (two workgroups per CU, a multiple of 8)
+  int64_t pgrid = 16;            // path-7 grid (the resident workgroups, a multiple of 8)
 };
 
 // Wavefronts of k_batch_rows<*, VEC> the device keeps resident (the least
@@ -1687,6 +1697,22 @@ int64_t rows_grid(int ncu, size_t lds) {
   }
   SUN_REQUIRE(least >= 1, SUN_ENOTSUP, "path 5 kernel cannot be resident");
   return std::max<int64_t>(8, (int64_t)least * ncu / 8 * 8);
+}
+
+// Workgroups of k_batch_pipe the device keeps resident (the least over the
+// four stages, at least one per XCD and two more), rounded down to a
+// multiple of 8 XCDs.
+int64_t pipe_grid(int ncu) {
+  int least = INT32_MAX;
+  const void* ks[4] = {(const void*)k_batch_pipe<0>, (const void*)k_batch_pipe<1>, (const void*)k_batch_pipe<2>,
+                       (const void*)k_batch_pipe<3>};
+  for (const void* k : ks) {
+    int nb = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kP7Threads, 0));
+    least = std::min(least, nb);
+  }
+  SUN_REQUIRE(least >= 1, SUN_ENOTSUP, "path 7 kernel cannot be resident");
+  return std::max<int64_t>(16, (int64_t)least * ncu / 8 * 8);
 }
 
 template <int STAGE>
@@ -1902,7 +1928,8 @@ extern "C" int sun_batch_tune(sun_batch bt, int32_t g, int32_t tile, int32_t row
     SUN_REQUIRE(path >= 0 && path <= 7 && path != 6, SUN_EINVAL, "path must be 0, 1, 2, 3, 4, 5 or 7");
     if (path == 7) {
       SUN_REQUIRE(tile == kP7Tile, SUN_EINVAL, "path 7 takes tiles of 64 instances");
-      SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= kP7Rows, SUN_EINVAL, "path 7 takes 1 to 32 rows per block");
+      SUN_REQUIRE(rows_per_item >= 1 && rows_per_item <= kP7Rows, SUN_EINVAL,
+                  "path 7 takes 1 to " + std::to_string(kP7Rows) + " rows per block");
       SUN_REQUIRE((bt->M[g] + 1) * (int64_t)bt->ld[g] * 8 < (int64_t)kP7Off, SUN_ENOTSUP,
                   "path 7 needs a group state below 2 GiB (32-bit buffer offsets)");
     } else if (path == 4) {
@@ -2005,6 +2032,9 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
         p5_vec[bt->ghost[g].vec] = true;
       }
     int64_t p5_grid[3] = {0, 0, 0};
+    bool any_p7 = false;
+    for (int g = 0; g < bt->ngroups; ++g) any_p7 = any_p7 || (todo[g] > 0 && bt->ghost[g].p7);
+    const int64_t p7_grid = any_p7 ? pipe_grid(ncu) : 16;
     if (p5_vec[1]) p5_grid[1] = rows_grid<1>(ncu, (size_t)p5_nt * 64 * sizeof(double));
     if (p5_vec[2]) p5_grid[2] = rows_grid<2>(ncu, (size_t)p5_nt * 128 * sizeof(double));
     for (int64_t n = 0; n < maxn; ++n) {
@@ -2054,7 +2084,7 @@ extern "C" int sun_batch_run(sun_batch bt, int64_t nsteps, int32_t only_group, v
       L.xgrid = std::max<int64_t>(8, (std::min<int64_t>(nx, (int64_t)ncu * 3) + 7) / 8 * 8);
       L.cf_len = max_nt * kCfStride;
       L.r_nt = p5_nt;
-      L.pgrid = std::max<int64_t>(16, (int64_t)ncu * 2 / 8 * 8);
+      L.pgrid = p7_grid;
       for (P7Plan& pl : L.p7)   // at least one workgroup per XCD keeps the blocks
         pl.klong = std::min<int>(pl.klong, (int)(L.pgrid / 8) - 1);
       L.rgrid[1] = p5_grid[1];
