@@ -215,6 +215,62 @@ def test_pipelined_path_dense_generator_long_rows(lib):
         assert rel_vec_err(out[1][j], want) <= TOL, j
 
 
+def test_pipelined_path_many_terms(lib):
+    """Path 7 with six terms whose coefficients all differ between
+    instances (H_J, H_U, H1 and two dissipators, one a random banded
+    operator): the coefficient table of the tile spans more terms than half
+    the workgroup's wavefronts; 90 instances at N = 21 and 61, bitwise equal
+    to path 0 after 10 steps, and one instance per group against the dense
+    oracle (N = 21) or plain single-instance propagation (N = 61) to
+    1e-12."""
+    flush("[batched] path 7 with six instance-dependent terms")
+    from workloads import random_ops
+    rng = np.random.default_rng(21)
+    steps, dt = 10, 0.002
+    specs, meta = [], []
+    for N in (21, 61):
+        ops = dimer.dimer_operators(dimer.DimerParams(N=N))
+        L2 = random_ops.random_complex_csr(N, 3.0 / N, seed=70 + N)
+        basis = lib.build_basis(N)
+        lind = lib.Lindbladian(basis, [ops["HJ"], ops["HU"], ops["H1"], ops["H1"]], [ops["L"], L2])
+        B = 90
+        w = rng.uniform(0.5, 1.5, (B, 6)) * np.array([-1.0, 0.02, 1.0, 0.3, 0.01, 0.005])
+        u = np.zeros((B, 6))
+        u[:, 2] = rng.uniform(0.5, 3.0, B)
+        wave = np.cos(0.5 * dt * np.arange(2 * steps + 1))
+        specs.append(dict(lind=lind, w=w, u=u, wave=wave, dt=dt, steps=steps))
+        meta.append((N, ops, L2, lind, w, u, wave))
+    bp = lib.BatchedPropagator(specs)
+    starts = [torch.as_tensor(np.stack([fock_bloch(N, j % N) for j in range(90)])) for (N, *_r) in meta]
+    out = []
+    for tile, rows, path in ((64, 64, 0), (64, 32, 7)):
+        for g in range(2):
+            bp.tune(g, tile, rows, path)
+            bp.set_state(g, starts[g])
+        bp.run(steps)
+        out.append([bp.get_state(g).cpu().numpy() for g in range(2)])
+    for a, b in zip(out[1], out[0]):
+        assert np.array_equal(a, b)
+    # group 0 (N = 21): the last instance against the dense oracle
+    N, ops, L2, lind, w, u, wave = meta[0]
+    j = 89
+    F = ob.generators(N)
+    c = w[j][None, :] + u[j][None, :] * wave[:, None]          # [2 steps + 1][6]
+    QJ, QU, Q1 = (lb.q_hamiltonian(F, ops[k].to_dense()) for k in ("HJ", "HU", "H1"))
+    RL, R2 = lb.q_dissipator(F, ops["L"].to_dense()), lb.q_dissipator(F, L2.to_dense())
+    KL, K2 = lb.k_dissipator(F, ops["L"].to_dense()), lb.k_dissipator(F, L2.to_dense())
+    G0 = w[j, 0] * QJ + w[j, 1] * QU + w[j, 3] * Q1 + w[j, 4] * RL + w[j, 5] * R2
+    want = pr.rk4_bloch(G0, [Q1], w[j, 4] * KL + w[j, 5] * K2, fock_bloch(N, j % N), c[:, 2:3], dt, steps)
+    assert rel_vec_err(out[1][0][j], want) <= TOL
+    # group 1 (N = 61): the first instance against plain propagation
+    N, ops, L2, lind, w, u, wave = meta[1]
+    prop = lind.propagator([w[0, 0], w[0, 1], 0.0, w[0, 3], w[0, 4], w[0, 5]], [2])
+    v = torch.as_tensor(fock_bloch(N, 0)).cuda()
+    eps = torch.as_tensor(w[0, 2] + u[0, 2] * wave).cuda().contiguous()
+    prop.propagate(v, eps, dt, steps)
+    assert rel_vec_err(out[1][1][0], v.cpu().numpy()) <= TOL
+
+
 def test_full_workload_sampled_against_plain(lib):
     """The 512-instance workload (N in {51,...,301}), 24 steps, in the
     launch configuration the benchmark times (autotuned tiles): 3 sampled
