@@ -354,8 +354,9 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  *  0 (default otherwise: faster for small generators) CSR stream: row blocks of about block_nnz
  *    nonzeros are streamed into LDS by a workgroup of `threads` lanes, then
  *    reduced one lane per row.
- * Rows summed by one lane (all of layout 0, the short rows of layout 1) add
- * their entries in nonzero order; long rows use a wavefront tree reduction.  sun_prop_tune selects layout 0
+ * Rows summed by one lane (all of layout 0, the short rows of layout 1 with
+ * one wavefront per slice) add their entries in nonzero order; long rows use
+ * a wavefront tree reduction.  sun_prop_tune selects layout 0
  * with its knobs (block_nnz a power of two in [128, 8192], threads 64, 128 or
  * 256, xcd_remap 0/1 gives each XCD one contiguous range of blocks);
  * sun_prop_tune_sliced selects layout 1 (sigma a power of two in [64, 4096],
@@ -371,9 +372,18 @@ int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
  * the matrix stay there, otherwise); bit 2 cuts the slices from the pair-interleaved row sequence (S_p,
  * J_p adjacent: one gathered range per slice range instead of two, but wider
  * column offsets; off by default); bits 16-23 the entries a lane loads per
- * round (0 = 8, or 4, 6, 12, 16).  Other bits must be 0 (else SUN_EINVAL).  Defaults: block_nnz 1024,
+ * round (4, 6, 8, 12, 16; 0 = chosen with the next field); bits 24-26 the
+ * wavefronts that share a slice (1, 2 or 4, the latter two with 4 or 8
+ * entries per round; 0 = chosen from the number of slices and long rows: 4
+ * below 12,000, 2 below 24,000, else 1, with 4 entries per round below
+ * 1,000 and 8 above).  With 2 or 4 wavefronts per slice a row's sum is
+ * formed in that many consecutive parts (ranges of whole multiples of 4
+ * entries; a long row: interleaved groups of 64 entries) added in part
+ * order, so results differ from one wavefront per slice in rounding only and
+ * do not depend on the other fields.  Other bits must be 0 (else SUN_EINVAL).  Defaults: block_nnz 1024,
  * threads 256, xcd_remap 1; sigma 4096, long_len 32, min_col_bytes 1,
- * flags 1 (3 when the matrix stream exceeds 288 MiB per launch). */
+ * flags 1 (3 when the matrix stream exceeds 288 MiB per launch), and the
+ * wavefronts per slice and entries per round chosen as for fields of 0. */
 int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_remap,
                   void* stream);
 int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,

@@ -308,10 +308,12 @@ class Propagator:
                                       _stream()))
 
     def tune_sliced(self, sigma: int = 4096, long_len: int = 32, min_col_bytes: int = 1, xcd_remap: bool = True,
-                    nontemporal: bool = False, unroll: int = 8, pairs: bool = False):
-        """Select the sliced-ELL layout with these knobs."""
+                    nontemporal: bool = False, unroll: int = 0, pairs: bool = False, split: int = 0):
+        """Select the sliced-ELL layout with these knobs (unroll: entries a
+        lane loads per round; split: wavefronts per slice, 1, 2 or 4; 0 for
+        either = the size-based choice)."""
         flags = int(bool(xcd_remap)) | (int(bool(nontemporal)) << 1) | (int(bool(pairs)) << 2) | \
-            ((int(unroll) & 0xFF) << 16)
+            ((int(unroll) & 0xFF) << 16) | ((int(split) & 7) << 24)
         check(self._lib.sun_prop_tune_sliced(self.handle, int(sigma), int(long_len), int(min_col_bytes), flags,
                                              _stream()))
 

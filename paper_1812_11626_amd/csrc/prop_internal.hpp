@@ -28,6 +28,7 @@ struct sun_prop_s {
   int sell_pairs = 0;        // 1: slices cut from the pair-interleaved row sequence
   int resident = 0;          // sun_propagate runs every step in one single-workgroup launch
   int sell_unroll = 8;       // entries per lane per load round (4, 6, 8, 12 or 16)
+  int sell_split = 1;        // wavefronts per slice of the stage kernel (1, 2 or 4)
   int64_t nshort = 0, nlong = 0, nslices = 0, sell_nnz = 0, sell_col_bytes = 0;
   DevBuf<int> sell_row, sell_len, sell_off, sell_coff, sell_base, long_rows;
   DevBuf<unsigned char> sell_cb;

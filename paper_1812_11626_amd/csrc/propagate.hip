@@ -501,16 +501,17 @@ __device__ inline int load_delta(const unsigned char* p, int64_t e) {
   return (int)stream_load<NTL>(reinterpret_cast<const T*>(p) + e);
 }
 
-// Sum of one lane's row over a slice whose column deltas are of type T.
-// wd, cb, gbase and vp - lane are wavefront-uniform.
+// Sum of one lane's row over entries k0 .. wd - 1 of a slice whose column
+// deltas are of type T.  k0, wd, cb, gbase and vp - lane are
+// wavefront-uniform.
 template <class T, int U, bool NTL>
 __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restrict__ gbase,
-                                     const double* __restrict__ vp, int wd, int lane, int slen, int len,
+                                     const double* __restrict__ vp, int k0, int wd, int lane, int slen, int len,
                                      const double* __restrict__ xin, double& a0, double& a1) {
   // accumulate in locals with value selects (a select of the target
   // accumulator would force both into scratch memory)
   double s0 = 0.0, s1 = 0.0;
-  int k = 0;
+  int k = k0;
   for (; k + U <= wd; k += U) {
     int ci[U];
     double cv[U], xv[U];
@@ -553,8 +554,15 @@ __device__ inline void slice_row_sum(const unsigned char* cb, const int* __restr
   a1 = s1;
 }
 
-// One wavefront per slice (or per long row).  Workgroups of 4 wavefronts.
-template <int STAGE, int U, bool NTL>
+// SPLIT wavefronts per slice (or per long row), workgroups of 4 wavefronts.
+// With SPLIT = 1 each wavefront sums its slice's rows alone.  With SPLIT = 2
+// or 4 the wavefronts of a slice take consecutive ranges of whole load
+// rounds (a long row: interleaved groups of 64 entries), leave their partial
+// sums in LDS and the first of them adds them in part order and stores: a
+// shorter chain of dependent loads per wavefront and SPLIT times as many
+// wavefronts, for generators too small to fill the chip one slice per
+// wavefront.
+template <int STAGE, int U, bool NTL, int SPLIT>
 __global__ __launch_bounds__(256) void k_rk4_sell(
     const int* __restrict__ sell_off, const int* __restrict__ sell_coff, const int* __restrict__ gbase_all,
     const unsigned char* __restrict__ cb_all, const int* __restrict__ sell_row, const int* __restrict__ sell_len,
@@ -563,6 +571,7 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
     const int* __restrict__ col, const double* __restrict__ val, int ndyn,
     const double* __restrict__ xin, const double* v, double* acc, double* xout,
     const double* __restrict__ coef, int64_t coef_row, double dt, int xcd_remap) {
+  static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4, "1, 2 or 4 wavefronts per slice");
   const int lane = threadIdx.x & 63;
   // Workgroups are dispatched round-robin over the 8 XCDs; with xcd_remap
   // each XCD takes one contiguous range of slices, so the x entries its
@@ -574,38 +583,47 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
   }
   // wavefront index, made explicitly uniform so that slice metadata become
   // scalar loads and width tests scalar branches
-  const int64_t wid = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int part = wv % SPLIT;
+  const int64_t wid = blk * (4 / SPLIT) + wv / SPLIT;
   const double eps = ndyn ? coef[coef_row] : 0.0;
+  double a0 = 0.0, a1 = 0.0, vr = 0.0, ar = 0.0;
+  int r = 0;
+  bool own = false;
   if (wid < nslices) {
     const int64_t i = wid * kSlice + lane;
     const int off = __builtin_amdgcn_readfirstlane(sell_off[wid]);
     const int wd = (__builtin_amdgcn_readfirstlane(sell_off[wid + 1]) - off) / kSlice;   // slice width
     const int coff = __builtin_amdgcn_readfirstlane(sell_coff[wid]);
-    const bool own = i < nshort;
-    const int r = own ? sell_row[i] : 0;
+    own = i < nshort && part == 0;
+    r = own ? sell_row[i] : 0;
     const int lens = sell_len[i];
     const int slen = lens & 0xFFFF, len = lens >> 16;
-    double vr = 0.0, ar = 0.0;
     if (own) {
       vr = v[r];
       if (reads_acc<STAGE>()) ar = acc[r];
     }
+    int k0 = 0, k1 = wd;
+    if constexpr (SPLIT > 1) {
+      // entries per part: a multiple of 4 that does not depend on U, so the
+      // parts, and the results, are the same for every U
+      const int per = ((wd + SPLIT - 1) / SPLIT + 3) & ~3;
+      k0 = min(wd, part * per);
+      k1 = min(wd, k0 + per);
+    }
     const unsigned char* cb = cb_all + (coff & ~63);
     const int* gbase = gbase_all + off / kSlice;
     const double* vp = sval + off + lane;
-    double a0 = 0.0, a1 = 0.0;
     switch (coff & 3) {
-      case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
-      default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, wd, lane, slen, len, xin, a0, a1); break;
+      case 0: slice_row_sum<uint8_t, U, NTL>(cb, gbase, vp, k0, k1, lane, slen, len, xin, a0, a1); break;
+      case 1: slice_row_sum<uint16_t, U, NTL>(cb, gbase, vp, k0, k1, lane, slen, len, xin, a0, a1); break;
+      default: slice_row_sum<uint32_t, U, NTL>(cb, gbase, vp, k0, k1, lane, slen, len, xin, a0, a1); break;
     }
-    if (own) stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
   } else if (wid < nslices + nlong) {
-    const int r = long_rows[wid - nslices];
+    r = long_rows[wid - nslices];
     const int a = rowptr[r], z = rowptr[r + 1];
     const int sb = ndyn ? seg[r] : z;
-    double a0 = 0.0, a1 = 0.0;
-    for (int e = a + lane; e < z; e += 64) {
+    for (int e = a + part * 64 + lane; e < z; e += 64 * SPLIT) {
       const double pr = val[e] * xin[col[e]];
       a0 += e < sb ? pr : 0.0;
       a1 += e < sb ? 0.0 : pr;
@@ -614,12 +632,25 @@ __global__ __launch_bounds__(256) void k_rk4_sell(
       a0 += __shfl_down(a0, o, 64);
       a1 += __shfl_down(a1, o, 64);
     }
-    if (lane == 0) {
-      const double vr = v[r];
-      const double ar = reads_acc<STAGE>() ? acc[r] : 0.0;
-      stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
+    own = lane == 0 && part == 0;
+    if (own) {
+      vr = v[r];
+      if (reads_acc<STAGE>()) ar = acc[r];
     }
   }
+  if constexpr (SPLIT > 1) {
+    __shared__ double red[2][4][64];
+    red[0][wv][lane] = a0;
+    red[1][wv][lane] = a1;
+    __syncthreads();
+    if (own) {
+      for (int q = 1; q < SPLIT; ++q) {
+        a0 += red[0][wv + q][lane];
+        a1 += red[1][wv + q][lane];
+      }
+    }
+  }
+  if (own) stage_store<STAGE>(r, a0 + eps * a1, vr, ar, acc, xout, dt);
 }
 
 // [stage-kernel source: end]
@@ -1199,6 +1230,28 @@ void maybe_inject_layout_failure() {
     SUN_THROW(SUN_ENOMEM, "injected failure (sun_debug_inject_failure) in the middle of a layout build");
 }
 
+// Wavefronts per slice and entries per load round of the sliced stage kernel,
+// from the work units (slices + long rows) of one launch: a generator too
+// small to give every SIMD several wavefronts gets 2 or 4 per slice, each
+// with a shorter chain of dependent loads.  Measured on the dimer, us per
+// stage launch with one wavefront per slice and 8 entries per round against
+// the choice: N = 101 (241 units) 4.73 / 3.39 (4, 4); N = 201 (813) 4.74 /
+// 4.17 (4, 4); N = 301 (1,698) 5.88 / 5.35 (4, 8); N = 701 (8,352) 21.2 /
+// 19.1 (4, 8); N = 1001 (16,623) 36.1 / 34.1 (2, 8); N = 1501 (36,662) 114.4
+// against 114.5 for (2, 8), so one wavefront per slice from 24,000 units on.
+// A given entries-per-round count other than 4 or 8 keeps one wavefront.
+void pick_split(sun_prop_s& p, int unroll) {
+  const int64_t units = p.nslices + p.nlong;
+  int split = units < 12000 ? 4 : (units < 24000 ? 2 : 1);
+  int u = units < 1000 ? 4 : 8;
+  if (unroll) {
+    u = unroll;
+    if (u != 4 && u != 8) split = 1;
+  }
+  p.sell_split = split;
+  p.sell_unroll = u;
+}
+
 void build_sell(sun_prop_s& p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));   // earlier launches may still read the old layout
   const int64_t M = p.M;
@@ -1316,20 +1369,28 @@ void launch_stage_v(const sun_prop_s& p, const double* xin, const double* vin, d
     return;
   }
   if (p.layout == 1) {
-    const int64_t waves = p.nslices + p.nlong;
+    const int64_t waves = (p.nslices + p.nlong) * p.sell_split;
     unsigned grid = (unsigned)((waves + 3) / 4);
     if (p.sell_remap) grid = (grid + 7) / 8 * 8;
-    auto kern = k_rk4_sell<STAGE, 8, false>;
-    switch (p.sell_unroll * 2 + p.sell_nt) {
-      case 8: kern = k_rk4_sell<STAGE, 4, false>; break;
-      case 9: kern = k_rk4_sell<STAGE, 4, true>; break;
-      case 12: kern = k_rk4_sell<STAGE, 6, false>; break;
-      case 13: kern = k_rk4_sell<STAGE, 6, true>; break;
-      case 17: kern = k_rk4_sell<STAGE, 8, true>; break;
-      case 24: kern = k_rk4_sell<STAGE, 12, false>; break;
-      case 25: kern = k_rk4_sell<STAGE, 12, true>; break;
-      case 32: kern = k_rk4_sell<STAGE, 16, false>; break;
-      case 33: kern = k_rk4_sell<STAGE, 16, true>; break;
+    auto kern = k_rk4_sell<STAGE, 8, false, 1>;
+    switch (p.sell_split * 64 + p.sell_unroll * 2 + p.sell_nt) {
+      case 64 + 8: kern = k_rk4_sell<STAGE, 4, false, 1>; break;
+      case 64 + 9: kern = k_rk4_sell<STAGE, 4, true, 1>; break;
+      case 64 + 12: kern = k_rk4_sell<STAGE, 6, false, 1>; break;
+      case 64 + 13: kern = k_rk4_sell<STAGE, 6, true, 1>; break;
+      case 64 + 17: kern = k_rk4_sell<STAGE, 8, true, 1>; break;
+      case 64 + 24: kern = k_rk4_sell<STAGE, 12, false, 1>; break;
+      case 64 + 25: kern = k_rk4_sell<STAGE, 12, true, 1>; break;
+      case 64 + 32: kern = k_rk4_sell<STAGE, 16, false, 1>; break;
+      case 64 + 33: kern = k_rk4_sell<STAGE, 16, true, 1>; break;
+      case 128 + 8: kern = k_rk4_sell<STAGE, 4, false, 2>; break;
+      case 128 + 9: kern = k_rk4_sell<STAGE, 4, true, 2>; break;
+      case 128 + 16: kern = k_rk4_sell<STAGE, 8, false, 2>; break;
+      case 128 + 17: kern = k_rk4_sell<STAGE, 8, true, 2>; break;
+      case 256 + 8: kern = k_rk4_sell<STAGE, 4, false, 4>; break;
+      case 256 + 9: kern = k_rk4_sell<STAGE, 4, true, 4>; break;
+      case 256 + 16: kern = k_rk4_sell<STAGE, 8, false, 4>; break;
+      case 256 + 17: kern = k_rk4_sell<STAGE, 8, true, 4>; break;
       default: break;
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, p.sell_off.get(), p.sell_coff.get(),
@@ -1630,6 +1691,7 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
       if (p->layout == 1) {
         build_sell(*p, s);
         p->sell_nt = sell_matrix_bytes(*p) > kNontemporalMinBytes ? 1 : 0;
+        pick_split(*p, 0);
       }
       if (p->layout == 2) {
         // 2-3 time-dependent terms: one segment each in the sliced layout
@@ -1699,17 +1761,27 @@ extern "C" int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len,
     const int u = (flags >> 16) & 0xFF;
     SUN_REQUIRE(u == 0 || u == 4 || u == 6 || u == 8 || u == 12 || u == 16, SUN_EINVAL,
                 "entries per load round (flags bits 16-23) must be 0, 4, 6, 8, 12 or 16");
-    SUN_REQUIRE((flags & ~0xFF0007) == 0, SUN_EINVAL, "unknown flag bits");
+    const int split = (flags >> 24) & 7;
+    SUN_REQUIRE(split == 0 || split == 1 || split == 2 || split == 4, SUN_EINVAL,
+                "wavefronts per slice (flags bits 24-26) must be 0, 1, 2 or 4");
+    SUN_REQUIRE(split <= 1 || u == 0 || u == 4 || u == 8, SUN_EINVAL,
+                "2 or 4 wavefronts per slice take 4 or 8 entries per load round");
+    SUN_REQUIRE((flags & ~0x7FF0007) == 0, SUN_EINVAL, "unknown flag bits");
     p->sell_remap = (flags & 1) ? 1 : 0;
     p->sell_pairs = (flags & 4) ? 1 : 0;
     p->sell_nt = (flags & 2) ? 1 : 0;
-    p->sell_unroll = u ? u : 8;
     p->usable = 0;
     ++p->layout_gen;
     p->resident = 0;
     p->layout = p->ndyn <= 1 ? 1 : 2;
     p->sell_segs = p->ndyn <= 1 ? 0 : p->ndyn;
     build_sell(*p, as_stream(stream));
+    if (split == 0) {
+      pick_split(*p, u);
+    } else {
+      p->sell_split = split;
+      p->sell_unroll = u ? u : 8;
+    }
     p->usable = 1;
   });
 }

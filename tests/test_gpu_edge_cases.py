@@ -176,6 +176,10 @@ def test_propagate_argument_checks(lib):
     with pytest.raises(lib.SunError):
         prop.tune_sliced(unroll=5)                                              # unsupported unroll
     with pytest.raises(lib.SunError):
+        prop.tune_sliced(split=3)                                               # 1, 2 or 4 wavefronts per slice
+    with pytest.raises(lib.SunError):
+        prop.tune_sliced(split=2, unroll=12)                                    # split slices take 4 or 8 per round
+    with pytest.raises(lib.SunError):
         lind.propagator([1.0, 0.0, 0.1], [0, 1, 2, 0, 1])                       # > 4 dynamic terms
 
 

@@ -212,29 +212,41 @@ def test_sliced_layout_matches_stream_layout(lib):
     assert torch.equal(a, b)
 
 
-def test_sliced_kernel_variants_are_bitwise_identical(lib):
-    """XCD remapping, load hints, entries per load round and the row sequence
-    the slices are cut from change only which wavefront handles a row and how
-    its loads are issued, never the order of a row's sum: results are bitwise
-    equal."""
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_sliced_kernel_variants_are_bitwise_identical(lib, split):
+    """XCD remapping, load hints, entries per load round and (with one
+    wavefront per slice) the row sequence the slices are cut from change only
+    which wavefront handles a row and how its loads are issued, never the
+    order of a row's sum: results are bitwise equal for a given number of
+    wavefronts per slice.  2 or 4 wavefronts per slice sum each row in parts
+    and agree with one to rounding."""
     N = 101
-    flush(f"[propagate] sliced variants N={N}")
+    flush(f"[propagate] sliced variants N={N} split={split}")
     p = dimer.plain_config(N)
     ops = dimer.dimer_operators(p)
     _, _, prop = _gpu_system(lib, p, ops)
     steps = 40
     eps = torch.as_tensor(dimer.drive_table(p, steps=steps)).cuda().contiguous()
     v0 = torch.as_tensor(_fock_v0(N)).cuda()
-    prop.tune_sliced()
+    prop.tune_sliced(split=split)
     ref = v0.clone()
     prop.propagate(ref, eps, p.dt, steps)
-    for kw in (dict(xcd_remap=False), dict(nontemporal=True), dict(unroll=4), dict(unroll=12),
-               dict(unroll=16, nontemporal=True), dict(unroll=4, xcd_remap=False), dict(pairs=True),
-               dict(pairs=True, xcd_remap=False, unroll=6)):
-        prop.tune_sliced(**kw)
+    if split == 1:
+        variants = (dict(xcd_remap=False), dict(nontemporal=True), dict(unroll=4), dict(unroll=12),
+                    dict(unroll=16, nontemporal=True), dict(unroll=4, xcd_remap=False), dict(pairs=True),
+                    dict(pairs=True, xcd_remap=False, unroll=6))
+    else:
+        variants = (dict(xcd_remap=False), dict(nontemporal=True), dict(unroll=4), dict(unroll=8),
+                    dict(unroll=4, xcd_remap=False, nontemporal=True))
+    for kw in variants:
+        prop.tune_sliced(split=split, **kw)
         v = v0.clone()
         prop.propagate(v, eps, p.dt, steps)
         assert torch.equal(v, ref), kw
+    prop.tune_sliced(split=1)
+    one = v0.clone()
+    prop.propagate(one, eps, p.dt, steps)
+    assert rel_vec_err(ref.cpu().numpy(), one.cpu().numpy()) <= 1e-14
 
 
 
@@ -368,7 +380,7 @@ def test_resident_path_matches_sliced_kernel(lib):
     a = v0.clone()
     prop.propagate(a, eps, p.dt, steps)              # one launch for all steps
     ra, _ = prop.record(v0.clone(), eps, p.dt, steps, 60)
-    prop.tune_sliced(long_len=64)                    # four launches per step, every row on a lane
+    prop.tune_sliced(long_len=64, split=1)           # four launches per step, every row on a lane
     b = v0.clone()
     prop.propagate(b, eps, p.dt, steps)
     rb, _ = prop.record(v0.clone(), eps, p.dt, steps, 60)
