@@ -346,12 +346,12 @@ int sun_debug_inject_failure(int32_t site);
  * (row blocks, or slices + long rows), rows M. */
 int sun_prop_info(sun_prop p, int64_t* nnz_fused, int64_t* nblocks, int64_t* M);
 /* Two device layouts exist for the stage kernel:
- *  1 (default when ndyn <= 1 and the fused generator has more than 100,000
- *    stored nonzeros) sliced ELL: rows of at most long_len nonzeros
+ *  1 (default when ndyn <= 1) sliced ELL: rows of at most long_len nonzeros
  *    are sorted by length inside windows of sigma rows and packed 64 per
  *    slice, one wavefront lane per row; longer rows are reduced by one
  *    wavefront each.
- *  0 (default otherwise: faster for small generators) CSR stream: row blocks of about block_nnz
+ *  0 (default for 2-3 time-dependent terms up to 100,000 fused nonzeros,
+ *    and for 4) CSR stream: row blocks of about block_nnz
  *    nonzeros are streamed into LDS by a workgroup of `threads` lanes, then
  *    reduced one lane per row.
  * Rows summed by one lane (all of layout 0, the short rows of layout 1 with

@@ -1682,12 +1682,15 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
                          p->rowptr.get());
       HIP_LAUNCH_OK();
       build_partition(*p, s);
-      // sliced ELL for large generators; the CSR stream layout for small ones,
-      // where its one load round per block beats the sliced kernel's per-lane
-      // chains (measured on the dimer: 5.3 against 7.4 us per stage at
-      // 45,773 nonzeros, 6.0 against 6.6 at 93,000; from ~190,000 on the
-      // sliced kernel is ahead)
-      p->layout = p->nnz > kStreamMaxNnz ? (ndyn <= 1 ? 1 : (ndyn <= kMaxRevSeg ? 2 : 0)) : 0;
+      // sliced ELL at every size for one time-dependent term: with several
+      // wavefronts per slice it is ahead of the CSR stream layout even for
+      // small generators (measured on the dimer, us per stage: N = 19, 6,163
+      // stored entries, 3.0 against 4.1; N = 51, 48,323, 3.3 against 5.2;
+      // N = 71, 94,953, 3.3 against 5.9).  With 2-3 time-dependent terms the
+      // segmented sliced layout above 100,000 nonzeros and the stream layout
+      // below (5.3 against 7.4 us per stage at 45,773 nonzeros with one
+      // wavefront per slice).
+      p->layout = ndyn <= 1 ? 1 : (p->nnz > kStreamMaxNnz && ndyn <= kMaxRevSeg ? 2 : 0);
       if (p->layout == 1) {
         build_sell(*p, s);
         p->sell_nt = sell_matrix_bytes(*p) > kNontemporalMinBytes ? 1 : 0;
