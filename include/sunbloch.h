@@ -388,7 +388,7 @@ int sun_prop_tune(sun_prop p, int32_t block_nnz, int32_t threads, int32_t xcd_re
                   void* stream);
 int sun_prop_tune_sliced(sun_prop p, int32_t sigma, int32_t long_len, int32_t min_col_bytes,
                          int32_t flags, void* stream);
-/* Resident path (on by default for small generators -- at most 6000 fused
+/* Resident path (on by default for small generators -- at most 2500 fused
  * nonzeros, 4(M+1) doubles within one workgroup's LDS, at most one
  * time-dependent term -- and selectable up to the LDS limit): sun_propagate and
  * sun_propagate_record keep v, the stage vectors and the accumulator in the

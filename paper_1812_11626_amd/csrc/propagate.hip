@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_sell_multi(
 // at most 64 entries then give the same bits as the sliced kernel).
 // ---------------------------------------------------------------------------
 constexpr int kResidentThreads = 1024;
-constexpr int64_t kResidentMaxNnz = 6000;   // default use of the resident path
+constexpr int64_t kResidentMaxNnz = 2500;   // default use of the resident path
 
 __device__ inline void resident_row(const int* __restrict__ rowptr, const int* __restrict__ col,
                                     const double* __restrict__ val, int sb, int r, const double* xin, double& s0,
@@ -1703,8 +1703,10 @@ extern "C" int sun_prop_create(sun_lind l, const double* static_w, const int32_t
         build_sell(*p, s);
       }
       // one workgroup wins while the whole generator is small (measured on
-      // the dimer: 2.9x faster at 140 nonzeros, 1.1x at 4,200, slower from
-      // ~9,000 on, where four wide launches per step hide latency better)
+      // the dimer against the sliced kernel with four wavefronts per slice,
+      // us per RK4 step: 5.6 against 8.0 at 140 nonzeros, 9.7 against 11.8
+      // at 2,224; slower from 3,135 on, 13.8 against 11.4, and 18.9 against
+      // 11.5 at 5,425)
       p->resident = (ndyn <= 1 && p->nnz <= kResidentMaxNnz && resident_lds_bytes(M) <= lds_limit()) ? 1 : 0;
       p->bad.alloc(1);
       set_int(p->bad.get(), 0, s);

@@ -36,7 +36,7 @@ def _code(exc):
 
 @pytest.mark.parametrize("N", [4, 51, 101])
 def test_nan_state_is_reported(lib, N):
-    """NaN in v0 (resident path at N = 4, CSR stream at 51, sliced at 101):
+    """NaN in v0 (resident path at N = 4, sliced at 51 and 101):
     SUN_EDIVERGED, from sun_propagate and from sun_propagate_record."""
     flush(f"[boundary] NaN state N={N}")
     p, basis, lind, prop, v0 = _plain(lib, N)
